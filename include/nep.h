@@ -1,0 +1,239 @@
+/*
+ * nep.h -- C ABI of the MI355X (gfx950) contour-integral eigensolver.
+ *
+ * The library computes the eigenvalues of a holomorphic matrix function T(z)
+ * (T(lambda) x = 0, eq (1.1) of Xi & Sun, "Parallel multi-step contour integral
+ * methods for nonlinear eigenvalue problems") that lie in a rectangle Omega,
+ * following pmCIMb (Section 3.2):
+ *
+ *   Step 1   cover Omega with equal cells, replace each cell by its circumscribed
+ *            disk (Section 3), and at the N trapezoidal nodes of every circle solve
+ *            T(z_j) X_j = [F | V] (eq (2.4)); form the N- and N/2-point rules of P f
+ *            (eq (2.3)) and the ratio indicator (eq (3.1)); flag disks with
+ *            I > tol_ind                                       -> nep_indicator
+ *   Step 2   Beyn's extraction on flagged disks from the moments C0, C1
+ *            (eqs (2.6)-(2.8), (3.2)-(3.3)) and the keep-inside-the-cell filter
+ *            (Step 2.f)                                         -> nep_beyn
+ *   Step 3   verification of each candidate by sigma_min(T(lambda)) < tol_ver
+ *            (Step 3, with the smallest singular value in place of the smallest
+ *            eigenvalue)                                        -> nep_verify
+ *
+ * Conventions for every entry point
+ *   - Complex numbers are interleaved (re, im) pairs of IEEE doubles, the layout of
+ *     C99 double _Complex, std::complex<double> and torch.complex128.
+ *   - Matrices are dense and row-major: element (i, j) of an n x m block sits at
+ *     offset i*m + j.
+ *   - "_dev" pointers are device (HBM) addresses on the current HIP device;
+ *     every other pointer is host memory.  Device pointers are borrowed: the caller
+ *     keeps them valid for the lifetime stated on each call.  The library allocates
+ *     its own device workspace in nep_plan and frees it in nep_destroy.
+ *   - No exceptions cross the ABI.  Every call returns a nep_status; on a negative
+ *     status, nep_last_error() holds a human-readable message.  Warnings
+ *     (positive statuses) mean the outputs are complete but some node or disk was
+ *     handled conservatively (see each status).
+ *   - A plan is not thread-safe.  All work of a plan runs, in order, on the HIP
+ *     stream given at nep_plan; calls return after that stream has produced the
+ *     host outputs.  Use one plan per stream.
+ */
+#ifndef NEP_H
+#define NEP_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum nep_status {
+  NEP_OK = 0,
+  NEP_WARN_SINGULAR_NODE = 1,   /* a node matrix had an exactly zero pivot or a non-finite
+                                   solution; its disk was flagged conservatively           */
+  NEP_WARN_REFINE_FALLBACK = 2, /* mixed precision: some node did not converge within
+                                   max_refine sweeps and was re-solved in complex128       */
+  NEP_WARN_SATURATED = 3,       /* Beyn: some disk kept p = L singular values (the rank test
+                                   may have been cut by the probe count)                   */
+  NEP_ERR_ARG = -1,             /* invalid argument (null pointer, size, option)           */
+  NEP_ERR_NOMEM = -2,           /* device or host allocation failed                        */
+  NEP_ERR_HIP = -3,             /* a HIP runtime call failed                               */
+  NEP_ERR_NONFINITE = -4,       /* non-finite data where the method cannot proceed         */
+  NEP_ERR_CAPACITY = -5,        /* an output or workspace capacity would be exceeded       */
+  NEP_ERR_STATE = -6            /* call order violated (e.g. nep_beyn before a sweep)      */
+} nep_status;
+
+/* Scalar functions phi_k of the split form T(z) = sum_k phi_k(z) A_k. */
+enum {
+  NEP_PHI_ONE = 0,            /* 1                                  */
+  NEP_PHI_Z = 1,              /* z                                  */
+  NEP_PHI_Z2 = 2,             /* z^2                                */
+  NEP_PHI_NEG_Z = 3,          /* -z                                 */
+  NEP_PHI_EXP_NEG_TAU_Z = 4   /* exp(-tau z), tau = phi_param[k]    */
+};
+
+/* Arithmetic of the node LU factorisations. */
+enum {
+  NEP_FP64 = 0,        /* complex128 LU with partial pivoting                          */
+  NEP_FP32_REFINE = 1  /* complex64 LU, then complex128 residual iterative refinement    */
+};
+
+/* The nonlinear eigenvalue problem T(lambda) x = 0 (eq (1.1)) in split form
+ * T(z) = sum_{k < nterms} phi_{phi_kind[k]}(z) A_k, the structure of the paper's
+ * appendix routine that generates T(z) (a quadratic T0 + z T1 + z^2 T2).
+ *   n          matrix order, 1 <= n <= 4096
+ *   A_dev[k]   device pointer to A_k, complex128 row-major n x n; NULL means A_k = I
+ *              (never materialised).  Borrowed until nep_destroy.
+ *   phi_kind   host array of nterms NEP_PHI_* codes (copied at nep_plan)
+ *   phi_param  host array of nterms parameters (tau), or NULL (copied)        */
+typedef struct nep_problem {
+  int n;
+  int nterms;
+  const void* const* A_dev;
+  const int* phi_kind;
+  const double* phi_param;
+} nep_problem;
+
+/* Omega = [x0, x1] x [y0, y1] split into nx x ny equal cells (Section 3).  Cell
+ * (ix, iy) has centre (x0 + (2 ix + 1) hx, y0 + (2 iy + 1) hy), half-widths
+ * hx = (x1 - x0) / (2 nx), hy = (y1 - y0) / (2 ny), and its disk has radius
+ * sqrt(hx^2 + hy^2).  Disks are numbered ix * ny + iy within a problem, and
+ * problems follow each other in the plan's global disk numbering.            */
+typedef struct nep_region {
+  double x0, x1, y0, y1;
+  int nx, ny;
+} nep_region;
+
+/* Method parameters.
+ *   N          trapezoidal nodes per circle (even, 4 <= N <= 256), eq (2.3)
+ *   s          probe columns of F for the indicator (1 <= s <= 8)
+ *   L          probe columns of V for Beyn's moments (0 <= L <= 32; 0 = no moments)
+ *   tol_ind    flag a disk iff its indicator I > tol_ind (Step 1.c)
+ *   tol_svd    keep singular values sigma > tol_svd (Step 2.d)
+ *   tol_ver    accept lambda iff sigma_min(T(lambda)) < tol_ver (Step 3)
+ *   precision  NEP_FP64 or NEP_FP32_REFINE
+ *   max_refine maximum refinement sweeps for NEP_FP32_REFINE (0..8)
+ *   batch      node matrices factored together (0 = chosen by the library)  */
+typedef struct nep_options {
+  int N;
+  int s;
+  int L;
+  double tol_ind;
+  double tol_svd;
+  double tol_ver;
+  int precision;
+  int max_refine;
+  int batch;
+} nep_options;
+
+/* Counters and phase timings of the last call on a plan (device time measured with
+ * HIP events on the plan's stream, milliseconds).                              */
+typedef struct nep_stats {
+  int64_t node_solves;       /* (problem, disk, node) units of the last sweep        */
+  int64_t lu_count;          /* LU factorisations in the last sweep / verify          */
+  double lu_flops;           /* sum of 8 n^3 / 3 over those LUs (real flops)          */
+  int64_t refine_sweeps;     /* residual sweeps run (mixed precision)                 */
+  int64_t refine_fallbacks;  /* nodes re-solved in complex128                         */
+  int64_t singular_nodes;    /* nodes with a zero pivot or non-finite solution        */
+  double ms_total;           /* the whole last call                                   */
+  double ms_assemble;        /* T(z_j) assembly                                       */
+  double ms_lu;              /* LU factorisations (panel + row exchange + update)      */
+  double ms_solve;           /* triangular solves                                     */
+  double ms_refine;          /* residuals + correction solves                         */
+  double ms_sums;            /* quadrature sums, profiles, indicators                 */
+  double ms_gemm;            /* the trailing-update kernel alone                      */
+  int64_t gemm_launches;     /* its launch count                                      */
+  double gemm_flops;         /* its algorithmic flops over those launches             */
+} nep_stats;
+
+typedef struct nep_plan nep_plan_t;
+
+/* nep_plan -- validate the inputs, build the cover, nodes z_j = c + r e^{i theta_j}
+ * (theta_j = 2 pi (j-1)/N, j = 1..N) and weights w_j = (r/N) e^{i theta_j} of every
+ * disk (eq (2.3), Section 3), choose the batching and allocate the device workspace.
+ *   probs, nprob  the problems (nprob >= 1); coefficient buffers are borrowed and
+ *                 must stay valid and unchanged until nep_destroy
+ *   regs          one region per problem
+ *   opt           method parameters (copied)
+ *   stream        the HIP stream all work of this plan runs on (0 = null stream)
+ *   out           receives the plan; set to NULL on failure
+ * Errors: NEP_ERR_ARG (bad sizes/options), NEP_ERR_NOMEM, NEP_ERR_HIP.            */
+nep_status nep_plan(const nep_problem* probs, int nprob, const nep_region* regs,
+                    const nep_options* opt, hipStream_t stream, nep_plan_t** out);
+
+/* nep_indicator -- Step 1 over every disk of every problem, plus the Beyn moments
+ * of Step 2.b when V is given (the same nodes serve both, so the moments come from
+ * the same factorisations: eqs (3.2)-(3.3) with the garbled factor of eq (3.3) read
+ * as the node z_j).
+ *   F_dev[p]   device, complex128 n_p x s, the indicator probes (unit columns)
+ *   V_dev      NULL, or V_dev[p] = device complex128 n_p x L (Beyn probes)
+ *   ind        host double [total_disks * s]: I_q of eq (3.1) per probe column, read
+ *              as || P f|_N ./ P f|_{N/2} ||_2 / sqrt(n) (elementwise ratio); a
+ *              non-finite ratio is reported as +inf
+ *   flags      host uint8 [total_disks]: 1 iff max_q I_q > tol_ind (or non-finite)
+ *   profiles   host double [total_disks * N * s] or NULL: ||x_j[:, q]||_2 per node
+ * The half rule uses the 1-based even nodes x_2, x_4, ..., x_N with weights 2 w_j.
+ * Returns NEP_OK, NEP_WARN_SINGULAR_NODE or NEP_WARN_REFINE_FALLBACK, or an error. */
+nep_status nep_indicator(nep_plan_t* plan, const void* const* F_dev, const void* const* V_dev,
+                         double* ind, uint8_t* flags, double* profiles);
+
+/* nep_beyn -- Step 2.c-2.f on the listed disks: thin SVD C0 = U S W^H, p =
+ * #{sigma > tol_svd}, D = U_0^H C1 W_0 S_0^{-1} (eq (2.8)), eig(D), and the
+ * ownership filter of Step 2.f.
+ *   disk_ids, ndisks   global disk indices (host)
+ *   V_dev      NULL: reuse the moments of the last nep_indicator (which must have had
+ *              V); otherwise per-problem device V blocks (n_p x L), and the listed disks
+ *              are swept again with them
+ *   eig        host complex128 [ndisks * L]: eigenvalues of D, first p[i] valid
+ *   p          host int32 [ndisks]
+ *   sv         host double [ndisks * L]: singular values of C0, descending
+ *   keep       host uint8 [ndisks * L] or NULL: 1 iff eigenvalue k of disk i lies in the
+ *              cell that owns it (strict inside test; a value within 1e-9 max(1,|l|) of
+ *              an edge shared by two cells belongs to the neighbour with the smaller
+ *              index, a value on the outer boundary of Omega to its only cell)
+ *   eigvec_dev NULL or device complex128 [ndisks * n * L]: eigenvectors U_0 s_k (unit
+ *              2-norm, column k of the n x L block of disk i; problems of one call must
+ *              then share n)
+ * Returns NEP_OK, NEP_WARN_SATURATED (some p == L), or an error.                  */
+nep_status nep_beyn(nep_plan_t* plan, const int32_t* disk_ids, int ndisks,
+                    const void* const* V_dev, void* eig, int32_t* p, double* sv,
+                    uint8_t* keep, void* eigvec_dev);
+
+/* nep_verify -- Step 3: sigma_min(T(lambda_i)) in complex128 for m candidates, from an
+ * LU of T(lambda_i) and inverse iteration on T^H T (the estimate never undershoots
+ * sigma_min); accepted[i] = sigma_min < tol_ver.
+ *   prob_ids   host int32 [m]: problem of each candidate
+ *   lam        host complex128 [m]
+ *   sigma_min  host double [m]
+ *   accepted   host uint8 [m]
+ * Errors: NEP_ERR_ARG.                                                            */
+nep_status nep_verify(nep_plan_t* plan, const int32_t* prob_ids, const void* lam, int m,
+                      double* sigma_min, uint8_t* accepted);
+
+/* nep_copy_sums -- copy the quadrature sums of disks [first, first + count) of the last
+ * sweep to host buffers (any may be NULL): PfN, PfN2 as n x s, C0, C1 as n x L per disk,
+ * complex128 row-major, disks back to back.  All listed disks must share n.        */
+nep_status nep_copy_sums(nep_plan_t* plan, int first, int count, void* PfN, void* PfN2,
+                         void* C0, void* C1);
+
+/* nep_dedup -- merge candidates closer than rel * max(1, |lambda|): of a close pair the
+ * one with the smaller sigma keeps its slot (the final list of Step 3 after values found
+ * from two neighbouring disks).  Host only; keep[i] = 1 for survivors.             */
+nep_status nep_dedup(const void* lam, const double* sigma, int m, double rel, uint8_t* keep);
+
+/* Sizes of a plan: total disks, and the first global disk of problem p.             */
+int nep_total_disks(const nep_plan_t* plan);
+int nep_disk_offset(const nep_plan_t* plan, int problem);
+
+/* Counters and timings of the last call.                                            */
+nep_status nep_get_stats(const nep_plan_t* plan, nep_stats* out);
+
+/* Release the plan and its device workspace (NULL is ignored).                      */
+void nep_destroy(nep_plan_t* plan);
+
+/* Messages.                                                                         */
+const char* nep_status_str(int status);
+const char* nep_last_error(const nep_plan_t* plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NEP_H */

@@ -1,0 +1,470 @@
+// Beyn's extraction on flagged disks (Step 2.c-2.f, eq (2.8)), complex128, one
+// workgroup per disk:
+//   1. Householder QR of C0 (n x L): C0 = Q R; the same reflectors give Q^H C1.
+//   2. One-sided (Hestenes) Jacobi SVD of the L x L factor R: R W = U_r S, so
+//      C0 = (Q U_r) S W^H.  Singular values sorted descending.
+//   3. p = #{sigma > tol_svd};  D = U_r0^H (Q^H C1) W_0 S_0^{-1}  (p x p).
+//   4. eig(D): Hessenberg reduction and single-shift complex QR iterations with
+//      Wilkinson shifts and deflation; Schur vectors kept for eigenvectors.
+//   5. Eigenvectors U_0 s_k = Q U_r0 s_k (optional), unit norm, phase fixed so the
+//      entry of largest modulus is real positive.
+//   6. Ownership filter of Step 2.f.
+#include "common.h"
+#include "beyn.h"
+
+namespace nep {
+
+constexpr int LMAX = 32;
+constexpr int BT = 256;
+
+NEP_DEV double cabsd(double2 a) { return hypot(a.x, a.y); }
+
+// owner cell along one axis (see the header for the tie rule); -1 = outside
+NEP_DEV int owner_axis(double v, double lo, double hi, int cells, double band) {
+  if (v < lo - band || v > hi + band) return -1;
+  const double h = (hi - lo) / cells;
+  const double t = (v - lo) / h;
+  const double k = rint(t);
+  int idx;
+  if (fabs(v - (lo + k * h)) <= band) idx = (int)k - 1;
+  else idx = (int)floor(t);
+  if (idx < 0) idx = 0;
+  if (idx > cells - 1) idx = cells - 1;
+  return idx;
+}
+
+// block-wide sum of up to 2*LMAX complex partials held per thread (acc[0..cnt))
+NEP_DEV void block_reduce_c(double2* acc, int cnt, double2 (*red)[2 * LMAX], double2* out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int c = 0; c < cnt; ++c) {
+    double x = wave_sum(acc[c].x), y = wave_sum(acc[c].y);
+    if (lane == 0) red[wave][c] = cmk<double>(x, y);
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < cnt; c += BT)
+    out[c] = cadd<double>(cadd<double>(red[0][c], red[1][c]), cadd<double>(red[2][c], red[3][c]));
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(BT) void beyn_kernel(BeynArgs a) {
+  const int di = blockIdx.x;
+  const int d = a.disk_ids[di];
+  const int n = a.dn[d];
+  const int L = a.L;
+  const int t = threadIdx.x;
+  const double2* C0 = a.C0 + a.soff[d] * L;
+  const double2* C1 = a.C1 + a.soff[d] * L;
+  double2* Q = a.scratch + (long long)di * 2 * a.nmax * L;   // n x L, reflectors
+  double2* G = Q + (long long)a.nmax * L;                   // n x L, reflected C1
+
+  __shared__ double2 red[4][2 * LMAX];
+  __shared__ double2 dots[2 * LMAX];
+  __shared__ double2 Rm[LMAX][LMAX + 1];   // R, then the Jacobi-rotated R
+  __shared__ double2 Ct[LMAX][LMAX + 1];   // (Q^H C1)[0:L, :]
+  __shared__ double2 Wm[LMAX][LMAX + 1];   // right singular vectors
+  __shared__ double2 Hm[LMAX][LMAX + 1];   // D, then its Schur form
+  __shared__ double2 Zm[LMAX][LMAX + 1];   // Schur vectors
+  __shared__ double2 Ym[LMAX][LMAX + 1];   // eigenvectors of D
+  __shared__ double sv[LMAX];
+  __shared__ int ordr[LMAX];
+  __shared__ double2 s_gamma;
+  __shared__ double s_unorm;
+  __shared__ int s_conv;
+
+  for (long long e = t; e < (long long)n * L; e += BT) { Q[e] = C0[e]; G[e] = C1[e]; }
+  __syncthreads();
+
+  // ---------------------------------------------------------------- Householder QR
+  for (int k = 0; k < L; ++k) {
+    double2 part[1] = {cmk<double>(0, 0)};
+    for (int i = k + t; i < n; i += BT) part[0].x += cabs2<double>(Q[(long long)i * L + k]);
+    block_reduce_c(part, 1, red, dots);
+    if (t == 0) {
+      const double nrm2 = dots[0].x;
+      const double nrm = sqrt(nrm2);
+      const double2 al = Q[(long long)k * L + k];
+      const double aa = cabsd(al);
+      double2 gam;
+      if (nrm == 0.0) gam = cmk<double>(0, 0);
+      else if (aa == 0.0) gam = cmk<double>(-nrm, 0.0);
+      else gam = cmk<double>(-al.x / aa * nrm, -al.y / aa * nrm);
+      const double2 uk = csub<double>(al, gam);
+      const double un2 = cabs2<double>(uk) + (nrm2 - aa * aa);
+      s_gamma = gam;
+      s_unorm = (un2 > 0.0 && nrm > 0.0) ? 1.0 / sqrt(un2) : 0.0;
+      Q[(long long)k * L + k] = uk;
+    }
+    __syncthreads();
+    const double sc = s_unorm;
+    for (int i = k + t; i < n; i += BT) Q[(long long)i * L + k] = cscale<double>(Q[(long long)i * L + k], sc);
+    __syncthreads();
+    // dots of u with the remaining columns of Q (j > k) and all columns of G
+    const int nq = L - 1 - k, nd = nq + L;
+    double2 acc[2 * LMAX];
+    for (int c = 0; c < nd; ++c) acc[c] = cmk<double>(0, 0);
+    for (int i = k + t; i < n; i += BT) {
+      const double2 u = Q[(long long)i * L + k];
+      for (int c = 0; c < nq; ++c) acc[c] = cadd<double>(acc[c], cconjmul<double>(u, Q[(long long)i * L + k + 1 + c]));
+      for (int c = 0; c < L; ++c) acc[nq + c] = cadd<double>(acc[nq + c], cconjmul<double>(u, G[(long long)i * L + c]));
+    }
+    block_reduce_c(acc, nd, red, dots);
+    for (int i = k + t; i < n; i += BT) {
+      const double2 u2 = cscale<double>(Q[(long long)i * L + k], 2.0);
+      for (int c = 0; c < nq; ++c)
+        Q[(long long)i * L + k + 1 + c] = cfms<double>(Q[(long long)i * L + k + 1 + c], u2, dots[c]);
+      for (int c = 0; c < L; ++c) G[(long long)i * L + c] = cfms<double>(G[(long long)i * L + c], u2, dots[nq + c]);
+    }
+    __syncthreads();
+    if (t == 0) Rm[k][k] = s_gamma;
+    for (int j = k + 1 + t; j < L; j += BT) Rm[k][j] = Q[(long long)k * L + j];
+    __syncthreads();
+  }
+  for (int e = t; e < L * L; e += BT) {
+    const int i = e / L, j = e % L;
+    if (j < i) Rm[i][j] = cmk<double>(0, 0);
+    Ct[i][j] = G[(long long)i * L + j];
+    Wm[i][j] = cmk<double>(i == j ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+
+  // ---------------------------------------------------------------- one-sided Jacobi
+  {
+    const int LL = (L + 1) & ~1;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+      if (t == 0) s_conv = 1;
+      __syncthreads();
+      for (int r = 0; r < LL - 1; ++r) {
+        if (t < LL / 2) {
+          int i, j;
+          if (t == 0) { i = 0; j = r % (LL - 1) + 1; }
+          else {
+            i = (r + t) % (LL - 1) + 1;
+            j = ((r - t) % (LL - 1) + (LL - 1)) % (LL - 1) + 1;
+          }
+          if (i > j) { const int x = i; i = j; j = x; }
+          if (j < L) {
+            double al = 0, be = 0;
+            double2 ga = cmk<double>(0, 0);
+            for (int q = 0; q < L; ++q) {
+              al += cabs2<double>(Rm[q][i]);
+              be += cabs2<double>(Rm[q][j]);
+              ga = cadd<double>(ga, cconjmul<double>(Rm[q][i], Rm[q][j]));
+            }
+            const double g = cabsd(ga);
+            if (g > 1e-15 * sqrt(al * be) && g > 1e-300) {
+              s_conv = 0;
+              const double2 ph = cmk<double>(ga.x / g, ga.y / g);   // e^{i phi}
+              const double zeta = (be - al) / (2.0 * g);
+              const double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+              const double c = 1.0 / sqrt(1.0 + tt * tt), s = c * tt;
+              // column j' = column j * e^{-i phi}; then [c*i - s*j', s*i + c*j']
+              for (int q = 0; q < L; ++q) {
+                const double2 xi = Rm[q][i], xj = cmulc<double>(Rm[q][j], ph);
+                Rm[q][i] = csub<double>(cscale<double>(xi, c), cscale<double>(xj, s));
+                Rm[q][j] = cadd<double>(cscale<double>(xi, s), cscale<double>(xj, c));
+                const double2 wi = Wm[q][i], wj = cmulc<double>(Wm[q][j], ph);
+                Wm[q][i] = csub<double>(cscale<double>(wi, c), cscale<double>(wj, s));
+                Wm[q][j] = cadd<double>(cscale<double>(wi, s), cscale<double>(wj, c));
+              }
+            }
+          }
+        }
+        __syncthreads();
+      }
+      if (s_conv) break;
+      __syncthreads();
+    }
+  }
+  if (t < L) {
+    double s2 = 0;
+    for (int q = 0; q < L; ++q) s2 += cabs2<double>(Rm[q][t]);
+    sv[t] = sqrt(s2);
+  }
+  __syncthreads();
+  if (t == 0) {   // descending order (stable insertion sort of indices)
+    for (int i = 0; i < L; ++i) ordr[i] = i;
+    for (int i = 1; i < L; ++i) {
+      const int x = ordr[i];
+      int j = i - 1;
+      while (j >= 0 && sv[ordr[j]] < sv[x]) { ordr[j + 1] = ordr[j]; --j; }
+      ordr[j + 1] = x;
+    }
+  }
+  __syncthreads();
+  // sorted singular values; U_r columns = Rm columns / sigma (kept in Ym temporarily)
+  int p = 0;
+  for (int i = 0; i < L; ++i) p += (sv[ordr[i]] > a.tol_svd) ? 1 : 0;
+  for (int e = t; e < L * L; e += BT) {
+    const int q = e / L, c = e % L;
+    const int oc = ordr[c];
+    const double sg = sv[oc];
+    Ym[q][c] = sg > 0 ? cscale<double>(Rm[q][oc], 1.0 / sg) : cmk<double>(0, 0);   // U_r (sorted)
+    Zm[q][c] = Wm[q][oc];                                                        // W (sorted)
+  }
+  __syncthreads();
+  if (t < L) a.sv_out[(long long)di * L + t] = sv[ordr[t]];
+  if (t == 0) a.p_out[di] = p;
+  // D = U_r0^H Ct W_0 S_0^{-1}: first M1 = Ct W_0 (L x p) into Rm, then D into Hm
+  for (int e = t; e < L * p; e += BT) {
+    const int i = e / p, j = e % p;
+    double2 acc = cmk<double>(0, 0);
+    for (int q = 0; q < L; ++q) acc = cfma<double>(acc, Ct[i][q], Zm[q][j]);
+    Rm[i][j] = acc;
+  }
+  __syncthreads();
+  for (int e = t; e < p * p; e += BT) {
+    const int i = e / p, j = e % p;
+    double2 acc = cmk<double>(0, 0);
+    for (int q = 0; q < L; ++q) acc = cadd<double>(acc, cconjmul<double>(Ym[q][i], Rm[q][j]));
+    Hm[i][j] = cscale<double>(acc, 1.0 / sv[ordr[j]]);
+  }
+  __syncthreads();
+  // keep U_r0 for the eigenvectors in Ct (Ct is no longer needed)
+  for (int e = t; e < L * L; e += BT) Ct[e / L][e % L] = Ym[e / L][e % L];
+  __syncthreads();
+
+  // ---------------------------------------------------------------- eig(D), one thread
+  if (t == 0 && p > 0) {
+    const double eps = 2.220446049250313e-16;
+    for (int i = 0; i < p; ++i)
+      for (int j = 0; j < p; ++j) Zm[i][j] = cmk<double>(i == j ? 1.0 : 0.0, 0.0);
+    // Hessenberg reduction by Householder similarity transforms
+    for (int k = 0; k < p - 2; ++k) {
+      double nrm2 = 0;
+      for (int i = k + 1; i < p; ++i) nrm2 += cabs2<double>(Hm[i][k]);
+      const double nrm = sqrt(nrm2);
+      if (nrm == 0.0) continue;
+      const double2 al = Hm[k + 1][k];
+      const double aa = cabsd(al);
+      const double2 gam = (aa == 0.0) ? cmk<double>(-nrm, 0.0) : cmk<double>(-al.x / aa * nrm, -al.y / aa * nrm);
+      double2 u[LMAX];
+      for (int i = 0; i < p; ++i) u[i] = cmk<double>(0, 0);
+      u[k + 1] = csub<double>(al, gam);
+      for (int i = k + 2; i < p; ++i) u[i] = Hm[i][k];
+      double un2 = 0;
+      for (int i = k + 1; i < p; ++i) un2 += cabs2<double>(u[i]);
+      if (un2 == 0.0) continue;
+      const double sc = 1.0 / sqrt(un2);
+      for (int i = k + 1; i < p; ++i) u[i] = cscale<double>(u[i], sc);
+      // H = P H P, P = I - 2 u u^H
+      for (int j = 0; j < p; ++j) {        // left: rows k+1..p-1
+        double2 dt = cmk<double>(0, 0);
+        for (int i = k + 1; i < p; ++i) dt = cadd<double>(dt, cconjmul<double>(u[i], Hm[i][j]));
+        for (int i = k + 1; i < p; ++i) Hm[i][j] = cfms<double>(Hm[i][j], cscale<double>(u[i], 2.0), dt);
+      }
+      for (int i = 0; i < p; ++i) {        // right: columns k+1..p-1
+        double2 dt = cmk<double>(0, 0);
+        for (int j = k + 1; j < p; ++j) dt = cfma<double>(dt, Hm[i][j], u[j]);
+        for (int j = k + 1; j < p; ++j)
+          Hm[i][j] = csub<double>(Hm[i][j], cmulc<double>(cscale<double>(dt, 2.0), u[j]));
+        double2 dz = cmk<double>(0, 0);
+        for (int j = k + 1; j < p; ++j) dz = cfma<double>(dz, Zm[i][j], u[j]);
+        for (int j = k + 1; j < p; ++j)
+          Zm[i][j] = csub<double>(Zm[i][j], cmulc<double>(cscale<double>(dz, 2.0), u[j]));
+      }
+      Hm[k + 1][k] = gam;
+      for (int i = k + 2; i < p; ++i) Hm[i][k] = cmk<double>(0, 0);
+    }
+    // shifted QR iterations
+    int hi = p - 1, iter = 0, total = 0;
+    double2 gc[LMAX], gs[LMAX];
+    while (hi > 0 && total < 60 * p) {
+      int l = hi;
+      while (l > 0) {
+        const double sub = cabsd(Hm[l][l - 1]);
+        const double dia = cabsd(Hm[l][l]) + cabsd(Hm[l - 1][l - 1]);
+        if (sub <= eps * (dia > 0 ? dia : 1e-300)) { Hm[l][l - 1] = cmk<double>(0, 0); break; }
+        --l;
+      }
+      if (l == hi) { --hi; iter = 0; continue; }
+      ++iter; ++total;
+      // Wilkinson shift: eigenvalue of the trailing 2x2 closest to H[hi][hi]
+      const double2 A = Hm[hi - 1][hi - 1], B = Hm[hi - 1][hi], C = Hm[hi][hi - 1], Dd = Hm[hi][hi];
+      double2 mu;
+      if (iter % 11 == 10) {
+        mu = cadd<double>(Dd, cmk<double>(0.75 * cabsd(C), 0.0));   // exceptional shift
+      } else {
+        const double2 tr = cscale<double>(cadd<double>(A, Dd), 0.5);
+        const double2 df = cscale<double>(csub<double>(A, Dd), 0.5);
+        const double2 disc = cadd<double>(cmul<double>(df, df), cmul<double>(B, C));
+        // complex square root
+        const double r = cabsd(disc);
+        double2 sq = cmk<double>(sqrt(0.5 * (r + disc.x)), 0.0);
+        sq.y = (sq.x > 0) ? disc.y / (2.0 * sq.x) : sqrt(0.5 * (r - disc.x)) * (disc.y < 0 ? -1.0 : 1.0);
+        const double2 m1 = cadd<double>(tr, sq), m2 = csub<double>(tr, sq);
+        mu = (cabs2<double>(csub<double>(m1, Dd)) < cabs2<double>(csub<double>(m2, Dd))) ? m1 : m2;
+      }
+      for (int k = l; k <= hi; ++k) Hm[k][k] = csub<double>(Hm[k][k], mu);
+      for (int k = l; k < hi; ++k) {
+        const double2 x = Hm[k][k], y = Hm[k + 1][k];
+        const double rr = sqrt(cabs2<double>(x) + cabs2<double>(y));
+        double2 al, be;
+        if (rr == 0.0) { al = cmk<double>(1, 0); be = cmk<double>(0, 0); }
+        else { al = cscale<double>(x, 1.0 / rr); be = cscale<double>(y, 1.0 / rr); }
+        gc[k] = al; gs[k] = be;
+        // rows k, k+1 <- [[conj(al), conj(be)], [-be, al]] rows, columns k..p-1
+        for (int j = k; j < p; ++j) {
+          const double2 hk = Hm[k][j], hk1 = Hm[k + 1][j];
+          Hm[k][j] = cadd<double>(cconjmul<double>(al, hk), cconjmul<double>(be, hk1));
+          Hm[k + 1][j] = csub<double>(cmul<double>(al, hk1), cmul<double>(be, hk));
+        }
+      }
+      for (int k = l; k < hi; ++k) {
+        const double2 al = gc[k], be = gs[k];
+        // columns k, k+1 <- columns * G^H, G^H = [[al, -conj(be)], [be, conj(al)]]
+        const int rmax = (k + 2 < hi) ? k + 2 : hi;
+        for (int i = 0; i <= rmax; ++i) {
+          const double2 hk = Hm[i][k], hk1 = Hm[i][k + 1];
+          Hm[i][k] = cadd<double>(cmul<double>(hk, al), cmul<double>(hk1, be));
+          Hm[i][k + 1] = csub<double>(cmulc<double>(hk1, al), cmulc<double>(hk, be));
+        }
+        for (int i = 0; i < p; ++i) {
+          const double2 zk = Zm[i][k], zk1 = Zm[i][k + 1];
+          Zm[i][k] = cadd<double>(cmul<double>(zk, al), cmul<double>(zk1, be));
+          Zm[i][k + 1] = csub<double>(cmulc<double>(zk1, al), cmulc<double>(zk, be));
+        }
+      }
+      for (int k = l; k <= hi; ++k) Hm[k][k] = cadd<double>(Hm[k][k], mu);
+    }
+    if (hi > 0) a.status[di] |= 1;   // QR iteration did not converge
+    // eigenvectors of the triangular factor, then of D: y_k = Z * (back substitution)
+    const double hn = [&] {
+      double m = 0;
+      for (int i = 0; i < p; ++i)
+        for (int j = i; j < p; ++j) m = fmax(m, cabsd(Hm[i][j]));
+      return m;
+    }();
+    for (int k = 0; k < p; ++k) {
+      double2 y[LMAX];
+      for (int i = 0; i < p; ++i) y[i] = cmk<double>(0, 0);
+      y[k] = cmk<double>(1, 0);
+      const double2 lk = Hm[k][k];
+      for (int i = k - 1; i >= 0; --i) {
+        double2 acc = cmk<double>(0, 0);
+        for (int j = i + 1; j <= k; ++j) acc = cfma<double>(acc, Hm[i][j], y[j]);
+        double2 den = csub<double>(Hm[i][i], lk);
+        if (cabsd(den) < eps * hn) den = cmk<double>(eps * (hn > 0 ? hn : 1.0), 0.0);
+        y[i] = cdiv<double>(cmk<double>(-acc.x, -acc.y), den);
+      }
+      for (int i = 0; i < p; ++i) {
+        double2 acc = cmk<double>(0, 0);
+        for (int j = 0; j <= k; ++j) acc = cfma<double>(acc, Zm[i][j], y[j]);
+        Ym[i][k] = acc;
+      }
+    }
+  }
+  __syncthreads();
+  if (t < a.L) {
+    double2 lam = cmk<double>(0, 0);
+    unsigned char keep = 0;
+    if (t < p) {
+      lam = Hm[t][t];
+      const double band = 1e-9 * fmax(1.0, cabsd(lam));
+      const int ox = owner_axis(lam.x, a.x0, a.x1, a.nx, band);
+      const int oy = owner_axis(lam.y, a.y0, a.y1, a.ny, band);
+      keep = (ox == a.ix[d] && oy == a.iy[d]) ? 1 : 0;
+    }
+    a.eig_out[(long long)di * L + t] = lam;
+    if (a.keep_out) a.keep_out[(long long)di * L + t] = keep;
+  }
+  if (!a.eigvec_out || p == 0) return;
+  // ---------------------------------------------------------------- eigenvectors
+  // x_k = U_r0 s_k (L-vector), v_k = Q [x_k; 0] by applying the reflectors backwards
+  double2* V = a.eigvec_out + (long long)di * n * L;
+  for (int k = 0; k < p; ++k) {
+    for (int i = t; i < n; i += BT) {
+      double2 acc = cmk<double>(0, 0);
+      if (i < L)
+        for (int j = 0; j < p; ++j) acc = cfma<double>(acc, Ct[i][j], Ym[j][k]);
+      V[(long long)i * L + k] = acc;
+    }
+  }
+  __syncthreads();
+  for (int r = L - 1; r >= 0; --r) {
+    double2 acc[LMAX];
+    for (int k = 0; k < p; ++k) acc[k] = cmk<double>(0, 0);
+    for (int i = r + t; i < n; i += BT) {
+      const double2 u = Q[(long long)i * L + r];
+      for (int k = 0; k < p; ++k) acc[k] = cadd<double>(acc[k], cconjmul<double>(u, V[(long long)i * L + k]));
+    }
+    block_reduce_c(acc, p, red, dots);
+    for (int i = r + t; i < n; i += BT) {
+      const double2 u2 = cscale<double>(Q[(long long)i * L + r], 2.0);
+      for (int k = 0; k < p; ++k) V[(long long)i * L + k] = cfms<double>(V[(long long)i * L + k], u2, dots[k]);
+    }
+    __syncthreads();
+  }
+  // normalise: unit 2-norm, largest-modulus entry real positive
+  {
+    double2 acc[LMAX];
+    for (int k = 0; k < p; ++k) acc[k] = cmk<double>(0, 0);
+    for (int i = t; i < n; i += BT)
+      for (int k = 0; k < p; ++k) acc[k].x += cabs2<double>(V[(long long)i * L + k]);
+    block_reduce_c(acc, p, red, dots);
+    __shared__ double2 ph[LMAX];
+    if (t < p) {
+      double best = -1;
+      double2 bv = cmk<double>(1, 0);
+      for (int i = 0; i < n; ++i) {
+        const double m = cabs2<double>(V[(long long)i * L + t]);
+        if (m > best) { best = m; bv = V[(long long)i * L + t]; }
+      }
+      const double nb = cabsd(bv);
+      const double nr = sqrt(dots[t].x);
+      // scale = conj(bv)/|bv| / ||v||
+      ph[t] = (nb > 0 && nr > 0) ? cmk<double>(bv.x / nb / nr, -bv.y / nb / nr) : cmk<double>(0, 0);
+    }
+    __syncthreads();
+    for (int i = t; i < n; i += BT)
+      for (int k = 0; k < p; ++k) V[(long long)i * L + k] = cmul<double>(V[(long long)i * L + k], ph[k]);
+  }
+}
+
+// normalise each candidate's vector x (length n) and keep min(1/||x||) as sigma estimate
+__global__ __launch_bounds__(256) void normalize_kernel(double2* __restrict__ X, long long xstride, int n,
+                                                        double* __restrict__ est, int record) {
+  const int b = blockIdx.x;
+  double2* x = X + (long long)b * xstride;
+  double a = 0;
+  for (int i = threadIdx.x; i < n; i += 256) a += cabs2<double>(x[i]);
+  __shared__ double ra[4];
+  a = wave_sum(a);
+  if ((threadIdx.x & 63) == 0) ra[threadIdx.x >> 6] = a;
+  __syncthreads();
+  const double nr = sqrt(ra[0] + ra[1] + ra[2] + ra[3]);
+  const double inv = (nr > 0 && nr < 1.7976931348623157e308) ? 1.0 / nr : 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) x[i] = cscale<double>(x[i], inv);
+  if (threadIdx.x == 0 && record) {
+    const double e = (nr > 0) ? inv : 0.0;   // 1/||T^{-1} u|| >= sigma_min for unit u
+    est[b] = fmin(est[b], nr < 1.7976931348623157e308 ? e : 0.0);
+  }
+}
+
+// deterministic start vectors for the inverse iteration, and est = +inf
+__global__ __launch_bounds__(256) void start_kernel(double2* __restrict__ X, long long xstride, int n,
+                                                    double* __restrict__ est) {
+  const int b = blockIdx.x;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    const double v = 1.0 + 0.5 * sin(0.7 * i + 0.3) + 0.25 * cos(1.9 * i);
+    X[(long long)b * xstride + i] = cmk<double>(v, 0.1 * cos(0.37 * i));
+  }
+  if (threadIdx.x == 0) est[b] = 1.7976931348623157e308;
+}
+
+hipError_t launch_beyn(const BeynArgs& a, int ndisks, hipStream_t st) {
+  if (a.L > LMAX || a.L < 1) return hipErrorInvalidValue;
+  beyn_kernel<<<ndisks, BT, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_normalize(double2* X, long long xstride, int n, double* est, int record, int nb, hipStream_t st) {
+  normalize_kernel<<<nb, 256, 0, st>>>(X, xstride, n, est, record);
+  return hipGetLastError();
+}
+
+hipError_t launch_start(double2* X, long long xstride, int n, double* est, int nb, hipStream_t st) {
+  start_kernel<<<nb, 256, 0, st>>>(X, xstride, n, est);
+  return hipGetLastError();
+}
+
+}  // namespace nep

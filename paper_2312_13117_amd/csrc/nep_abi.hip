@@ -1,0 +1,793 @@
+// Host side of the C ABI (include/nep.h): plan construction (cover, nodes and weights,
+// batching, workspace), the sweep driver, Beyn and verification drivers.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/nep.h"
+#include "beyn.h"
+#include "common.h"
+#include "lu.h"
+#include "sweep.h"
+
+using namespace nep;
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipError_t alloc(size_t b) {
+    if (b <= bytes && p) return hipSuccess;
+    if (p) { hipFree(p); p = nullptr; bytes = 0; }
+    if (b == 0) return hipSuccess;
+    hipError_t e = hipMalloc(&p, b);
+    if (e == hipSuccess) bytes = b;
+    else p = nullptr;
+    return e;
+  }
+  void release() {
+    if (p) hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <typename X> X* as() const { return static_cast<X*>(p); }
+};
+
+struct PhaseTimer {
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<int, int>> marks[6];   // per phase: (start ev, end ev)
+  int used = 0;
+  hipEvent_t get() {
+    if (used == (int)pool.size()) {
+      hipEvent_t e;
+      hipEventCreate(&e);
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  void reset() {
+    used = 0;
+    for (auto& m : marks) m.clear();
+  }
+};
+
+enum { PH_ASM = 0, PH_LU = 1, PH_SOLVE = 2, PH_REFINE = 3, PH_SUMS = 4, PH_TOTAL = 5 };
+
+}  // namespace
+
+struct nep_plan {
+  hipStream_t st = 0;
+  nep_options opt{};
+  int nprob = 0;
+  std::vector<ProblemDev> pd;
+  std::vector<nep_region> reg;
+  // disks (global numbering)
+  int nd = 0;
+  std::vector<int> disk_first;        // per problem
+  std::vector<int> d_prob, d_n, d_ix, d_iy;
+  std::vector<double> d_hx, d_hy, d_r;
+  std::vector<double2> d_c;
+  std::vector<long long> d_soff;      // rows before this disk in the sums buffers
+  long long sum_rows = 0;
+  std::vector<double2> h_z, h_w;      // nodes and weights, nd x N
+  int nmax = 0;
+  // device copies
+  DevBuf dev_dn, dev_ix, dev_iy, dev_soff, dev_w, dev_z;
+  DevBuf PfN, PfN2, C0, C1, prof, ind, flags;
+  DevBuf X, R, xoff, tnode, dlist;
+  // LU workspaces
+  DevBuf W, ipiv, perm, Linv, Uinv, info;
+  DevBuf W64, ipiv64, perm64, Linv64, Uinv64, info64;
+  DevBuf rn2, xn2, active, coefn, counter, sing;
+  DevBuf bscr, beig, bp, bsv, bkeep, bstat, bvec;
+  DevBuf vest;
+  int batch = 0;
+  bool swept = false, swept_with_V = false;
+  const void* const* last_V = nullptr;
+  std::vector<const void*> last_F;
+  std::string err;
+  nep_stats stats{};
+  PhaseTimer timer;
+  LuTimers lut;
+  std::vector<hipEvent_t> gemm_ev;
+};
+
+static nep_status fail(nep_plan_t* p, nep_status s, const char* fmt, ...) {
+  if (p) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    p->err = buf;
+  }
+  return s;
+}
+
+#define HIPCHK(plan, expr)                                                                   \
+  do {                                                                                       \
+    hipError_t _e = (expr);                                                                  \
+    if (_e != hipSuccess)                                                                    \
+      return fail(plan, _e == hipErrorOutOfMemory ? NEP_ERR_NOMEM : NEP_ERR_HIP, "%s: %s (%s:%d)", #expr, \
+                  hipGetErrorString(_e), __FILE__, __LINE__);                                \
+  } while (0)
+
+static thread_local std::string g_last_create_error;
+
+static size_t elem_bytes(int precision) { return precision == NEP_FP32_REFINE ? 8 : 16; }
+
+static int choose_batch(int n, int precision, int ntask_max, int requested) {
+  if (requested > 0) return std::min(requested, std::max(1, ntask_max));
+  const double budget = 8.0e9;   // bytes of factor workspace
+  const double per = (double)n * n * elem_bytes(precision);
+  int b = (int)std::min(512.0, std::max(1.0, std::floor(budget / per)));
+  if (b >= 8) b -= b % 8;
+  return std::max(1, std::min(b, std::max(1, ntask_max)));
+}
+
+static void tmark(nep_plan_t* p, int phase, bool start) {
+  hipEvent_t e = p->timer.get();
+  hipEventRecord(e, p->st);
+  int idx = p->timer.used - 1;
+  if (start) p->timer.marks[phase].push_back({idx, -1});
+  else if (!p->timer.marks[phase].empty()) p->timer.marks[phase].back().second = idx;
+}
+
+static double tsum(nep_plan_t* p, int phase) {
+  double ms = 0;
+  for (auto& m : p->timer.marks[phase]) {
+    if (m.second < 0) continue;
+    float x = 0;
+    hipEventElapsedTime(&x, p->timer.pool[m.first], p->timer.pool[m.second]);
+    ms += x;
+  }
+  return ms;
+}
+
+static void finish_stats(nep_plan_t* p) {
+  p->stats.ms_assemble = tsum(p, PH_ASM);
+  p->stats.ms_lu = tsum(p, PH_LU);
+  p->stats.ms_solve = tsum(p, PH_SOLVE);
+  p->stats.ms_refine = tsum(p, PH_REFINE);
+  p->stats.ms_sums = tsum(p, PH_SUMS);
+  p->stats.ms_total = tsum(p, PH_TOTAL);
+  double g = 0;
+  for (int i = 0; i < p->lut.npairs; ++i) {
+    float x = 0;
+    hipEventElapsedTime(&x, p->lut.ev[2 * i], p->lut.ev[2 * i + 1]);
+    g += x;
+  }
+  p->stats.ms_gemm = g;
+  p->stats.gemm_launches = p->lut.gemm_launches;
+  p->stats.gemm_flops = p->lut.gemm_flops;
+}
+
+static void reset_stats(nep_plan_t* p) {
+  std::memset(&p->stats, 0, sizeof p->stats);
+  p->timer.reset();
+  p->lut.npairs = 0;
+  p->lut.gemm_launches = 0;
+  p->lut.gemm_flops = 0;
+}
+
+// ---------------------------------------------------------------------------- plan
+extern "C" nep_status nep_plan(const nep_problem* probs, int nprob, const nep_region* regs,
+                               const nep_options* opt, hipStream_t stream, nep_plan_t** out) {
+  if (!out) return NEP_ERR_ARG;
+  *out = nullptr;
+  g_last_create_error.clear();
+  auto bad = [](const char* m) { g_last_create_error = m; return NEP_ERR_ARG; };
+  if (!probs || nprob < 1 || !regs || !opt) return bad("null argument or nprob < 1");
+  const nep_options& o = *opt;
+  if (o.N < 4 || o.N > 256 || (o.N & 1)) return bad("N must be even, 4..256");
+  if (o.s < 1 || o.s > 8) return bad("s must be 1..8");
+  if (o.L < 0 || o.L > 32 || o.s + o.L > 32) return bad("L must be 0..32 with s + L <= 32");
+  if (o.precision != NEP_FP64 && o.precision != NEP_FP32_REFINE) return bad("unknown precision");
+  if (o.max_refine < 0 || o.max_refine > 8) return bad("max_refine must be 0..8");
+  if (!(o.tol_ind >= 0) || !(o.tol_svd >= 0) || !(o.tol_ver >= 0)) return bad("tolerances must be >= 0");
+  for (int p = 0; p < nprob; ++p) {
+    const nep_problem& q = probs[p];
+    if (q.n < 1 || q.n > 4096) return bad("n must be 1..4096");
+    if (q.nterms < 1 || q.nterms > MAX_TERMS || !q.A_dev || !q.phi_kind) return bad("bad problem terms");
+    for (int k = 0; k < q.nterms; ++k)
+      if (q.phi_kind[k] < NEP_PHI_ONE || q.phi_kind[k] > NEP_PHI_EXP_NEG_TAU_Z) return bad("unknown phi kind");
+    const nep_region& r = regs[p];
+    if (r.nx < 1 || r.ny < 1 || !(r.x1 > r.x0) || !(r.y1 > r.y0)) return bad("bad region");
+    if ((long long)r.nx * r.ny > 1000000) return bad("too many cells");
+  }
+  nep_plan_t* P = new (std::nothrow) nep_plan_t();
+  if (!P) return NEP_ERR_NOMEM;
+  P->st = stream;
+  P->opt = o;
+  P->nprob = nprob;
+  P->reg.assign(regs, regs + nprob);
+  for (int p = 0; p < nprob; ++p) {
+    const nep_problem& q = probs[p];
+    ProblemDev d{};
+    d.n = q.n;
+    d.nterms = q.nterms;
+    for (int k = 0; k < q.nterms; ++k) {
+      d.A[k] = static_cast<const double2*>(q.A_dev[k]);
+      d.kind[k] = q.phi_kind[k];
+      d.param[k] = q.phi_param ? q.phi_param[k] : 0.0;
+    }
+    P->pd.push_back(d);
+    P->nmax = std::max(P->nmax, q.n);
+  }
+  // cover: cells x-major, circumscribed circles; nodes/weights of eq (2.3)
+  const int N = o.N;
+  for (int p = 0; p < nprob; ++p) {
+    const nep_region& r = regs[p];
+    P->disk_first.push_back(P->nd);
+    const double hx = (r.x1 - r.x0) / r.nx / 2.0, hy = (r.y1 - r.y0) / r.ny / 2.0;
+    const double rad = std::hypot(hx, hy);
+    for (int ix = 0; ix < r.nx; ++ix)
+      for (int iy = 0; iy < r.ny; ++iy) {
+        const double cx = r.x0 + (2 * ix + 1) * hx, cy = r.y0 + (2 * iy + 1) * hy;
+        P->d_prob.push_back(p);
+        P->d_n.push_back(probs[p].n);
+        P->d_ix.push_back(ix);
+        P->d_iy.push_back(iy);
+        P->d_hx.push_back(hx);
+        P->d_hy.push_back(hy);
+        P->d_r.push_back(rad);
+        P->d_c.push_back(make_double2(cx, cy));
+        P->d_soff.push_back(P->sum_rows);
+        P->sum_rows += probs[p].n;
+        for (int j = 0; j < N; ++j) {
+          const double th = 2.0 * M_PI * j / N;
+          const double cs = std::cos(th), sn = std::sin(th);
+          P->h_z.push_back(make_double2(cx + rad * cs, cy + rad * sn));
+          P->h_w.push_back(make_double2(rad / N * cs, rad / N * sn));
+        }
+        P->nd++;
+      }
+  }
+  const int nd = P->nd, s = o.s, L = o.L, m = s + L;
+  auto up = [&](DevBuf& b, const void* src, size_t bytes) -> hipError_t {
+    hipError_t e = b.alloc(bytes);
+    if (e != hipSuccess) return e;
+    return hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice);
+  };
+#define PCHK(expr)                                                                 \
+  do {                                                                             \
+    hipError_t _e = (expr);                                                        \
+    if (_e != hipSuccess) {                                                        \
+      g_last_create_error = std::string(#expr) + ": " + hipGetErrorString(_e);     \
+      nep_destroy(P);                                                              \
+      return _e == hipErrorOutOfMemory ? NEP_ERR_NOMEM : NEP_ERR_HIP;             \
+    }                                                                              \
+  } while (0)
+  PCHK(up(P->dev_dn, P->d_n.data(), sizeof(int) * nd));
+  PCHK(up(P->dev_ix, P->d_ix.data(), sizeof(int) * nd));
+  PCHK(up(P->dev_iy, P->d_iy.data(), sizeof(int) * nd));
+  PCHK(up(P->dev_soff, P->d_soff.data(), sizeof(long long) * nd));
+  PCHK(up(P->dev_w, P->h_w.data(), sizeof(double2) * nd * N));
+  PCHK(up(P->dev_z, P->h_z.data(), sizeof(double2) * nd * N));
+  PCHK(P->PfN.alloc(sizeof(double2) * P->sum_rows * s));
+  PCHK(P->PfN2.alloc(sizeof(double2) * P->sum_rows * s));
+  if (L > 0) {
+    PCHK(P->C0.alloc(sizeof(double2) * P->sum_rows * L));
+    PCHK(P->C1.alloc(sizeof(double2) * P->sum_rows * L));
+  }
+  PCHK(P->prof.alloc(sizeof(double) * (size_t)nd * N * s));
+  PCHK(P->ind.alloc(sizeof(double) * (size_t)nd * s));
+  PCHK(P->flags.alloc((size_t)nd));
+  // solutions of every node of a full sweep
+  long long xelems = 0;
+  for (int d = 0; d < nd; ++d) xelems += (long long)N * P->d_n[d] * m;
+  PCHK(P->X.alloc(sizeof(double2) * xelems));
+  PCHK(P->xoff.alloc(sizeof(long long) * nd));
+  PCHK(P->dlist.alloc(sizeof(int) * nd));
+  PCHK(P->tnode.alloc(sizeof(double2) * (size_t)nd * N));
+  PCHK(P->sing.alloc(sizeof(int) * (size_t)nd * N));
+  PCHK(P->counter.alloc(sizeof(int) * 4));
+  // factor workspace
+  int ntask_max = 0;
+  for (int p = 0; p < nprob; ++p) ntask_max = std::max(ntask_max, (regs[p].nx * regs[p].ny) * N);
+  P->batch = choose_batch(P->nmax, o.precision, ntask_max, o.batch);
+  const int B = P->batch, nm = P->nmax;
+  const int steps = (nm + LU_NB - 1) / LU_NB;
+  const size_t eb = elem_bytes(o.precision);
+  PCHK(P->W.alloc(eb * (size_t)B * nm * nm));
+  PCHK(P->ipiv.alloc(sizeof(int) * (size_t)B * nm));
+  PCHK(P->perm.alloc(sizeof(int) * (size_t)B * steps * perm_ints_per_step()));
+  PCHK(P->Linv.alloc(eb * (size_t)B * steps * LU_NB * LU_NB));
+  PCHK(P->Uinv.alloc(eb * (size_t)B * steps * LU_NB * LU_NB));
+  PCHK(P->info.alloc(sizeof(int) * B));
+  if (o.precision == NEP_FP32_REFINE) {
+    PCHK(P->R.alloc(sizeof(double2) * (size_t)B * nm * m));
+    PCHK(P->rn2.alloc(sizeof(double) * B));
+    PCHK(P->xn2.alloc(sizeof(double) * B));
+    PCHK(P->active.alloc(sizeof(int) * B));
+  }
+  PCHK(P->coefn.alloc(sizeof(double) * MAX_TERMS * nprob));
+  for (int p = 0; p < nprob; ++p)
+    PCHK(launch_coef_norms(P->pd[p], P->coefn.as<double>() + MAX_TERMS * p, P->st));
+  P->gemm_ev.resize(2 * LuTimers::MAXP);
+  for (auto& e : P->gemm_ev) PCHK(hipEventCreate(&e));
+  P->lut.ev = P->gemm_ev.data();
+  P->lut.ev_enabled = true;
+  PCHK(hipStreamSynchronize(P->st));
+#undef PCHK
+  *out = P;
+  return NEP_OK;
+}
+
+extern "C" void nep_destroy(nep_plan_t* P) {
+  if (!P) return;
+  hipStreamSynchronize(P->st);
+  DevBuf* bufs[] = {&P->dev_dn, &P->dev_ix, &P->dev_iy, &P->dev_soff, &P->dev_w, &P->dev_z, &P->PfN, &P->PfN2,
+                    &P->C0, &P->C1, &P->prof, &P->ind, &P->flags, &P->X, &P->R, &P->xoff, &P->tnode, &P->dlist,
+                    &P->W, &P->ipiv, &P->perm, &P->Linv, &P->Uinv, &P->info, &P->W64, &P->ipiv64, &P->perm64,
+                    &P->Linv64, &P->Uinv64, &P->info64, &P->rn2, &P->xn2, &P->active, &P->coefn, &P->counter, &P->sing, &P->bscr,
+                    &P->beig, &P->bp, &P->bsv, &P->bkeep, &P->bstat, &P->bvec, &P->vest};
+  for (DevBuf* b : bufs) b->release();
+  for (auto& e : P->gemm_ev) if (e) hipEventDestroy(e);
+  for (auto& e : P->timer.pool) hipEventDestroy(e);
+  delete P;
+}
+
+// ---------------------------------------------------------------------------- factor + solve
+// Mixed-precision convergence: active[b] = ||R_b|| > eps * ||T(z_b)|| * ||X_b||, with
+// ||T(z)||_F bounded by sum_k |phi_k(z)| ||A_k||_F.
+__global__ void converge_kernel(ProblemDev pd, const double2* znode, const double* coefn, const double* rn2,
+                                const double* xn2, double eps, int* active, int nb, int* count) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  const double2 z = znode[b];
+  double tn = 0;
+  for (int k = 0; k < pd.nterms; ++k) {
+    double2 f;
+    switch (pd.kind[k]) {
+      case PHI_ONE: f = make_double2(1, 0); break;
+      case PHI_Z: f = z; break;
+      case PHI_Z2: f = make_double2(z.x * z.x - z.y * z.y, 2 * z.x * z.y); break;
+      case PHI_NEG_Z: f = make_double2(-z.x, -z.y); break;
+      default: {
+        const double e = exp(-pd.param[k] * z.x);
+        f = make_double2(e, 0);
+      }
+    }
+    tn += hypot(f.x, f.y) * coefn[k];
+  }
+  const double r = sqrt(rn2[b]), x = sqrt(xn2[b]);
+  const int a = (r > eps * tn * x || !(r == r)) ? 1 : 0;
+  active[b] = a;
+  if (a) atomicAdd(count, 1);
+}
+
+struct SweepCall {
+  std::vector<int> disks;   // global disk ids of this sweep
+  int s, L;                 // columns of F and V used
+  const void* const* F;
+  const void* const* V;
+};
+
+template <typename T>
+static nep_status factor_chunk(nep_plan_t* P, DevBuf& W, DevBuf& ipv, DevBuf& prm, DevBuf& Li, DevBuf& Ui,
+                               DevBuf& inf, const ProblemDev& pd, const double2* znode, int nb) {
+  const int n = pd.n;
+  const int steps = (n + LU_NB - 1) / LU_NB;
+  const long long mstride = (long long)n * n;
+  const long long pstride = (long long)steps * perm_ints_per_step();
+  const long long istride = (long long)steps * LU_NB * LU_NB;
+  tmark(P, PH_ASM, true);
+  HIPCHK(P, launch_assemble<T>(pd, znode, W.as<c2<T>>(), mstride, nb, P->st));
+  tmark(P, PH_ASM, false);
+  HIPCHK(P, hipMemsetAsync(inf.p, 0, sizeof(int) * nb, P->st));
+  tmark(P, PH_LU, true);
+  HIPCHK(P, lu_factor_batch<T>(W.as<c2<T>>(), mstride, n, nb, ipv.as<int>(), prm.as<int>(), pstride,
+                               Li.as<c2<T>>(), Ui.as<c2<T>>(), istride, inf.as<int>(), P->st, &P->lut));
+  tmark(P, PH_LU, false);
+  P->stats.lu_count += nb;
+  P->stats.lu_flops += 8.0 / 3.0 * (double)n * n * n * nb;
+  return NEP_OK;
+}
+
+template <typename T>
+static nep_status solve_chunk(nep_plan_t* P, DevBuf& W, DevBuf& prm, DevBuf& Li, DevBuf& Ui, int n, int nb,
+                              double2* X, int m, bool trans, const int* active) {
+  const int steps = (n + LU_NB - 1) / LU_NB;
+  HIPCHK(P, lu_solve_batch<T>(W.as<c2<T>>(), (long long)n * n, n, nb, prm.as<int>(),
+                              (long long)steps * perm_ints_per_step(), Li.as<c2<T>>(), Ui.as<c2<T>>(),
+                              (long long)steps * LU_NB * LU_NB, X, (long long)n * m, m, trans, active, P->st));
+  return NEP_OK;
+}
+
+static nep_status ensure_fp64_ws(nep_plan_t* P, int n, int B) {
+  const int steps = (n + LU_NB - 1) / LU_NB;
+  HIPCHK(P, P->W64.alloc(16ull * B * n * n));
+  HIPCHK(P, P->ipiv64.alloc(sizeof(int) * (size_t)B * n));
+  HIPCHK(P, P->perm64.alloc(sizeof(int) * (size_t)B * steps * perm_ints_per_step()));
+  HIPCHK(P, P->Linv64.alloc(16ull * B * steps * LU_NB * LU_NB));
+  HIPCHK(P, P->Uinv64.alloc(16ull * B * steps * LU_NB * LU_NB));
+  HIPCHK(P, P->info64.alloc(sizeof(int) * B));
+  return NEP_OK;
+}
+
+static nep_status run_sweep(nep_plan_t* P, const SweepCall& sc, bool* singular, bool* fallback) {
+  const int N = P->opt.N, s = sc.s, L = sc.L, m = s + L;
+  const int nl = (int)sc.disks.size();
+  // layout of this call's solutions: entry li, node j at xoff[li] + j*n*m
+  std::vector<long long> xoff(nl);
+  std::vector<double2> nodes((size_t)nl * N);
+  long long acc = 0;
+  for (int li = 0; li < nl; ++li) {
+    const int d = sc.disks[li];
+    xoff[li] = acc;
+    acc += (long long)N * P->d_n[d] * m;
+    for (int j = 0; j < N; ++j) nodes[(size_t)li * N + j] = P->h_z[(size_t)d * N + j];
+  }
+  if (acc * (long long)sizeof(double2) > (long long)P->X.bytes)
+    return fail(P, NEP_ERR_CAPACITY, "solution buffer too small for this sweep");
+  HIPCHK(P, hipMemsetAsync(P->sing.p, 0, sizeof(int) * (size_t)nl * N, P->st));
+  HIPCHK(P, hipMemcpyAsync(P->xoff.p, xoff.data(), sizeof(long long) * nl, hipMemcpyHostToDevice, P->st));
+  HIPCHK(P, hipMemcpyAsync(P->tnode.p, nodes.data(), sizeof(double2) * nodes.size(), hipMemcpyHostToDevice, P->st));
+  HIPCHK(P, hipMemcpyAsync(P->dlist.p, sc.disks.data(), sizeof(int) * nl, hipMemcpyHostToDevice, P->st));
+  double2* X = P->X.as<double2>();
+  const double2* tn = P->tnode.as<double2>();
+  const bool mixed = P->opt.precision == NEP_FP32_REFINE;
+  // runs of consecutive list entries of one problem
+  int li = 0;
+  while (li < nl) {
+    const int prob = P->d_prob[sc.disks[li]];
+    int lj = li;
+    while (lj < nl && P->d_prob[sc.disks[lj]] == prob) ++lj;
+    const ProblemDev& pd = P->pd[prob];
+    const int n = pd.n;
+    const double2* F = static_cast<const double2*>(sc.F[prob]);
+    const double2* V = (L > 0) ? static_cast<const double2*>(sc.V[prob]) : nullptr;
+    const long long ntask = (long long)(lj - li) * N;
+    for (long long t0 = 0; t0 < ntask; t0 += P->batch) {
+      const int nb = (int)std::min<long long>(P->batch, ntask - t0);
+      const double2* zb = tn + (long long)li * N + t0;
+      double2* Xb = X + xoff[li] + t0 * (long long)n * m;
+      HIPCHK(P, launch_rhs(F, s, V, L, n, Xb, (long long)n * m, nb, P->st));
+      if (!mixed) {
+        nep_status r = factor_chunk<double>(P, P->W, P->ipiv, P->perm, P->Linv, P->Uinv, P->info, pd, zb, nb);
+        if (r != NEP_OK) return r;
+        HIPCHK(P, launch_mark_singular(P->info.as<int>(), nb, P->sing.as<int>() + (long long)li * N + t0, P->st));
+        tmark(P, PH_SOLVE, true);
+        r = solve_chunk<double>(P, P->W, P->perm, P->Linv, P->Uinv, n, nb, Xb, m, false, nullptr);
+        tmark(P, PH_SOLVE, false);
+        if (r != NEP_OK) return r;
+      } else {
+        nep_status r = factor_chunk<float>(P, P->W, P->ipiv, P->perm, P->Linv, P->Uinv, P->info, pd, zb, nb);
+        if (r != NEP_OK) return r;
+        tmark(P, PH_SOLVE, true);
+        r = solve_chunk<float>(P, P->W, P->perm, P->Linv, P->Uinv, n, nb, Xb, m, false, nullptr);
+        tmark(P, PH_SOLVE, false);
+        if (r != NEP_OK) return r;
+        // complex128 residual refinement: R = B - T X; X += LU32 \ R until converged
+        const double eps = std::ldexp(1.0, -52) * std::sqrt((double)n);
+        double2* Rb = P->R.as<double2>();
+        tmark(P, PH_REFINE, true);
+        std::vector<int> act(nb, 1);
+        int nact = nb;
+        for (int it = 0; it <= P->opt.max_refine; ++it) {
+          HIPCHK(P, launch_residual(pd, zb, Xb, F, s, V, L, (long long)n * m, m, nb, Rb, P->st));
+          HIPCHK(P, launch_norms(Rb, Xb, (long long)n * m, n * m, P->rn2.as<double>(), P->xn2.as<double>(), nb,
+                                 P->st));
+          int* cnt = P->counter.as<int>();
+          HIPCHK(P, hipMemsetAsync(cnt, 0, sizeof(int), P->st));
+          converge_kernel<<<(nb + 255) / 256, 256, 0, P->st>>>(pd, zb, P->coefn.as<double>() + MAX_TERMS * prob,
+                                                                P->rn2.as<double>(), P->xn2.as<double>(), eps,
+                                                                P->active.as<int>(), nb, cnt);
+          HIPCHK(P, hipGetLastError());
+          HIPCHK(P, hipMemcpyAsync(&nact, cnt, sizeof(int), hipMemcpyDeviceToHost, P->st));
+          HIPCHK(P, hipStreamSynchronize(P->st));
+          if (nact == 0 || it == P->opt.max_refine) break;
+          P->stats.refine_sweeps++;
+          r = solve_chunk<float>(P, P->W, P->perm, P->Linv, P->Uinv, n, nb, Rb, m, false, P->active.as<int>());
+          if (r != NEP_OK) return r;
+          HIPCHK(P, launch_axpy(Xb, Rb, (long long)n * m, n * m, P->active.as<int>(), nb, P->st));
+        }
+        tmark(P, PH_REFINE, false);
+        if (nact > 0) {
+          // nodes that did not converge: factor again in complex128
+          HIPCHK(P, hipMemcpyAsync(act.data(), P->active.p, sizeof(int) * nb, hipMemcpyDeviceToHost, P->st));
+          HIPCHK(P, hipStreamSynchronize(P->st));
+          nep_status e = ensure_fp64_ws(P, n, 1);
+          if (e != NEP_OK) return e;
+          for (int b = 0; b < nb; ++b) {
+            if (!act[b]) continue;
+            *fallback = true;
+            P->stats.refine_fallbacks++;
+            double2* xb = Xb + (long long)b * n * m;
+            HIPCHK(P, launch_rhs(F, s, V, L, n, xb, (long long)n * m, 1, P->st));
+            e = factor_chunk<double>(P, P->W64, P->ipiv64, P->perm64, P->Linv64, P->Uinv64, P->info64, pd, zb + b, 1);
+            if (e != NEP_OK) return e;
+            e = solve_chunk<double>(P, P->W64, P->perm64, P->Linv64, P->Uinv64, n, 1, xb, m, false, nullptr);
+            if (e != NEP_OK) return e;
+          }
+        }
+      }
+    }
+    li = lj;
+  }
+  P->stats.node_solves += (long long)nl * N;
+  // quadrature sums, profiles, indicators
+  tmark(P, PH_SUMS, true);
+  li = 0;
+  while (li < nl) {
+    const int prob = P->d_prob[sc.disks[li]];
+    int lj = li;
+    while (lj < nl && P->d_prob[sc.disks[lj]] == prob) ++lj;
+    const int n = P->pd[prob].n;
+    HIPCHK(P, launch_sums(X + xoff[li], (long long)n * m, P->dev_w.as<double2>(), P->dev_z.as<double2>(), N, n,
+                          s, L, P->PfN.as<double2>(), P->PfN2.as<double2>(), P->C0.as<double2>(),
+                          P->C1.as<double2>(), P->dlist.as<int>() + li, lj - li, P->dev_soff.as<long long>(),
+                          P->st));
+    if (s > 0 && sc.s == P->opt.s)
+      HIPCHK(P, launch_profile(X + xoff[li], (long long)n * m, N, n, s, m, P->prof.as<double>(),
+                               P->dlist.as<int>() + li, lj - li, P->st));
+    li = lj;
+  }
+  tmark(P, PH_SUMS, false);
+  return NEP_OK;
+}
+
+extern "C" nep_status nep_indicator(nep_plan_t* P, const void* const* F_dev, const void* const* V_dev, double* ind,
+                                    uint8_t* flags, double* profiles) {
+  if (!P) return NEP_ERR_ARG;
+  if (!F_dev || !ind || !flags) return fail(P, NEP_ERR_ARG, "F_dev, ind and flags are required");
+  for (int p = 0; p < P->nprob; ++p)
+    if (!F_dev[p] || (V_dev && P->opt.L > 0 && !V_dev[p])) return fail(P, NEP_ERR_ARG, "null probe block");
+  reset_stats(P);
+  tmark(P, PH_TOTAL, true);
+  SweepCall sc;
+  sc.disks.resize(P->nd);
+  for (int d = 0; d < P->nd; ++d) sc.disks[d] = d;
+  sc.s = P->opt.s;
+  sc.L = (V_dev && P->opt.L > 0) ? P->opt.L : 0;
+  sc.F = F_dev;
+  sc.V = V_dev;
+  bool sing = false, fb = false;
+  nep_status r = run_sweep(P, sc, &sing, &fb);
+  if (r != NEP_OK) return r;
+  HIPCHK(P, launch_indicator(P->PfN.as<double2>(), P->PfN2.as<double2>(), P->dev_dn.as<int>(),
+                             P->dev_soff.as<long long>(), P->opt.s, P->opt.tol_ind, P->ind.as<double>(),
+                             P->flags.as<unsigned char>(), P->sing.as<int>(), P->opt.N, P->nd, P->st));
+  tmark(P, PH_TOTAL, false);
+  HIPCHK(P, hipMemcpyAsync(ind, P->ind.p, sizeof(double) * P->nd * P->opt.s, hipMemcpyDeviceToHost, P->st));
+  HIPCHK(P, hipMemcpyAsync(flags, P->flags.p, P->nd, hipMemcpyDeviceToHost, P->st));
+  if (profiles)
+    HIPCHK(P, hipMemcpyAsync(profiles, P->prof.p, sizeof(double) * P->nd * P->opt.N * P->opt.s,
+                             hipMemcpyDeviceToHost, P->st));
+  HIPCHK(P, hipStreamSynchronize(P->st));
+  finish_stats(P);
+  P->swept = true;
+  P->swept_with_V = sc.L > 0;
+  P->last_F.assign(F_dev, F_dev + P->nprob);
+  {
+    std::vector<int> hs((size_t)P->nd * P->opt.N);
+    HIPCHK(P, hipMemcpy(hs.data(), P->sing.p, sizeof(int) * hs.size(), hipMemcpyDeviceToHost));
+    for (int v : hs) if (v) { sing = true; P->stats.singular_nodes++; }
+  }
+  if (sing) return NEP_WARN_SINGULAR_NODE;   // the disks holding such nodes are flagged
+  return fb ? NEP_WARN_REFINE_FALLBACK : NEP_OK;
+}
+
+// ---------------------------------------------------------------------------- Beyn
+extern "C" nep_status nep_beyn(nep_plan_t* P, const int32_t* disk_ids, int ndisks, const void* const* V_dev,
+                               void* eig, int32_t* p, double* sv, uint8_t* keep, void* eigvec_dev) {
+  if (!P) return NEP_ERR_ARG;
+  if (ndisks < 0 || (ndisks > 0 && (!disk_ids || !eig || !p || !sv))) return fail(P, NEP_ERR_ARG, "null output");
+  const int L = P->opt.L;
+  if (L < 1) return fail(P, NEP_ERR_ARG, "plan has L = 0");
+  if (ndisks == 0) return NEP_OK;
+  for (int i = 0; i < ndisks; ++i)
+    if (disk_ids[i] < 0 || disk_ids[i] >= P->nd) return fail(P, NEP_ERR_ARG, "disk id out of range");
+  reset_stats(P);
+  tmark(P, PH_TOTAL, true);
+  if (V_dev) {
+    // sweep the listed disks again with these probes (moments only; F unchanged)
+    if (!P->swept) return fail(P, NEP_ERR_STATE, "nep_beyn with V needs a previous nep_indicator");
+    SweepCall sc;
+    sc.disks.assign(disk_ids, disk_ids + ndisks);
+    std::sort(sc.disks.begin(), sc.disks.end());
+    sc.disks.erase(std::unique(sc.disks.begin(), sc.disks.end()), sc.disks.end());
+    // F columns are carried along so that the layout of the solve is unchanged
+    sc.s = P->opt.s;
+    sc.L = L;
+    sc.F = P->last_F.empty() ? nullptr : P->last_F.data();
+    sc.V = V_dev;
+    if (!sc.F) return fail(P, NEP_ERR_STATE, "no probe block F from the previous sweep");
+    bool sing = false, fb = false;
+    nep_status r = run_sweep(P, sc, &sing, &fb);
+    if (r != NEP_OK) return r;
+  } else if (!P->swept_with_V) {
+    return fail(P, NEP_ERR_STATE, "no moments: call nep_indicator with V first, or pass V_dev");
+  }
+  HIPCHK(P, P->bscr.alloc(sizeof(double2) * 2ull * ndisks * P->nmax * L));
+  HIPCHK(P, P->beig.alloc(sizeof(double2) * (size_t)ndisks * L));
+  HIPCHK(P, P->bp.alloc(sizeof(int) * ndisks));
+  HIPCHK(P, P->bsv.alloc(sizeof(double) * (size_t)ndisks * L));
+  HIPCHK(P, P->bkeep.alloc((size_t)ndisks * L));
+  HIPCHK(P, P->bstat.alloc(sizeof(int) * ndisks));
+  HIPCHK(P, hipMemsetAsync(P->bstat.p, 0, sizeof(int) * ndisks, P->st));
+  // one launch per problem (region parameters differ)
+  std::vector<int> ids(disk_ids, disk_ids + ndisks);
+  HIPCHK(P, P->dlist.alloc(sizeof(int) * std::max(P->nd, ndisks)));
+  HIPCHK(P, hipMemcpyAsync(P->dlist.p, ids.data(), sizeof(int) * ndisks, hipMemcpyHostToDevice, P->st));
+  int i = 0;
+  while (i < ndisks) {
+    const int prob = P->d_prob[ids[i]];
+    int j = i;
+    while (j < ndisks && P->d_prob[ids[j]] == prob) ++j;
+    BeynArgs a{};
+    a.disk_ids = P->dlist.as<int>() + i;
+    a.dn = P->dev_dn.as<int>();
+    a.soff = P->dev_soff.as<long long>();
+    a.ix = P->dev_ix.as<int>();
+    a.iy = P->dev_iy.as<int>();
+    a.C0 = P->C0.as<double2>();
+    a.C1 = P->C1.as<double2>();
+    a.L = L;
+    a.nmax = P->nmax;
+    a.tol_svd = P->opt.tol_svd;
+    const nep_region& r = P->reg[prob];
+    a.x0 = r.x0; a.x1 = r.x1; a.y0 = r.y0; a.y1 = r.y1; a.nx = r.nx; a.ny = r.ny;
+    a.scratch = P->bscr.as<double2>() + 2ll * i * P->nmax * L;
+    a.eig_out = P->beig.as<double2>() + (long long)i * L;
+    a.p_out = P->bp.as<int>() + i;
+    a.sv_out = P->bsv.as<double>() + (long long)i * L;
+    a.keep_out = P->bkeep.as<unsigned char>() + (long long)i * L;
+    a.eigvec_out = eigvec_dev ? static_cast<double2*>(eigvec_dev) + (long long)i * P->nmax * L : nullptr;
+    a.status = P->bstat.as<int>() + i;
+    if (eigvec_dev && P->pd[prob].n != P->nmax)
+      return fail(P, NEP_ERR_ARG, "eigenvectors requested for problems of different n");
+    HIPCHK(P, launch_beyn(a, j - i, P->st));
+    i = j;
+  }
+  tmark(P, PH_TOTAL, false);
+  HIPCHK(P, hipMemcpyAsync(eig, P->beig.p, sizeof(double2) * (size_t)ndisks * L, hipMemcpyDeviceToHost, P->st));
+  HIPCHK(P, hipMemcpyAsync(p, P->bp.p, sizeof(int) * ndisks, hipMemcpyDeviceToHost, P->st));
+  HIPCHK(P, hipMemcpyAsync(sv, P->bsv.p, sizeof(double) * (size_t)ndisks * L, hipMemcpyDeviceToHost, P->st));
+  if (keep) HIPCHK(P, hipMemcpyAsync(keep, P->bkeep.p, (size_t)ndisks * L, hipMemcpyDeviceToHost, P->st));
+  HIPCHK(P, hipStreamSynchronize(P->st));
+  finish_stats(P);
+  bool sat = false;
+  for (int k = 0; k < ndisks; ++k) sat |= (p[k] == L);
+  return sat ? NEP_WARN_SATURATED : NEP_OK;
+}
+
+// ---------------------------------------------------------------------------- verify
+extern "C" nep_status nep_verify(nep_plan_t* P, const int32_t* prob_ids, const void* lam, int m, double* sigma_min,
+                                 uint8_t* accepted) {
+  if (!P) return NEP_ERR_ARG;
+  if (m < 0 || (m > 0 && (!prob_ids || !lam || !sigma_min || !accepted))) return fail(P, NEP_ERR_ARG, "null argument");
+  for (int i = 0; i < m; ++i)
+    if (prob_ids[i] < 0 || prob_ids[i] >= P->nprob) return fail(P, NEP_ERR_ARG, "problem id out of range");
+  if (m == 0) return NEP_OK;
+  reset_stats(P);
+  tmark(P, PH_TOTAL, true);
+  const double2* lh = static_cast<const double2*>(lam);
+  constexpr int ITERS = 4;
+  for (int prob = 0; prob < P->nprob; ++prob) {
+    std::vector<int> idx;
+    for (int i = 0; i < m; ++i)
+      if (prob_ids[i] == prob) idx.push_back(i);
+    if (idx.empty()) continue;
+    const ProblemDev& pd = P->pd[prob];
+    const int n = pd.n;
+    const int B = std::min<int>((int)idx.size(), choose_batch(n, NEP_FP64, (int)idx.size(), 0));
+    nep_status e = ensure_fp64_ws(P, n, B);
+    if (e != NEP_OK) return e;
+    HIPCHK(P, P->vest.alloc(sizeof(double) * (B + 2) + sizeof(double2) * (size_t)B * n + sizeof(double2) * B));
+    double* est = P->vest.as<double>();
+    double2* xv = reinterpret_cast<double2*>(est + B + (B & 1));
+    double2* zn = xv + (size_t)B * n;
+    for (size_t c0 = 0; c0 < idx.size(); c0 += B) {
+      const int nb = (int)std::min<size_t>(B, idx.size() - c0);
+      std::vector<double2> z(nb);
+      for (int b = 0; b < nb; ++b) z[b] = lh[idx[c0 + b]];
+      HIPCHK(P, hipMemcpyAsync(zn, z.data(), sizeof(double2) * nb, hipMemcpyHostToDevice, P->st));
+      e = factor_chunk<double>(P, P->W64, P->ipiv64, P->perm64, P->Linv64, P->Uinv64, P->info64, pd, zn, nb);
+      if (e != NEP_OK) return e;
+      HIPCHK(P, launch_start(xv, n, n, est, nb, P->st));
+      HIPCHK(P, launch_normalize(xv, n, n, est, 0, nb, P->st));
+      for (int it = 0; it < ITERS; ++it) {
+        e = solve_chunk<double>(P, P->W64, P->perm64, P->Linv64, P->Uinv64, n, nb, xv, 1, true, nullptr);
+        if (e != NEP_OK) return e;
+        HIPCHK(P, launch_normalize(xv, n, n, est, 1, nb, P->st));
+        e = solve_chunk<double>(P, P->W64, P->perm64, P->Linv64, P->Uinv64, n, nb, xv, 1, false, nullptr);
+        if (e != NEP_OK) return e;
+        HIPCHK(P, launch_normalize(xv, n, n, est, 1, nb, P->st));
+      }
+      std::vector<double> hest(nb);
+      std::vector<int> hinf(nb);
+      HIPCHK(P, hipMemcpyAsync(hest.data(), est, sizeof(double) * nb, hipMemcpyDeviceToHost, P->st));
+      HIPCHK(P, hipMemcpyAsync(hinf.data(), P->info64.p, sizeof(int) * nb, hipMemcpyDeviceToHost, P->st));
+      HIPCHK(P, hipStreamSynchronize(P->st));
+      for (int b = 0; b < nb; ++b) {
+        const int i = idx[c0 + b];
+        const double sgm = hinf[b] ? 0.0 : hest[b];
+        sigma_min[i] = sgm;
+        accepted[i] = (sgm < P->opt.tol_ver) ? 1 : 0;
+      }
+    }
+  }
+  tmark(P, PH_TOTAL, false);
+  HIPCHK(P, hipStreamSynchronize(P->st));
+  finish_stats(P);
+  return NEP_OK;
+}
+
+// ---------------------------------------------------------------------------- accessors
+extern "C" nep_status nep_copy_sums(nep_plan_t* P, int first, int count, void* PfN, void* PfN2, void* C0,
+                                   void* C1) {
+  if (!P) return NEP_ERR_ARG;
+  if (first < 0 || count < 0 || first + count > P->nd) return fail(P, NEP_ERR_ARG, "disk range out of bounds");
+  if (count == 0) return NEP_OK;
+  const int n = P->d_n[first];
+  for (int d = first; d < first + count; ++d)
+    if (P->d_n[d] != n) return fail(P, NEP_ERR_ARG, "disks of different n");
+  const long long r0 = P->d_soff[first];
+  const size_t rows = (size_t)count * n;
+  const int s = P->opt.s, L = P->opt.L;
+  if (PfN) HIPCHK(P, hipMemcpy(PfN, P->PfN.as<double2>() + r0 * s, sizeof(double2) * rows * s, hipMemcpyDeviceToHost));
+  if (PfN2) HIPCHK(P, hipMemcpy(PfN2, P->PfN2.as<double2>() + r0 * s, sizeof(double2) * rows * s, hipMemcpyDeviceToHost));
+  if (L > 0 && C0) HIPCHK(P, hipMemcpy(C0, P->C0.as<double2>() + r0 * L, sizeof(double2) * rows * L, hipMemcpyDeviceToHost));
+  if (L > 0 && C1) HIPCHK(P, hipMemcpy(C1, P->C1.as<double2>() + r0 * L, sizeof(double2) * rows * L, hipMemcpyDeviceToHost));
+  return NEP_OK;
+}
+
+extern "C" nep_status nep_dedup(const void* lam, const double* sigma, int m, double rel, uint8_t* keep) {
+  if (m < 0 || (m > 0 && (!lam || !sigma || !keep)) || !(rel >= 0)) return NEP_ERR_ARG;
+  const double2* l = static_cast<const double2*>(lam);
+  std::vector<int> order(m);
+  for (int i = 0; i < m; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return sigma[a] < sigma[b]; });
+  std::vector<int> kept;
+  for (int i = 0; i < m; ++i) keep[i] = 0;
+  for (int i : order) {
+    const double scale = std::max(1.0, std::hypot(l[i].x, l[i].y));
+    bool close = false;
+    for (int k : kept)
+      if (std::hypot(l[i].x - l[k].x, l[i].y - l[k].y) <= rel * scale) { close = true; break; }
+    if (!close) { kept.push_back(i); keep[i] = 1; }
+  }
+  return NEP_OK;
+}
+
+extern "C" int nep_total_disks(const nep_plan_t* P) { return P ? P->nd : 0; }
+extern "C" int nep_disk_offset(const nep_plan_t* P, int problem) {
+  if (!P || problem < 0 || problem >= P->nprob) return -1;
+  return P->disk_first[problem];
+}
+
+extern "C" nep_status nep_get_stats(const nep_plan_t* P, nep_stats* out) {
+  if (!P || !out) return NEP_ERR_ARG;
+  *out = P->stats;
+  return NEP_OK;
+}
+
+extern "C" const char* nep_status_str(int s) {
+  switch (s) {
+    case NEP_OK: return "ok";
+    case NEP_WARN_SINGULAR_NODE: return "warning: singular or non-finite node (disk flagged)";
+    case NEP_WARN_REFINE_FALLBACK: return "warning: refinement fell back to complex128";
+    case NEP_WARN_SATURATED: return "warning: Beyn rank saturated (p == L)";
+    case NEP_ERR_ARG: return "invalid argument";
+    case NEP_ERR_NOMEM: return "out of memory";
+    case NEP_ERR_HIP: return "HIP runtime error";
+    case NEP_ERR_NONFINITE: return "non-finite data";
+    case NEP_ERR_CAPACITY: return "capacity exceeded";
+    case NEP_ERR_STATE: return "call order violated";
+  }
+  return "unknown status";
+}
+
+extern "C" const char* nep_last_error(const nep_plan_t* P) {
+  if (!P) return g_last_create_error.c_str();
+  return P->err.c_str();
+}

@@ -1,0 +1,42 @@
+// Sweep kernels' launchers (see sweep.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include "common.h"
+
+namespace nep {
+
+constexpr int MAX_TERMS = 4;
+enum { PHI_ONE = 0, PHI_Z = 1, PHI_Z2 = 2, PHI_NEG_Z = 3, PHI_EXP_NEG_TAU_Z = 4 };
+
+// Problem descriptor passed by value to kernels.  A[k] == nullptr means A_k = I.
+struct ProblemDev {
+  int n;
+  int nterms;
+  const double2* A[MAX_TERMS];
+  int kind[MAX_TERMS];
+  double param[MAX_TERMS];
+};
+
+template <typename T>
+hipError_t launch_assemble(const ProblemDev& pd, const double2* znode, c2<T>* W, long long mstride, int nbatch,
+                           hipStream_t st);
+hipError_t launch_rhs(const double2* F, int s, const double2* V, int L, int n, double2* X, long long xstride,
+                      int nbatch, hipStream_t st);
+hipError_t launch_sums(const double2* X, long long xstride, const double2* wts, const double2* zn, int N, int n,
+                       int s, int L, double2* PfN, double2* PfN2, double2* C0, double2* C1, const int* disk_ids,
+                       int ndisks, const long long* soff, hipStream_t st);
+hipError_t launch_profile(const double2* X, long long xstride, int N, int n, int s, int m, double* prof,
+                          const int* disk_ids, int ndisks, hipStream_t st);
+hipError_t launch_indicator(const double2* PfN, const double2* PfN2, const int* dn, const long long* soff, int s,
+                            double tol, double* ind, unsigned char* flags, const int* sing, int N, int ndisks,
+                            hipStream_t st);
+hipError_t launch_residual(const ProblemDev& pd, const double2* znode, const double2* X, const double2* F, int s,
+                           const double2* V, int L, long long xstride, int m, int nbatch, double2* R, hipStream_t st);
+hipError_t launch_norms(const double2* R, const double2* X, long long xstride, int len, double* rn2, double* xn2,
+                        int nbatch, hipStream_t st);
+hipError_t launch_axpy(double2* X, const double2* D, long long xstride, int len, const int* active, int nbatch,
+                       hipStream_t st);
+hipError_t launch_coef_norms(const ProblemDev& pd, double* out, hipStream_t st);
+hipError_t launch_mark_singular(const int* info, int nb, int* sing, hipStream_t st);
+
+}  // namespace nep

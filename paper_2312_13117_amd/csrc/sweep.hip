@@ -1,0 +1,381 @@
+// Quadrature sweep kernels around the batched LU:
+//   assemble_kernel   T(z_t) = sum_k phi_k(z_t) A_k for a batch of nodes (eq (2.4)),
+//                     written in the LU's arithmetic (complex128 or complex64)
+//   rhs_kernel        copies [F | V] of each node's problem into its solution slot
+//   sums_kernel       per disk: P f|_N, P f|_{N/2} (1-based even nodes, weight 2 w_j),
+//                     C0 = sum w_j X_j^V, C1 = sum w_j z_j X_j^V (eqs (2.3), (3.2)-(3.3)),
+//                     accumulated in complex128 in node order
+//   profile_kernel    ||x_j[:, q]||_2 per node and probe column
+//   indicator_kernel  I_q = || P f|_N ./ P f|_{N/2} ||_2 / sqrt(n)   (eq (3.1))
+//   residual_kernel   R_t = B_t - T(z_t) X_t in complex128 (mixed-precision refinement)
+#include "common.h"
+#include "sweep.h"
+
+namespace nep {
+
+NEP_DEV double2 phi_eval(int kind, double par, double2 z) {
+  switch (kind) {
+    case PHI_ONE: return cmk<double>(1.0, 0.0);
+    case PHI_Z: return z;
+    case PHI_Z2: return cmul<double>(z, z);
+    case PHI_NEG_Z: return cmk<double>(-z.x, -z.y);
+    case PHI_EXP_NEG_TAU_Z: {
+      const double e = exp(-par * z.x), a = -par * z.y;
+      double s, c;
+      sincos(a, &s, &c);
+      return cmk<double>(e * c, e * s);
+    }
+  }
+  return cmk<double>(0.0, 0.0);
+}
+
+// grid: (ceil(n*n / (256*4)), nbatch); each thread writes 4 consecutive entries.
+template <typename T>
+__global__ __launch_bounds__(256) void assemble_kernel(ProblemDev pd, const double2* __restrict__ znode,
+                                                       c2<T>* __restrict__ W, long long mstride, int nbatch) {
+  const int b = blockIdx.y;
+  if (b >= nbatch) return;
+  const int n = pd.n;
+  const long long nn = (long long)n * n;
+  const double2 z = znode[b];
+  double2 f[MAX_TERMS];
+#pragma unroll
+  for (int k = 0; k < MAX_TERMS; ++k) f[k] = (k < pd.nterms) ? phi_eval(pd.kind[k], pd.param[k], z) : cmk<double>(0, 0);
+  const long long e0 = ((long long)blockIdx.x * 256 + threadIdx.x) * 4;
+  c2<T>* out = W + (long long)b * mstride;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const long long e = e0 + u;
+    if (e >= nn) break;
+    const int i = (int)(e / n), j = (int)(e % n);
+    double2 acc = cmk<double>(0.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < MAX_TERMS; ++k) {
+      if (k >= pd.nterms) break;
+      if (pd.A[k]) acc = cfma<double>(acc, f[k], pd.A[k][e]);
+      else if (i == j) acc = cadd<double>(acc, f[k]);
+    }
+    out[e] = ccast<T, double>(acc);
+  }
+}
+
+// X_t (n x m) = [F | V] of the node's problem; grid (ceil(n*m/256), nbatch)
+__global__ __launch_bounds__(256) void rhs_kernel(const double2* __restrict__ F, int s, const double2* __restrict__ V,
+                                                  int L, int n, double2* __restrict__ X, long long xstride,
+                                                  int nbatch) {
+  const int b = blockIdx.y;
+  if (b >= nbatch) return;
+  const int m = s + L;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= n * m) return;
+  const int i = e / m, q = e % m;
+  X[(long long)b * xstride + e] = (q < s) ? F[(long long)i * s + q] : V[(long long)i * L + (q - s)];
+}
+
+// grid (ceil(n*m/256), ndisks).  Node j of list entry dl has its solution at
+// X + (dl*N + j)*xstride (n x m); dl maps to the global disk disk_ids[dl].  Sums run over j = 1..N in order (fixed rounding order).
+__global__ __launch_bounds__(256) void sums_kernel(const double2* __restrict__ X, long long xstride,
+                                                   const double2* __restrict__ wts, const double2* __restrict__ zn,
+                                                   int N, int n, int s, int L, double2* __restrict__ PfN,
+                                                   double2* __restrict__ PfN2, double2* __restrict__ C0,
+                                                   double2* __restrict__ C1, const int* __restrict__ disk_ids,
+                                                   const long long* __restrict__ soff) {
+  const int dl = blockIdx.y;
+  const int d = disk_ids ? disk_ids[dl] : dl;
+  const int m = s + L;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= n * m) return;
+  const int i = e / m, q = e % m;
+  const double2* w = wts + (long long)d * N;
+  const double2* z = zn + (long long)d * N;
+  const long long t0 = (long long)dl * N;
+  double2 a0 = cmk<double>(0, 0), a1 = cmk<double>(0, 0);
+  for (int j = 0; j < N; ++j) {
+    const double2 x = X[(t0 + j) * xstride + e];
+    if (q < s) {
+      a0 = cfma<double>(a0, w[j], x);
+      if (j & 1) a1 = cfma<double>(a1, cscale<double>(w[j], 2.0), x);   // 1-based even node
+    } else {
+      a0 = cfma<double>(a0, w[j], x);
+      a1 = cfma<double>(a1, cmul<double>(w[j], z[j]), x);
+    }
+  }
+  const long long base = soff[d];
+  if (q < s) {
+    PfN[base * s + (long long)i * s + q] = a0;
+    PfN2[base * s + (long long)i * s + q] = a1;
+  } else if (L > 0) {
+    C0[base * L + (long long)i * L + (q - s)] = a0;
+    C1[base * L + (long long)i * L + (q - s)] = a1;
+  }
+}
+
+// grid (N, ndisks), 256 threads: profile[d][j][q] = ||x_j[:, q]||_2, q < s
+__global__ __launch_bounds__(256) void profile_kernel(const double2* __restrict__ X, long long xstride, int N,
+                                                      int n, int s, int m, double* __restrict__ prof,
+                                                      const int* __restrict__ disk_ids) {
+  const int j = blockIdx.x, dl = blockIdx.y, d = disk_ids[dl];
+  const double2* x = X + ((long long)dl * N + j) * xstride;
+  __shared__ double red[4][8];
+  double acc[8];
+  for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256)
+    for (int q = 0; q < s; ++q) acc[q] += cabs2<double>(x[(long long)i * m + q]);
+  for (int q = 0; q < s; ++q) {
+    const double v = wave_sum(acc[q]);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][q] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < s) {
+    const int q = threadIdx.x;
+    prof[((long long)d * N + j) * s + q] = sqrt(red[0][q] + red[1][q] + red[2][q] + red[3][q]);
+  }
+}
+
+// one workgroup per disk: I_q = ||PfN[:,q] ./ PfN2[:,q]||_2 / sqrt(n); +inf if not finite
+__global__ __launch_bounds__(256) void indicator_kernel(const double2* __restrict__ PfN,
+                                                        const double2* __restrict__ PfN2, const int* __restrict__ dn,
+                                                        const long long* __restrict__ soff, int s, double tol,
+                                                        double* __restrict__ ind, unsigned char* __restrict__ flags,
+                                                        const int* __restrict__ sing, int N) {
+  const int d = blockIdx.x;
+  const int n = dn[d];
+  const double2* a = PfN + soff[d] * s;
+  const double2* b = PfN2 + soff[d] * s;
+  __shared__ double red[4][8];
+  double acc[8];
+  for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256)
+    for (int q = 0; q < s; ++q) {
+      const double2 num = a[(long long)i * s + q], den = b[(long long)i * s + q];
+      // |num / den|^2 = |num|^2 / |den|^2 (0/0 and x/0 give NaN / inf, caught below)
+      acc[q] += cabs2<double>(num) / cabs2<double>(den);
+    }
+  for (int q = 0; q < s; ++q) {
+    const double v = wave_sum(acc[q]);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][q] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    bool flag = false;
+    for (int q = 0; q < s; ++q) {
+      double v = sqrt((red[0][q] + red[1][q] + red[2][q] + red[3][q]) / (double)n);
+      if (!(v <= 1.7976931348623157e308)) v = __builtin_inf();
+      ind[(long long)d * s + q] = v;
+      if (v > tol) flag = true;
+    }
+    if (sing)
+      for (int j = 0; j < N; ++j) flag = flag || sing[(long long)d * N + j] != 0;
+    flags[d] = flag ? 1 : 0;
+  }
+}
+
+// R_t = B_t - sum_k phi_k(z_t) A_k X_t over the batch; grid (row tiles of 64, column
+// tiles of 64 over the concatenated columns of all tasks).  Column c of the product is
+// column c % m of task c / m.  Matrix cores, complex128.
+__global__ __launch_bounds__(256) void residual_kernel(ProblemDev pd, const double2* __restrict__ znode,
+                                                       const double2* __restrict__ X, const double2* __restrict__ F,
+                                                       int s, const double2* __restrict__ V, int L,
+                                                       long long xstride, int m, int nbatch,
+                                                       double2* __restrict__ R) {
+  const int n = pd.n;
+  const int ncol = nbatch * m;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int l16 = lane & 15, kq = lane >> 4;
+  const int rb = blockIdx.x * 64 + (wave >> 1) * 32;
+  const int cb = blockIdx.y * 64 + (wave & 1) * 32;
+  // per-lane columns of the two 16-wide column blocks and their phi weights
+  int ctask[2], cq[2];
+  double2 ph[2][MAX_TERMS];
+#pragma unroll
+  for (int bj = 0; bj < 2; ++bj) {
+    const int c = cb + bj * 16 + l16;
+    ctask[bj] = (c < ncol) ? c / m : -1;
+    cq[bj] = (c < ncol) ? c % m : 0;
+#pragma unroll
+    for (int k = 0; k < MAX_TERMS; ++k)
+      ph[bj][k] = (ctask[bj] >= 0 && k < pd.nterms) ? phi_eval(pd.kind[k], pd.param[k], znode[ctask[bj]])
+                                                    : cmk<double>(0, 0);
+  }
+  d4 cre[2][2], cim[2][2];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) { cre[bi][bj] = acc_zero<double>(); cim[bi][bj] = acc_zero<double>(); }
+#pragma unroll
+  for (int k = 0; k < MAX_TERMS; ++k) {
+    if (k >= pd.nterms) break;
+    const double2* Ak = pd.A[k];
+    if (!Ak) continue;
+    for (int kk = 0; kk < n; kk += 4) {
+      const int j = kk + kq;
+      double2 af[2], bf[2];
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi) {
+        const int row = rb + bi * 16 + l16;
+        af[bi] = (row < n && j < n) ? Ak[(long long)row * n + j] : cmk<double>(0, 0);
+      }
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) {
+        bf[bj] = (ctask[bj] >= 0 && j < n)
+                     ? cmul<double>(ph[bj][k], X[(long long)ctask[bj] * xstride + (long long)j * m + cq[bj]])
+                     : cmk<double>(0, 0);
+      }
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+          cre[bi][bj] = mfma16(af[bi].x, bf[bj].x, cre[bi][bj]);
+          cim[bi][bj] = mfma16(af[bi].x, bf[bj].y, cim[bi][bj]);
+          cre[bi][bj] = mfma16(-af[bi].y, bf[bj].y, cre[bi][bj]);
+          cim[bi][bj] = mfma16(af[bi].y, bf[bj].x, cim[bi][bj]);
+        }
+    }
+  }
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+      if (ctask[bj] < 0) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = rb + bi * 16 + acc_row<double>(lane, r);
+        if (row >= n) continue;
+        const long long off = (long long)ctask[bj] * xstride + (long long)row * m + cq[bj];
+        double2 tx = cmk<double>(cre[bi][bj][r], cim[bi][bj][r]);
+        const double2 x = X[off];
+#pragma unroll
+        for (int k = 0; k < MAX_TERMS; ++k)
+          if (k < pd.nterms && !pd.A[k]) tx = cfma<double>(tx, ph[bj][k], x);   // identity coefficient
+        const int q = cq[bj];
+        const double2 bv = (q < s) ? F[(long long)row * s + q] : V[(long long)row * L + (q - s)];
+        R[off] = csub<double>(bv, tx);
+      }
+    }
+}
+
+// per task: ||R_t||_F^2 and ||X_t||_F^2 (one workgroup per task)
+__global__ __launch_bounds__(256) void norms_kernel(const double2* __restrict__ R, const double2* __restrict__ X,
+                                                    long long xstride, int len, double* __restrict__ rn2,
+                                                    double* __restrict__ xn2) {
+  const int b = blockIdx.x;
+  double a = 0, c = 0;
+  for (int e = threadIdx.x; e < len; e += 256) {
+    a += cabs2<double>(R[(long long)b * xstride + e]);
+    c += cabs2<double>(X[(long long)b * xstride + e]);
+  }
+  __shared__ double ra[4], rc[4];
+  a = wave_sum(a);
+  c = wave_sum(c);
+  if ((threadIdx.x & 63) == 0) { ra[threadIdx.x >> 6] = a; rc[threadIdx.x >> 6] = c; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    rn2[b] = ra[0] + ra[1] + ra[2] + ra[3];
+    xn2[b] = rc[0] + rc[1] + rc[2] + rc[3];
+  }
+}
+
+// X += D for active tasks
+__global__ __launch_bounds__(256) void axpy_kernel(double2* __restrict__ X, const double2* __restrict__ D,
+                                                   long long xstride, int len, const int* __restrict__ active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= len) return;
+  const long long o = (long long)b * xstride + e;
+  X[o] = cadd<double>(X[o], D[o]);
+}
+
+// sing[t0 + b] = info[b] != 0 (exact zero pivot in the factorisation of node b)
+__global__ void mark_singular_kernel(const int* __restrict__ info, int nb, int* __restrict__ sing) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < nb) sing[b] = info[b] != 0 ? 1 : 0;
+}
+
+hipError_t launch_mark_singular(const int* info, int nb, int* sing, hipStream_t st) {
+  mark_singular_kernel<<<(nb + 255) / 256, 256, 0, st>>>(info, nb, sing);
+  return hipGetLastError();
+}
+
+// ||A_k||_F per coefficient (one workgroup per coefficient; identity -> sqrt(n))
+__global__ __launch_bounds__(256) void coef_norm_kernel(ProblemDev pd, double* __restrict__ out) {
+  const int k = blockIdx.x;
+  const int n = pd.n;
+  if (!pd.A[k]) {
+    if (threadIdx.x == 0) out[k] = sqrt((double)n);
+    return;
+  }
+  double a = 0;
+  for (long long e = threadIdx.x; e < (long long)n * n; e += 256) a += cabs2<double>(pd.A[k][e]);
+  __shared__ double ra[4];
+  a = wave_sum(a);
+  if ((threadIdx.x & 63) == 0) ra[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) out[k] = sqrt(ra[0] + ra[1] + ra[2] + ra[3]);
+}
+
+// ----------------------------------------------------------------------------- launchers
+template <typename T>
+hipError_t launch_assemble(const ProblemDev& pd, const double2* znode, c2<T>* W, long long mstride, int nbatch,
+                           hipStream_t st) {
+  const long long nn = (long long)pd.n * pd.n;
+  dim3 grid((unsigned)((nn + 1023) / 1024), (unsigned)nbatch);
+  assemble_kernel<T><<<grid, 256, 0, st>>>(pd, znode, W, mstride, nbatch);
+  return hipGetLastError();
+}
+template hipError_t launch_assemble<double>(const ProblemDev&, const double2*, c2<double>*, long long, int, hipStream_t);
+template hipError_t launch_assemble<float>(const ProblemDev&, const double2*, c2<float>*, long long, int, hipStream_t);
+
+hipError_t launch_rhs(const double2* F, int s, const double2* V, int L, int n, double2* X, long long xstride,
+                      int nbatch, hipStream_t st) {
+  dim3 grid((unsigned)((n * (s + L) + 255) / 256), (unsigned)nbatch);
+  rhs_kernel<<<grid, 256, 0, st>>>(F, s, V, L, n, X, xstride, nbatch);
+  return hipGetLastError();
+}
+
+hipError_t launch_sums(const double2* X, long long xstride, const double2* wts, const double2* zn, int N, int n,
+                       int s, int L, double2* PfN, double2* PfN2, double2* C0, double2* C1, const int* disk_ids,
+                       int ndisks, const long long* soff, hipStream_t st) {
+  dim3 grid((unsigned)((n * (s + L) + 255) / 256), (unsigned)ndisks);
+  sums_kernel<<<grid, 256, 0, st>>>(X, xstride, wts, zn, N, n, s, L, PfN, PfN2, C0, C1, disk_ids, soff);
+  return hipGetLastError();
+}
+
+hipError_t launch_profile(const double2* X, long long xstride, int N, int n, int s, int m, double* prof,
+                          const int* disk_ids, int ndisks, hipStream_t st) {
+  profile_kernel<<<dim3((unsigned)N, (unsigned)ndisks), 256, 0, st>>>(X, xstride, N, n, s, m, prof, disk_ids);
+  return hipGetLastError();
+}
+
+hipError_t launch_indicator(const double2* PfN, const double2* PfN2, const int* dn, const long long* soff, int s,
+                            double tol, double* ind, unsigned char* flags, const int* sing, int N, int ndisks,
+                            hipStream_t st) {
+  indicator_kernel<<<ndisks, 256, 0, st>>>(PfN, PfN2, dn, soff, s, tol, ind, flags, sing, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual(const ProblemDev& pd, const double2* znode, const double2* X, const double2* F, int s,
+                           const double2* V, int L, long long xstride, int m, int nbatch, double2* R, hipStream_t st) {
+  dim3 grid((unsigned)((pd.n + 63) / 64), (unsigned)((nbatch * m + 63) / 64));
+  residual_kernel<<<grid, 256, 0, st>>>(pd, znode, X, F, s, V, L, xstride, m, nbatch, R);
+  return hipGetLastError();
+}
+
+hipError_t launch_norms(const double2* R, const double2* X, long long xstride, int len, double* rn2, double* xn2,
+                        int nbatch, hipStream_t st) {
+  norms_kernel<<<nbatch, 256, 0, st>>>(R, X, xstride, len, rn2, xn2);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy(double2* X, const double2* D, long long xstride, int len, const int* active, int nbatch,
+                       hipStream_t st) {
+  axpy_kernel<<<dim3((unsigned)((len + 255) / 256), (unsigned)nbatch), 256, 0, st>>>(X, D, xstride, len, active);
+  return hipGetLastError();
+}
+
+hipError_t launch_coef_norms(const ProblemDev& pd, double* out, hipStream_t st) {
+  coef_norm_kernel<<<pd.nterms, 256, 0, st>>>(pd, out);
+  return hipGetLastError();
+}
+
+}  // namespace nep

@@ -1,0 +1,292 @@
+"""ctypes binding of libnep.so (include/nep.h).  Argument marshalling only.
+
+Device memory and streams come from PyTorch (torch.cuda tensors, current stream);
+every step of the method runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnep.so")
+
+NEP_OK, NEP_WARN_SINGULAR_NODE, NEP_WARN_REFINE_FALLBACK, NEP_WARN_SATURATED = 0, 1, 2, 3
+NEP_FP64, NEP_FP32_REFINE = 0, 1
+
+
+class nep_problem(C.Structure):
+    _fields_ = [("n", C.c_int), ("nterms", C.c_int), ("A_dev", C.POINTER(C.c_void_p)),
+                ("phi_kind", C.POINTER(C.c_int)), ("phi_param", C.POINTER(C.c_double))]
+
+
+class nep_region(C.Structure):
+    _fields_ = [("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
+                ("nx", C.c_int), ("ny", C.c_int)]
+
+
+class nep_options(C.Structure):
+    _fields_ = [("N", C.c_int), ("s", C.c_int), ("L", C.c_int), ("tol_ind", C.c_double),
+                ("tol_svd", C.c_double), ("tol_ver", C.c_double), ("precision", C.c_int),
+                ("max_refine", C.c_int), ("batch", C.c_int)]
+
+
+class nep_stats(C.Structure):
+    _fields_ = [("node_solves", C.c_int64), ("lu_count", C.c_int64), ("lu_flops", C.c_double),
+                ("refine_sweeps", C.c_int64), ("refine_fallbacks", C.c_int64),
+                ("singular_nodes", C.c_int64), ("ms_total", C.c_double), ("ms_assemble", C.c_double),
+                ("ms_lu", C.c_double), ("ms_solve", C.c_double), ("ms_refine", C.c_double),
+                ("ms_sums", C.c_double), ("ms_gemm", C.c_double), ("gemm_launches", C.c_int64),
+                ("gemm_flops", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libnep.so; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2312_13117_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, ip, dp, u8p = C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(C.c_uint8)
+    L.nep_plan.argtypes = [C.POINTER(nep_problem), C.c_int, C.POINTER(nep_region), C.POINTER(nep_options),
+                           vp, C.POINTER(vp)]
+    L.nep_indicator.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), dp, u8p, dp]
+    L.nep_beyn.argtypes = [vp, ip, C.c_int, C.POINTER(vp), vp, ip, dp, u8p, vp]
+    L.nep_verify.argtypes = [vp, ip, vp, C.c_int, dp, u8p]
+    L.nep_copy_sums.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp, vp]
+    L.nep_dedup.argtypes = [vp, dp, C.c_int, C.c_double, u8p]
+    L.nep_total_disks.argtypes = [vp]
+    L.nep_disk_offset.argtypes = [vp, C.c_int]
+    L.nep_get_stats.argtypes = [vp, C.POINTER(nep_stats)]
+    L.nep_destroy.argtypes = [vp]
+    L.nep_destroy.restype = None
+    L.nep_status_str.argtypes = [C.c_int]
+    L.nep_status_str.restype = C.c_char_p
+    L.nep_last_error.argtypes = [vp]
+    L.nep_last_error.restype = C.c_char_p
+    for f in ("nep_plan", "nep_indicator", "nep_beyn", "nep_verify", "nep_copy_sums", "nep_dedup",
+              "nep_total_disks", "nep_disk_offset", "nep_get_stats"):
+        getattr(L, f).restype = C.c_int
+    _lib = L
+    return L
+
+
+class NepError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+def _check(status: int, plan_handle=None) -> int:
+    if status < 0:
+        L = lib()
+        msg = L.nep_last_error(plan_handle).decode() or L.nep_status_str(status).decode()
+        raise NepError(status, msg)
+    return status
+
+
+def _ptr(a):
+    return C.cast(a.ctypes.data, C.c_void_p) if isinstance(a, np.ndarray) else C.c_void_p(a)
+
+
+def _dev_complex(x, torch):
+    """Host complex array -> contiguous complex128 tensor on cuda:0 (or None)."""
+    if x is None:
+        return None
+    if isinstance(x, torch.Tensor):
+        t = x.to(device="cuda", dtype=torch.complex128)
+    else:
+        t = torch.from_numpy(np.ascontiguousarray(x, dtype=np.complex128)).to("cuda")
+    return t.contiguous()
+
+
+@dataclass
+class Plan:
+    handle: C.c_void_p
+    nprob: int
+    n: List[int]
+    N: int
+    s: int
+    L: int
+    total_disks: int
+    keep_alive: list = field(default_factory=list)
+
+
+def nep_plan(problems, regions, opts, stream=None) -> Plan:
+    """problems: gen.Problem list (coefficients uploaded here to device tensors);
+    regions: gen.Region list; opts: gen.Options (with optional .batch)."""
+    import torch
+    L = lib()
+    keep = []
+    cp = (nep_problem * len(problems))()
+    for i, pr in enumerate(problems):
+        devs = []
+        for A in pr.coeffs:
+            t = _dev_complex(A, torch)
+            keep.append(t)
+            devs.append(t.data_ptr() if t is not None else None)
+        arr = (C.c_void_p * len(devs))(*devs)
+        kinds = (C.c_int * len(devs))(*pr.phi_kind)
+        pars = (C.c_double * len(devs))(*pr.phi_param)
+        keep += [arr, kinds, pars]
+        cp[i] = nep_problem(pr.n, len(devs), arr, kinds, pars)
+    cr = (nep_region * len(regions))()
+    for i, r in enumerate(regions):
+        cr[i] = nep_region(r.x0, r.x1, r.y0, r.y1, r.nx, r.ny)
+    co = nep_options(opts.N, opts.s, opts.L, opts.tol_ind, opts.tol_svd, opts.tol_ver, opts.precision,
+                     opts.max_refine, int(getattr(opts, "batch", 0) or 0))
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    h = C.c_void_p()
+    _check(L.nep_plan(cp, len(problems), cr, C.byref(co), C.c_void_p(stream), C.byref(h)), None)
+    nd = L.nep_total_disks(h)
+    return Plan(h, len(problems), [p.n for p in problems], opts.N, opts.s, opts.L, nd, keep)
+
+
+def _ptr_array(tensors):
+    return (C.c_void_p * len(tensors))(*[t.data_ptr() for t in tensors])
+
+
+def nep_indicator(plan: Plan, F, V=None, want_profiles: bool = False):
+    """F, V: per-problem device complex128 tensors (n x s, n x L), or host arrays.
+    Returns (ind [nd x s], flags [nd] bool, profiles [nd x N x s] or None, status)."""
+    import torch
+    L = lib()
+    Ft = [_dev_complex(f, torch) for f in F]
+    Vt = [_dev_complex(v, torch) for v in V] if V is not None else None
+    plan.keep_alive.append(Ft)            # the plan may re-sweep with F in nep_beyn
+    nd = plan.total_disks
+    ind = np.zeros(nd * plan.s)
+    flags = np.zeros(nd, np.uint8)
+    prof = np.zeros(nd * plan.N * plan.s) if want_profiles else None
+    st = L.nep_indicator(plan.handle, _ptr_array(Ft), _ptr_array(Vt) if Vt is not None else None,
+                         ind.ctypes.data_as(C.POINTER(C.c_double)), flags.ctypes.data_as(C.POINTER(C.c_uint8)),
+                         prof.ctypes.data_as(C.POINTER(C.c_double)) if prof is not None else None)
+    _check(st, plan.handle)
+    return (ind.reshape(nd, plan.s), flags.astype(bool),
+            prof.reshape(nd, plan.N, plan.s) if prof is not None else None, st)
+
+
+def nep_beyn(plan: Plan, disk_ids: Sequence[int], V=None, want_vectors: bool = False):
+    """Returns (eig [k x L] complex, p [k], sv [k x L], keep [k x L] bool, vectors or None, status)."""
+    import torch
+    L = lib()
+    ids = np.ascontiguousarray(np.asarray(disk_ids, dtype=np.int32))
+    k = len(ids)
+    eig = np.zeros(k * plan.L, np.complex128)
+    p = np.zeros(k, np.int32)
+    sv = np.zeros(k * plan.L)
+    keep = np.zeros(k * plan.L, np.uint8)
+    vt = None
+    if want_vectors and k > 0:
+        vt = torch.zeros((k, max(plan.n), plan.L), dtype=torch.complex128, device="cuda")
+    Vt = [_dev_complex(v, torch) for v in V] if V is not None else None
+    st = L.nep_beyn(plan.handle, ids.ctypes.data_as(C.POINTER(C.c_int32)), k,
+                    _ptr_array(Vt) if Vt is not None else None, _ptr(eig),
+                    p.ctypes.data_as(C.POINTER(C.c_int32)), sv.ctypes.data_as(C.POINTER(C.c_double)),
+                    keep.ctypes.data_as(C.POINTER(C.c_uint8)), C.c_void_p(vt.data_ptr()) if vt is not None else None)
+    _check(st, plan.handle)
+    return (eig.reshape(k, plan.L), p, sv.reshape(k, plan.L), keep.reshape(k, plan.L).astype(bool), vt, st)
+
+
+def nep_verify(plan: Plan, prob_ids: Sequence[int], lam: Sequence[complex]):
+    L = lib()
+    m = len(lam)
+    pid = np.ascontiguousarray(np.asarray(prob_ids, dtype=np.int32))
+    la = np.ascontiguousarray(np.asarray(lam, dtype=np.complex128))
+    sig = np.zeros(m)
+    acc = np.zeros(m, np.uint8)
+    st = L.nep_verify(plan.handle, pid.ctypes.data_as(C.POINTER(C.c_int32)), _ptr(la), m,
+                      sig.ctypes.data_as(C.POINTER(C.c_double)), acc.ctypes.data_as(C.POINTER(C.c_uint8)))
+    _check(st, plan.handle)
+    return sig, acc.astype(bool)
+
+
+def nep_copy_sums(plan: Plan, first: int, count: int):
+    L = lib()
+    n = plan.n[0] if plan.nprob == 1 else None
+    if n is None:
+        raise ValueError("nep_copy_sums binding expects a single-problem plan")
+    PfN = np.zeros((count, n, plan.s), np.complex128)
+    PfN2 = np.zeros((count, n, plan.s), np.complex128)
+    C0 = np.zeros((count, n, plan.L), np.complex128) if plan.L else None
+    C1 = np.zeros((count, n, plan.L), np.complex128) if plan.L else None
+    _check(L.nep_copy_sums(plan.handle, first, count, _ptr(PfN), _ptr(PfN2),
+                           _ptr(C0) if C0 is not None else None, _ptr(C1) if C1 is not None else None),
+           plan.handle)
+    return PfN, PfN2, C0, C1
+
+
+def nep_dedup(lam, sigma, rel: float = 1e-8):
+    L = lib()
+    la = np.ascontiguousarray(np.asarray(lam, dtype=np.complex128))
+    sg = np.ascontiguousarray(np.asarray(sigma, dtype=np.float64))
+    keep = np.zeros(len(la), np.uint8)
+    _check(L.nep_dedup(_ptr(la), sg.ctypes.data_as(C.POINTER(C.c_double)), len(la), rel,
+                       keep.ctypes.data_as(C.POINTER(C.c_uint8))))
+    return keep.astype(bool)
+
+
+def nep_get_stats(plan: Plan) -> dict:
+    L = lib()
+    s = nep_stats()
+    _check(L.nep_get_stats(plan.handle, C.byref(s)), plan.handle)
+    return {f: getattr(s, f) for f, _ in nep_stats._fields_}
+
+
+def nep_destroy(plan: Plan) -> None:
+    if plan.handle:
+        lib().nep_destroy(plan.handle)
+        plan.handle = C.c_void_p()
+
+
+@dataclass
+class Result:
+    ind: np.ndarray
+    flags: np.ndarray
+    flagged: np.ndarray
+    eig: np.ndarray
+    p: np.ndarray
+    sv: np.ndarray
+    keep: np.ndarray
+    cand_disk: np.ndarray
+    cand: np.ndarray
+    sigma: np.ndarray
+    accepted: np.ndarray
+    eigs: np.ndarray
+    status: dict
+
+
+def pmcimb(plan: Plan, F, V, disk_problem=None) -> Result:
+    """The three steps in order: indicators (and moments) -> Beyn on flagged disks ->
+    sigma_min verification of the kept candidates -> merge of duplicates."""
+    ind, flags, _, st1 = nep_indicator(plan, F, V)
+    flagged = np.nonzero(flags)[0]
+    eig, p, sv, keep, _, st2 = nep_beyn(plan, flagged) if len(flagged) else (
+        np.zeros((0, plan.L), np.complex128), np.zeros(0, np.int32), np.zeros((0, plan.L)),
+        np.zeros((0, plan.L), bool), None, 0)
+    cd, cl = [], []
+    for i, d in enumerate(flagged):
+        for k in range(int(p[i])):
+            if keep[i, k]:
+                cd.append(d)
+                cl.append(eig[i, k])
+    cd = np.asarray(cd, dtype=np.int64)
+    cl = np.asarray(cl, dtype=np.complex128)
+    if disk_problem is None:
+        disk_problem = np.zeros(plan.total_disks, np.int32)
+    sig, acc = nep_verify(plan, disk_problem[cd] if len(cd) else [], cl) if len(cl) else (np.zeros(0), np.zeros(0, bool))
+    al, asg = cl[acc], sig[acc]
+    kd = nep_dedup(al, asg) if len(al) else np.zeros(0, bool)
+    eigs = al[kd]
+    order = np.lexsort((eigs.imag, eigs.real))
+    return Result(ind, flags, flagged, eig, p, sv, keep, cd, cl, sig, acc, eigs[order],
+                  {"indicator": st1, "beyn": st2})
