@@ -186,9 +186,10 @@ nep_status nep_indicator(nep_plan_t* plan, const void* const* F_dev, const void*
  *   p          host int32 [ndisks]
  *   sv         host double [ndisks * L]: singular values of C0, descending
  *   keep       host uint8 [ndisks * L] or NULL: 1 iff eigenvalue k of disk i lies in the
- *              cell that owns it (strict inside test; a value within 1e-9 max(1,|l|) of
+ *              cell that owns it (strict inside test; a value within 1e-6 max(1,|l|) of
  *              an edge shared by two cells belongs to the neighbour with the smaller
- *              index, a value on the outer boundary of Omega to its only cell)
+ *              index, a value on the outer boundary of Omega to its only cell; the band
+ *              exceeds the quadrature error of eigenvalues that lie on cell edges)
  *   eigvec_dev NULL or device complex128 [ndisks * n * L]: eigenvectors U_0 s_k (unit
  *              2-norm, column k of the n x L block of disk i; problems of one call must
  *              then share n)

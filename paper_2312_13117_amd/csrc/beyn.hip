@@ -359,7 +359,7 @@ __global__ __launch_bounds__(BT) void beyn_kernel(BeynArgs a) {
     unsigned char keep = 0;
     if (t < p) {
       lam = Hm[t][t];
-      const double band = 1e-9 * fmax(1.0, cabsd(lam));
+      const double band = 1e-6 * fmax(1.0, cabsd(lam));
       const int ox = owner_axis(lam.x, a.x0, a.x1, a.nx, band);
       const int oy = owner_axis(lam.y, a.y0, a.y1, a.ny, band);
       keep = (ox == a.ix[d] && oy == a.iy[d]) ? 1 : 0;

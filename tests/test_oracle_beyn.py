@@ -140,7 +140,8 @@ def test_owner_cell_edges():
     assert oracle.owner_cell(0.3 + 0.3j, reg) == (2, 2)
     assert oracle.owner_cell(0.0 + 0.3j, reg) == (1, 2)      # on x = 0: the smaller neighbour
     assert oracle.owner_cell(1e-13 + 0.3j, reg) == (1, 2)    # inside the tie band
-    assert oracle.owner_cell(1e-6 + 0.3j, reg) == (2, 2)     # outside the band
+    assert oracle.owner_cell(5e-7 + 0.3j, reg) == (1, 2)     # inside the 1e-6 band
+    assert oracle.owner_cell(1e-5 + 0.3j, reg) == (2, 2)     # outside the band
     assert oracle.owner_cell(-2.0 - 2.0j, reg) == (0, 0)      # closed region corner
     assert oracle.owner_cell(2.0 + 2.0j, reg) == (3, 3)
     assert oracle.owner_cell(2.1 + 0j, reg) is None
