@@ -19,6 +19,114 @@
 
 namespace nep {
 
+
+// ----------------------------------------------------------------------------- small inverses
+// In-place inverses of the nbk x nbk diagonal blocks held in LDS (M[i][j]), blocked in
+// 8 x 8 tiles: the diagonal tiles are inverted by substitution (one thread per column),
+// then each block row is formed from the rows above it (two small products, two
+// barriers per block row).
+constexpr int TB = 8;
+
+// unit lower: strict lower part of M holds L on entry and inv(L) on exit
+template <typename T, int NB, int NT>
+__device__ void inv_unit_lower(c2<T> (*M)[NB + 1], c2<T> (*S)[NB], int nbk) {
+  const int t = threadIdx.x;
+  const int nblk = (nbk + TB - 1) / TB;
+  c2<T> x[TB];
+  const int col = t;            // one thread per column for the diagonal tiles
+  const bool act = col < nbk;
+  const int b0 = (col / TB) * TB, b1 = min(b0 + TB, nbk);
+  if (act) {
+#pragma unroll
+    for (int u = 0; u < TB; ++u) x[u] = czero<T>();
+    for (int i = col + 1; i < b1; ++i) {
+      c2<T> v = M[i][col];
+      for (int l = col + 1; l < i; ++l) v = cfma<T>(v, M[i][l], x[l - b0]);
+      x[i - b0] = cmk<T>(-v.x, -v.y);
+    }
+  }
+  __syncthreads();
+  if (act)
+    for (int i = col + 1; i < b1; ++i) M[i][col] = x[i - b0];
+  __syncthreads();
+  for (int I = 1; I < nblk; ++I) {
+    const int r0 = I * TB, r1 = min(r0 + TB, nbk), nr = r1 - r0, nc = r0;
+    // S[i][j] = sum_{l = j..r0-1} L[i][l] X[l][j]   (X unit lower, already inverted)
+    for (int e = t; e < nr * nc; e += NT) {
+      const int i = r0 + e / nc, j = e % nc;
+      c2<T> v = M[i][j];                       // l = j term (X[j][j] = 1)
+      for (int l = j + 1; l < r0; ++l) v = cfma<T>(v, M[i][l], M[l][j]);
+      S[i - r0][j] = v;
+    }
+    __syncthreads();
+    // X[i][j] = -(S[i][j] + sum_{r0 <= l < i} X_II[i][l] S[l][j])
+    c2<T> out[(TB * NB + NT - 1) / NT];
+    int q = 0;
+    for (int e = t; e < nr * nc; e += NT, ++q) {
+      const int i = r0 + e / nc, j = e % nc;
+      c2<T> v = S[i - r0][j];
+      for (int l = r0; l < i; ++l) v = cfma<T>(v, M[i][l], S[l - r0][j]);
+      out[q] = cmk<T>(-v.x, -v.y);
+    }
+    __syncthreads();
+    q = 0;
+    for (int e = t; e < nr * nc; e += NT, ++q) M[r0 + e / nc][e % nc] = out[q];
+    __syncthreads();
+  }
+}
+
+// upper (non-unit): upper part of M holds U on entry and inv(U) on exit
+template <typename T, int NB, int NT>
+__device__ void inv_upper(c2<T> (*M)[NB + 1], c2<T> (*S)[NB], int nbk) {
+  const int t = threadIdx.x;
+  const int nblk = (nbk + TB - 1) / TB;
+  c2<T> x[TB];
+  const int col = t;
+  const bool act = col < nbk;
+  const int b0 = (col / TB) * TB;
+  if (act) {
+#pragma unroll
+    for (int u = 0; u < TB; ++u) x[u] = czero<T>();
+    const c2<T> d = M[col][col];
+    x[col - b0] = (d.x != T(0) || d.y != T(0)) ? crcp<T>(d) : czero<T>();
+    for (int i = col - 1; i >= b0; --i) {
+      c2<T> v = czero<T>();
+      for (int l = i + 1; l <= col; ++l) v = cfma<T>(v, M[i][l], x[l - b0]);
+      const c2<T> di = M[i][i];
+      const c2<T> rd = (di.x != T(0) || di.y != T(0)) ? crcp<T>(di) : czero<T>();
+      x[i - b0] = cmul<T>(cmk<T>(-v.x, -v.y), rd);
+    }
+  }
+  __syncthreads();
+  if (act)
+    for (int i = b0; i <= col; ++i) M[i][col] = x[i - b0];
+  __syncthreads();
+  for (int I = nblk - 2; I >= 0; --I) {
+    const int r0 = I * TB, r1 = r0 + TB, c0 = r1, nc = nbk - c0;
+    // S[i][j] = sum_{l = r1..j} U[i][l] X[l][j]   (j >= r1, X upper already inverted)
+    for (int e = t; e < TB * nc; e += NT) {
+      const int i = r0 + e / nc, j = c0 + e % nc;
+      c2<T> v = czero<T>();
+      for (int l = r1; l <= j; ++l) v = cfma<T>(v, M[i][l], M[l][j]);
+      S[i - r0][j] = v;
+    }
+    __syncthreads();
+    // X[i][j] = -sum_{i <= l < r1} X_II[i][l] S[l][j]
+    c2<T> out[(TB * NB + NT - 1) / NT];
+    int q = 0;
+    for (int e = t; e < TB * nc; e += NT, ++q) {
+      const int i = r0 + e / nc, j = c0 + e % nc;
+      c2<T> v = czero<T>();
+      for (int l = i; l < r1; ++l) v = cfma<T>(v, M[i][l], S[l - r0][j]);
+      out[q] = cmk<T>(-v.x, -v.y);
+    }
+    __syncthreads();
+    q = 0;
+    for (int e = t; e < TB * nc; e += NT, ++q) M[r0 + e / nc][c0 + e % nc] = out[q];
+    __syncthreads();
+  }
+}
+
 // ----------------------------------------------------------------------------- panel
 // One workgroup of NT threads per matrix.  Row r >= k0 belongs to thread (r-k0) % NT,
 // slot (r-k0) / NT, so n - k0 <= NT * RPT.
@@ -46,6 +154,9 @@ __global__ __launch_bounds__(NT) void lu_panel_kernel(c2<T>* __restrict__ W, lon
   __shared__ int s_pos[2 * NB], s_src[2 * NB];
   __shared__ int s_cnt;
   __shared__ c2<T> Mtri[NB][NB + 1];
+  __shared__ c2<T> Stmp[TB][NB];
+  __shared__ int s_ipos[2 * IB], s_isrc[2 * IB];
+  __shared__ int s_icnt;
 
   c2<T> a[RPT][IB];
   for (int c0 = k0; c0 < k0 + nbk; c0 += IB) {
@@ -57,7 +168,9 @@ __global__ __launch_bounds__(NT) void lu_panel_kernel(c2<T>* __restrict__ W, lon
       for (int jj = 0; jj < IB; ++jj)
         a[q][jj] = (r >= c0 && r < n && jj < ib) ? A[(long long)r * n + c0 + jj] : czero<T>();
     }
-    for (int jj = 0; jj < ib; ++jj) {
+#pragma unroll
+    for (int jj = 0; jj < IB; ++jj) {
+      if (jj >= ib) break;
       const int c = c0 + jj;
       // ---- pivot search: max |re|+|im| over rows r >= c, first index on ties
       T bv = T(-1);
@@ -158,22 +271,52 @@ __global__ __launch_bounds__(NT) void lu_panel_kernel(c2<T>* __restrict__ W, lon
           if (u < ib) A[(long long)r * n + c0 + u] = a[q][u];
     }
     __syncthreads();
-    // ---- the inner block's row exchanges on the other panel columns
+    // ---- the inner block's row exchanges on the other panel columns, as one compact
+    //      permutation (new row s_ipos[i] = old row s_isrc[i]): one gather and one
+    //      scatter per column instead of a chain of dependent swaps
+    if (t == 0) {
+      int cnt = ib;
+      for (int i = 0; i < ib; ++i) { s_ipos[i] = c0 + i; s_isrc[i] = c0 + i; }
+      for (int i = 0; i < ib; ++i) {
+        const int p = s_ipiv[c0 + i - k0];
+        if (p == c0 + i) continue;
+        int ip = -1;
+        if (p < c0 + ib) ip = p - c0;
+        else {
+          for (int j = ib; j < cnt; ++j)
+            if (s_ipos[j] == p) { ip = j; break; }
+          if (ip < 0) { ip = cnt; s_ipos[cnt] = p; s_isrc[cnt] = p; ++cnt; }
+        }
+        const int x = s_isrc[i]; s_isrc[i] = s_isrc[ip]; s_isrc[ip] = x;
+      }
+      s_icnt = cnt;
+    }
+    __syncthreads();
     {
-      const int nleft = c0 - k0, nother = nbk - ib;
-      for (int e = t; e < nother; e += NT) {
-        const int col = (e < nleft) ? k0 + e : c0 + ib + (e - nleft);
-        for (int u = 0; u < ib; ++u) {
-          const int c = c0 + u, p = s_ipiv[c - k0];
-          if (p != c) {
-            const c2<T> x = A[(long long)c * n + col];
-            A[(long long)c * n + col] = A[(long long)p * n + col];
-            A[(long long)p * n + col] = x;
-          }
+      const int nleft = c0 - k0, nother = nbk - ib, cnt = s_icnt;
+      constexpr int GQ = (2 * IB * NB + NT - 1) / NT;
+      c2<T> g[GQ];
+#pragma unroll
+      for (int q = 0; q < GQ; ++q) {
+        const int e = t + q * NT;
+        g[q] = czero<T>();
+        if (e < nother * cnt) {
+          const int ee = e % nother, i = e / nother;
+          const int col = (ee < nleft) ? k0 + ee : c0 + ib + (ee - nleft);
+          g[q] = A[(long long)s_isrc[i] * n + col];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < GQ; ++q) {
+        const int e = t + q * NT;
+        if (e < nother * cnt) {
+          const int ee = e % nother, i = e / nother;
+          const int col = (ee < nleft) ? k0 + ee : c0 + ib + (ee - nleft);
+          A[(long long)s_ipos[i] * n + col] = g[q];
         }
       }
     }
-    __syncthreads();
     // ---- right part of the panel: U rows of this block, then the rank-ib update
     const int cr0 = c0 + ib, nr = k0 + nbk - cr0;
     if (nr > 0) {
@@ -185,32 +328,66 @@ __global__ __launch_bounds__(NT) void lu_panel_kernel(c2<T>* __restrict__ W, lon
           for (int u = 0; u < IB; ++u) Lb[r - c0][u] = a[q][u];
       }
       __syncthreads();
+      // U rows of this block: unit-lower substitution with Lb, in halves of 8 rows so
+      // that every register array stays statically indexed
       for (int e = t; e < nr; e += NT) {
-        c2<T> x[IB];
+        constexpr int H = (IB > 8) ? 8 : IB;
+        c2<T> x[H], y[H];
 #pragma unroll
-        for (int i = 0; i < IB; ++i) x[i] = (i < ib) ? A[(long long)(c0 + i) * n + cr0 + e] : czero<T>();
+        for (int i = 0; i < H; ++i) x[i] = (i < ib) ? A[(long long)(c0 + i) * n + cr0 + e] : czero<T>();
 #pragma unroll
-        for (int i = 1; i < IB; ++i)
+        for (int i = 0; i < H; ++i) y[i] = (H + i < ib && IB > H) ? A[(long long)(c0 + H + i) * n + cr0 + e] : czero<T>();
 #pragma unroll
-          for (int j = 0; j < IB; ++j)
+        for (int i = 1; i < H; ++i)
+#pragma unroll
+          for (int j = 0; j < H; ++j)
             if (j < i) x[i] = cfms<T>(x[i], Lb[i][j], x[j]);
+        if (IB > H) {
 #pragma unroll
-        for (int i = 0; i < IB; ++i)
+          for (int i = 0; i < H; ++i)
+#pragma unroll
+            for (int j = 0; j < H; ++j) y[i] = cfms<T>(y[i], Lb[(H + i) & (IB - 1)][j], x[j]);
+#pragma unroll
+          for (int i = 1; i < H; ++i)
+#pragma unroll
+            for (int j = 0; j < H; ++j)
+              if (j < i) y[i] = cfms<T>(y[i], Lb[(H + i) & (IB - 1)][(H + j) & (IB - 1)], y[j]);
+        }
+#pragma unroll
+        for (int i = 0; i < H; ++i)
           if (i < ib) { A[(long long)(c0 + i) * n + cr0 + e] = x[i]; Ub[i][e] = x[i]; }
+#pragma unroll
+        for (int i = 0; i < H; ++i)
+          if (IB > H && H + i < ib) {
+            A[(long long)(c0 + H + i) * n + cr0 + e] = y[i];
+            Ub[(H + i) & (IB - 1)][e] = y[i];
+          }
       }
       __syncthreads();
+      // chunks of 8 columns; all of a thread's rows load together before any store
+      for (int e0 = 0; e0 < nr; e0 += 8) {
+        c2<T> acc[RPT][8];
 #pragma unroll
-      for (int q = 0; q < RPT; ++q) {
-        const int r = k0 + t + q * NT;
-        if (r >= cr0 && r < n) {
-          c2<T>* row = A + (long long)r * n + cr0;
-          for (int e = 0; e < nr; ++e) {
-            c2<T> acc = row[e];
+        for (int q = 0; q < RPT; ++q) {
+          const int r = k0 + t + q * NT;
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            acc[q][u] = (r >= cr0 && r < n && e0 + u < nr) ? A[(long long)r * n + cr0 + e0 + u] : czero<T>();
+        }
+#pragma unroll
+        for (int q = 0; q < RPT; ++q)
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
 #pragma unroll
             for (int i = 0; i < IB; ++i)
-              if (i < ib) acc = cfms<T>(acc, a[q][i], Ub[i][e]);
-            row[e] = acc;
-          }
+              if (i < ib) acc[q][u] = cfms<T>(acc[q][u], a[q][i], Ub[i][(e0 + u) & (NB - 1)]);
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+          const int r = k0 + t + q * NT;
+          if (r >= cr0 && r < n)
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+              if (e0 + u < nr) A[(long long)r * n + cr0 + e0 + u] = acc[q][u];
         }
       }
       __syncthreads();
@@ -247,8 +424,7 @@ __global__ __launch_bounds__(NT) void lu_panel_kernel(c2<T>* __restrict__ W, lon
     if (t == 0) P[0] = s_cnt;
   }
 
-  // ---- inverse of the unit lower diagonal block L11 (column sweep from the right:
-  //      column j of inv(L) = -inv(L)[j+1:, j+1:] * L[j+1:, j], one sync per column)
+  // ---- inverses of the diagonal blocks L11 (unit lower) and U11 (upper)
   c2<T>* Li = Linv + (long long)b * inv_stride + (long long)step * NB * NB;
   c2<T>* Ui = Uinv + (long long)b * inv_stride + (long long)step * NB * NB;
   for (int e = t; e < nbk * nbk; e += NT) {
@@ -256,19 +432,7 @@ __global__ __launch_bounds__(NT) void lu_panel_kernel(c2<T>* __restrict__ W, lon
     Mtri[i][j] = A[(long long)(k0 + i) * n + k0 + j];
   }
   __syncthreads();
-  for (int j = nbk - 2; j >= 0; --j) {
-    // rows i > j: new M[i][j] = -(L[i][j] + sum_{j<l<i} X[i][l] L[l][j]),  X = current inv
-    c2<T> v = czero<T>();
-    const int i = j + 1 + t;
-    if (t < nbk - 1 - j) {
-      v = Mtri[i][j];
-      for (int l = j + 1; l < i; ++l) v = cfma<T>(v, Mtri[i][l], Mtri[l][j]);
-      v = cmk<T>(-v.x, -v.y);
-    }
-    __syncthreads();
-    if (t < nbk - 1 - j) Mtri[i][j] = v;
-    __syncthreads();
-  }
+  inv_unit_lower<T, NB, NT>(Mtri, Stmp, nbk);
   for (int e = t; e < NB * NB; e += NT) {
     const int i = e / NB, j = e % NB;
     c2<T> v = czero<T>();
@@ -276,27 +440,12 @@ __global__ __launch_bounds__(NT) void lu_panel_kernel(c2<T>* __restrict__ W, lon
     Li[e] = v;
   }
   __syncthreads();
-  // ---- inverse of the upper diagonal block U11 (row sweep from the bottom:
-  //      row i of inv(U) = -inv(U_ii) * U[i, i+1:] * inv(U)[i+1:, i+1:])
   for (int e = t; e < nbk * nbk; e += NT) {
     const int i = e / nbk, j = e % nbk;
     Mtri[i][j] = A[(long long)(k0 + i) * n + k0 + j];
   }
   __syncthreads();
-  for (int i = nbk - 1; i >= 0; --i) {
-    const c2<T> d = Mtri[i][i];
-    const c2<T> rd = (d.x != T(0) || d.y != T(0)) ? crcp<T>(d) : cmk<T>(T(0), T(0));
-    c2<T> v = czero<T>();
-    const int j = i + 1 + t;
-    if (t < nbk - 1 - i) {
-      for (int l = i + 1; l <= j; ++l) v = cfma<T>(v, Mtri[i][l], Mtri[l][j]);
-      v = cmul<T>(cmk<T>(-v.x, -v.y), rd);
-    }
-    __syncthreads();
-    if (t < nbk - 1 - i) Mtri[i][j] = v;
-    if (t == 0) Mtri[i][i] = rd;
-    __syncthreads();
-  }
+  inv_upper<T, NB, NT>(Mtri, Stmp, nbk);
   for (int e = t; e < NB * NB; e += NT) {
     const int i = e / NB, j = e % NB;
     c2<T> v = czero<T>();
@@ -345,6 +494,9 @@ __global__ __launch_bounds__(256) void lu_gemm_kernel(c2<T>* __restrict__ W, lon
     Li = Linv + (long long)b * inv_stride + (long long)step * NBMAX * NBMAX;
   }
 
+  // C tile (update mode) fetched up front; the product accumulates from zero and is
+  // subtracted at the end, so the C loads overlap the matrix-core work.
+  c2<T> cv[2][2][4];
   acc4<T> cre[2][2], cim[2][2];
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
@@ -352,17 +504,11 @@ __global__ __launch_bounds__(256) void lu_gemm_kernel(c2<T>* __restrict__ W, lon
     for (int bj = 0; bj < 2; ++bj) {
       cre[bi][bj] = acc_zero<T>();
       cim[bi][bj] = acc_zero<T>();
-      if (MODE == GEMM_UPDATE) {
-        const int col = cb + bj * 16 + l16;
+      const int col = cb + bj * 16 + l16;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = rb + bi * 16 + acc_row<T>(lane, r);
-          if (row < n && col < n) {
-            const c2<T> v = A[(long long)row * n + col];
-            cre[bi][bj][r] = v.x;
-            cim[bi][bj][r] = v.y;
-          }
-        }
+      for (int r = 0; r < 4; ++r) {
+        const int row = rb + bi * 16 + acc_row<T>(lane, r);
+        cv[bi][bj][r] = (MODE == GEMM_UPDATE && row < n && col < n) ? A[(long long)row * n + col] : czero<T>();
       }
     }
 
@@ -380,9 +526,8 @@ __global__ __launch_bounds__(256) void lu_gemm_kernel(c2<T>* __restrict__ W, lon
     }
   }
 
-  for (int kk = 0; kk < nbk; kk += 4) {
+  auto load_frags = [&](int kk, c2<T>* af, c2<T>* bf) {
     const int k = kk + kq;
-    c2<T> af[2], bf[2];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi) {
       const int row = rb + bi * 16 + l16;
@@ -401,22 +546,28 @@ __global__ __launch_bounds__(256) void lu_gemm_kernel(c2<T>* __restrict__ W, lon
         bf[bj] = czero<T>();
       }
     }
+  };
+  c2<T> af[2], bf[2], an[2], bn[2];
+  load_frags(0, af, bf);
+  for (int kk = 0; kk < nbk; kk += 4) {
+    if (kk + 4 < nbk) load_frags(kk + 4, an, bn);
+    // real parts of A first, then imaginary parts: dependent products 8 apart
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
       for (int bj = 0; bj < 2; ++bj) {
-        if (MODE == GEMM_UPDATE) {   // C -= A B
-          cre[bi][bj] = mfma16(-af[bi].x, bf[bj].x, cre[bi][bj]);
-          cim[bi][bj] = mfma16(-af[bi].x, bf[bj].y, cim[bi][bj]);
-          cre[bi][bj] = mfma16(af[bi].y, bf[bj].y, cre[bi][bj]);
-          cim[bi][bj] = mfma16(-af[bi].y, bf[bj].x, cim[bi][bj]);
-        } else {                     // C = A B
-          cre[bi][bj] = mfma16(af[bi].x, bf[bj].x, cre[bi][bj]);
-          cim[bi][bj] = mfma16(af[bi].x, bf[bj].y, cim[bi][bj]);
-          cre[bi][bj] = mfma16(-af[bi].y, bf[bj].y, cre[bi][bj]);
-          cim[bi][bj] = mfma16(af[bi].y, bf[bj].x, cim[bi][bj]);
-        }
+        cre[bi][bj] = mfma16(af[bi].x, bf[bj].x, cre[bi][bj]);
+        cim[bi][bj] = mfma16(af[bi].x, bf[bj].y, cim[bi][bj]);
       }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) {
+        cre[bi][bj] = mfma16(-af[bi].y, bf[bj].y, cre[bi][bj]);
+        cim[bi][bj] = mfma16(af[bi].y, bf[bj].x, cim[bi][bj]);
+      }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) { af[u] = an[u]; bf[u] = bn[u]; }
   }
   if (MODE == GEMM_TRSM) __syncthreads();   // every wave has read its operands
 
@@ -428,7 +579,12 @@ __global__ __launch_bounds__(256) void lu_gemm_kernel(c2<T>* __restrict__ W, lon
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = rb + bi * 16 + acc_row<T>(lane, r);
-        if (row < rlim && col < n) A[(long long)row * n + col] = cmk<T>(cre[bi][bj][r], cim[bi][bj][r]);
+        if (row < rlim && col < n) {
+          const c2<T> o = (MODE == GEMM_UPDATE)
+                              ? cmk<T>(cv[bi][bj][r].x - cre[bi][bj][r], cv[bi][bj][r].y - cim[bi][bj][r])
+                              : cmk<T>(cre[bi][bj][r], cim[bi][bj][r]);
+          A[(long long)row * n + col] = o;
+        }
       }
     }
   if (MODE == GEMM_TRSM) {
@@ -442,27 +598,64 @@ __global__ __launch_bounds__(256) void lu_gemm_kernel(c2<T>* __restrict__ W, lon
 }
 
 // ----------------------------------------------------------------------------- solves
-// One workgroup per matrix; the right-hand side block X (n x m, complex128, row-major)
-// is solved in place in the factor's arithmetic T.  TRANS = false: A x = b;
-// TRANS = true: A^H x = b.
+// One workgroup of 256 threads per matrix; the right-hand sides X (n x m, m <= 32,
+// complex128, row-major) are solved in place in the factor's arithmetic T.
+// Every block product runs as a 64 x m tile (thread t owns rows 2(t/8)+{0,1} and
+// columns t%8 + 8{0..3}) over operand chunks staged in LDS.
+template <typename T>
+struct SolveTile {
+  static constexpr int MMAX = 32, KC = 32;
+  c2<T> acc[2][4];
+  int r0, cb;
+  __device__ SolveTile() {
+    r0 = 2 * (threadIdx.x >> 3);
+    cb = threadIdx.x & 7;
+  }
+  __device__ void zero() {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = czero<T>();
+  }
+  // acc (+|-)= Ash[r][0:kc] * Bsh[kbase + 0:kc][c]
+  template <bool SUB>
+  __device__ void mma(const c2<T> (*Ash)[KC + 1], const c2<T> (*Bsh)[MMAX], int kbase, int kc) {
+    for (int k = 0; k < kc; ++k) {
+      const c2<T> a0 = Ash[r0][k], a1 = Ash[r0 + 1][k];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const c2<T> bv = Bsh[kbase + k][cb + 8 * j];
+        if (SUB) {
+          acc[0][j] = cfms<T>(acc[0][j], a0, bv);
+          acc[1][j] = cfms<T>(acc[1][j], a1, bv);
+        } else {
+          acc[0][j] = cfma<T>(acc[0][j], a0, bv);
+          acc[1][j] = cfma<T>(acc[1][j], a1, bv);
+        }
+      }
+    }
+  }
+};
+
 template <typename T, int NB, bool TRANS>
 __global__ __launch_bounds__(256) void lu_solve_kernel(const c2<T>* __restrict__ W, long long mstride, int n,
                                                        const int* __restrict__ perm, long long perm_stride,
                                                        const c2<T>* __restrict__ Linv, const c2<T>* __restrict__ Uinv,
                                                        long long inv_stride, double2* __restrict__ X,
                                                        long long xstride, int m, const int* __restrict__ active) {
-  constexpr int MMAX = 32;
+  constexpr int MMAX = 32, KC = SolveTile<T>::KC;
   const int b = blockIdx.x;
   if (active && !active[b]) return;
   const int t = threadIdx.x;
   const c2<T>* A = W + (long long)b * mstride;
   double2* Xb = X + (long long)b * xstride;
   const int nsteps = (n + NB - 1) / NB;
-  __shared__ c2<T> Y[NB][MMAX];
-  __shared__ c2<T> Z[NB][MMAX];
+  __shared__ c2<T> Ash[NB][KC + 1];
+  __shared__ c2<T> Bsh[NB][MMAX];
   __shared__ int s_pos[2 * NB], s_src[2 * NB];
   __shared__ int s_cnt;
   constexpr int GMAX = (2 * NB * MMAX + 255) / 256;
+  SolveTile<T> tile;
 
   auto load_perm = [&](int s) {
     const int* P = perm + (long long)b * perm_stride + (long long)s * (1 + 4 * NB);
@@ -490,59 +683,111 @@ __global__ __launch_bounds__(256) void lu_solve_kernel(const c2<T>* __restrict__
     }
     __syncthreads();
   };
+  // stage rows [r0, r0+nr) x cols [c0, c0+kc) of a row-major matrix (leading dim ld) into Ash
+  auto stage_A = [&](const c2<T>* src, long long ld, int nr, int kc) {
+    for (int e = t; e < NB * KC; e += 256) {
+      const int i = e / KC, k = e % KC;
+      Ash[i][k] = (i < nr && k < kc) ? src[(long long)i * ld + k] : czero<T>();
+    }
+  };
+  // stage rows of X (complex128) into Bsh rows [dst0, dst0+nr)
+  auto stage_X = [&](int xrow0, int nr, int dst0) {
+    for (int e = t; e < nr * MMAX; e += 256) {
+      const int i = e / MMAX, c = e % MMAX;
+      Bsh[dst0 + i][c] = (c < m) ? ccast<T, double>(Xb[(long long)(xrow0 + i) * m + c]) : czero<T>();
+    }
+  };
+  auto load_acc_X = [&](int xrow0, int nr) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = tile.r0 + i, c = tile.cb + 8 * j;
+        tile.acc[i][j] = (r < nr && c < m) ? ccast<T, double>(Xb[(long long)(xrow0 + r) * m + c]) : czero<T>();
+      }
+  };
+  auto store_acc_X = [&](int xrow0, int nr) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = tile.r0 + i, c = tile.cb + 8 * j;
+        if (r < nr && c < m) Xb[(long long)(xrow0 + r) * m + c] = ccast<double, T>(tile.acc[i][j]);
+      }
+  };
+  auto store_acc_B = [&]() {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) Bsh[tile.r0 + i][tile.cb + 8 * j] = tile.acc[i][j];
+  };
 
   if (!TRANS) {
-    // forward: for each step, exchange rows, y = inv(L11) x_top, x_rest -= L21 y
+    // forward: exchange rows, y = inv(L11) x_top, x_rest -= L21 y
     for (int s = 0; s < nsteps; ++s) {
       const int k0 = s * NB, nbk = min(NB, n - k0), kend = k0 + nbk;
       load_perm(s);
       permute(false);
-      for (int e = t; e < nbk * m; e += 256) Z[e / m][e % m] = ccast<T, double>(Xb[(long long)(k0 + e / m) * m + e % m]);
-      __syncthreads();
+      stage_X(k0, nbk, 0);
+      for (int i = nbk + t / MMAX; i < NB; i += 256 / MMAX) Bsh[i][t % MMAX] = czero<T>();
       const c2<T>* Li = Linv + (long long)b * inv_stride + (long long)s * NB * NB;
-      for (int e = t; e < nbk * m; e += 256) {
-        const int i = e / m, c = e % m;
-        c2<T> acc = czero<T>();
-        for (int j = 0; j <= i; ++j) acc = cfma<T>(acc, Li[i * NB + j], Z[j][c]);
-        Y[i][c] = acc;
-        Xb[(long long)(k0 + i) * m + c] = ccast<double, T>(acc);
+      tile.zero();
+      for (int kc = 0; kc < nbk; kc += KC) {
+        __syncthreads();
+        stage_A(Li + kc, NB, nbk, min(KC, nbk - kc));
+        __syncthreads();
+        tile.template mma<false>(Ash, Bsh, kc, min(KC, nbk - kc));
       }
       __syncthreads();
-      for (int e = t; e < (n - kend) * m; e += 256) {
-        const int r = kend + e / m, c = e % m;
-        const c2<T>* Lr = A + (long long)r * n + k0;
-        c2<T> acc = ccast<T, double>(Xb[(long long)r * m + c]);
-        for (int j = 0; j < nbk; ++j) acc = cfms<T>(acc, Lr[j], Y[j][c]);
-        Xb[(long long)r * m + c] = ccast<double, T>(acc);
+      store_acc_B();                       // y for the trailing rows
+      store_acc_X(k0, nbk);
+      __syncthreads();
+      for (int r = kend; r < n; r += NB) {
+        const int nr = min(NB, n - r);
+        load_acc_X(r, nr);
+        for (int kc = 0; kc < nbk; kc += KC) {
+          __syncthreads();
+          stage_A(A + (long long)r * n + k0 + kc, n, nr, min(KC, nbk - kc));
+          __syncthreads();
+          tile.template mma<true>(Ash, Bsh, kc, min(KC, nbk - kc));
+        }
+        store_acc_X(r, nr);
       }
       __syncthreads();
     }
     // backward: x_top = inv(U11) (x_top - U12 x_rest)
     for (int s = nsteps - 1; s >= 0; --s) {
       const int k0 = s * NB, nbk = min(NB, n - k0), kend = k0 + nbk;
-      for (int e = t; e < nbk * m; e += 256) {
-        const int i = e / m, c = e % m;
-        const c2<T>* Ur = A + (long long)(k0 + i) * n;
-        c2<T> acc = ccast<T, double>(Xb[(long long)(k0 + i) * m + c]);
-        for (int j = kend; j < n; ++j) acc = cfms<T>(acc, Ur[j], ccast<T, double>(Xb[(long long)j * m + c]));
-        Z[i][c] = acc;
+      load_acc_X(k0, nbk);
+      for (int kc = kend; kc < n; kc += KC) {
+        const int kk = min(KC, n - kc);
+        __syncthreads();
+        stage_A(A + (long long)k0 * n + kc, n, nbk, kk);
+        stage_X(kc, kk, 0);
+        for (int i = kk + t / MMAX; i < KC; i += 256 / MMAX) Bsh[i][t % MMAX] = czero<T>();
+        __syncthreads();
+        tile.template mma<true>(Ash, Bsh, 0, kk);
       }
       __syncthreads();
+      store_acc_B();                       // z
+      for (int i = nbk + t / MMAX; i < NB; i += 256 / MMAX) Bsh[i][t % MMAX] = czero<T>();
       const c2<T>* Ui = Uinv + (long long)b * inv_stride + (long long)s * NB * NB;
-      for (int e = t; e < nbk * m; e += 256) {
-        const int i = e / m, c = e % m;
-        c2<T> acc = czero<T>();
-        for (int j = i; j < nbk; ++j) acc = cfma<T>(acc, Ui[i * NB + j], Z[j][c]);
-        Xb[(long long)(k0 + i) * m + c] = ccast<double, T>(acc);
+      tile.zero();
+      for (int kc = 0; kc < nbk; kc += KC) {
+        __syncthreads();
+        stage_A(Ui + kc, NB, nbk, min(KC, nbk - kc));
+        __syncthreads();
+        tile.template mma<false>(Ash, Bsh, kc, min(KC, nbk - kc));
       }
+      store_acc_X(k0, nbk);
       __syncthreads();
     }
   } else {
     // A = P_0^T L_0 ... P_{S-1}^T L_{S-1} U  =>  A^H x = b:  w = U^{-H} b, then for
     // s = S-1..0: w_blk = inv(L11)^H (w_blk - L21^H w_rest), w = P_s^T w.
+    __shared__ c2<T> Z[NB][MMAX];
     for (int s = 0; s < nsteps; ++s) {   // U^H is lower triangular: forward over steps
       const int k0 = s * NB, nbk = min(NB, n - k0);
-      // z_blk = b_blk - sum_{j < k0} U[j, blk]^H w_j
       for (int e = t; e < nbk * m; e += 256) {
         const int i = e / m, c = e % m;
         c2<T> acc = ccast<T, double>(Xb[(long long)(k0 + i) * m + c]);
@@ -589,24 +834,21 @@ __global__ __launch_bounds__(256) void lu_solve_kernel(const c2<T>* __restrict__
 
 // ----------------------------------------------------------------------------- launchers
 template <typename T>
-static int panel_threads(int n) { return n <= 1024 ? 256 : (n <= 2048 ? 512 : 1024); }
-
-template <typename T>
 hipError_t lu_factor_batch(c2<T>* W, long long mstride, int n, int nbatch, int* ipiv, int* perm,
                            long long perm_stride, c2<T>* Linv, c2<T>* Uinv, long long inv_stride, int* info,
                            hipStream_t st, LuTimers* tm) {
-  constexpr int NB = LU_NB, IB = 8, RPT = 4;
+  constexpr int NB = LU_NB, IB = 8;
   if (n > 4096 || n < 1) return hipErrorInvalidValue;
   const int nsteps = (n + NB - 1) / NB;
   for (int s = 0; s < nsteps; ++s) {
     const int k0 = s * NB, nbk = min(NB, n - k0), m = n - k0 - nbk;
-    const int nt = panel_threads<T>(n);
-    if (nt == 256)
-      lu_panel_kernel<T, NB, IB, 256, RPT><<<nbatch, 256, 0, st>>>(W, mstride, n, k0, s, ipiv, perm, perm_stride, Linv, Uinv, inv_stride, info);
-    else if (nt == 512)
-      lu_panel_kernel<T, NB, IB, 512, RPT><<<nbatch, 512, 0, st>>>(W, mstride, n, k0, s, ipiv, perm, perm_stride, Linv, Uinv, inv_stride, info);
+    // panel rows n - k0 <= threads * rows-per-thread
+    if (n <= 1024)
+      lu_panel_kernel<T, NB, IB, 512, 2><<<nbatch, 512, 0, st>>>(W, mstride, n, k0, s, ipiv, perm, perm_stride, Linv, Uinv, inv_stride, info);
+    else if (n <= 2048)
+      lu_panel_kernel<T, NB, IB, 1024, 2><<<nbatch, 1024, 0, st>>>(W, mstride, n, k0, s, ipiv, perm, perm_stride, Linv, Uinv, inv_stride, info);
     else
-      lu_panel_kernel<T, NB, IB, 1024, RPT><<<nbatch, 1024, 0, st>>>(W, mstride, n, k0, s, ipiv, perm, perm_stride, Linv, Uinv, inv_stride, info);
+      lu_panel_kernel<T, NB, IB, 1024, 4><<<nbatch, 1024, 0, st>>>(W, mstride, n, k0, s, ipiv, perm, perm_stride, Linv, Uinv, inv_stride, info);
     if (m <= 0) continue;
     const int tc = (m + 63) / 64;
     const long long groups = (nbatch + 7) / 8;

@@ -60,6 +60,22 @@ struct PhaseTimer {
 
 enum { PH_ASM = 0, PH_LU = 1, PH_SOLVE = 2, PH_REFINE = 3, PH_SUMS = 4, PH_TOTAL = 5 };
 
+// Factorisation workspace bound to one stream.  The sweep alternates batches over two
+// of them so that one batch's latency-bound panel steps share the GPU with the other
+// batch's matrix-core updates.
+struct Workspace {
+  hipStream_t st = 0;
+  bool own = false;
+  DevBuf W, ipiv, perm, Linv, Uinv, info, R, rn2, xn2, active, counter;
+  void release() {
+    DevBuf* b[] = {&W, &ipiv, &perm, &Linv, &Uinv, &info, &R, &rn2, &xn2, &active, &counter};
+    for (DevBuf* x : b) x->release();
+    if (own && st) hipStreamDestroy(st);
+    st = 0;
+    own = false;
+  }
+};
+
 }  // namespace
 
 struct nep_plan {
@@ -81,11 +97,12 @@ struct nep_plan {
   // device copies
   DevBuf dev_dn, dev_ix, dev_iy, dev_soff, dev_w, dev_z;
   DevBuf PfN, PfN2, C0, C1, prof, ind, flags;
-  DevBuf X, R, xoff, tnode, dlist;
-  // LU workspaces
-  DevBuf W, ipiv, perm, Linv, Uinv, info;
-  DevBuf W64, ipiv64, perm64, Linv64, Uinv64, info64;
-  DevBuf rn2, xn2, active, coefn, counter, sing;
+  DevBuf X, xoff, tnode, dlist;
+  // LU workspaces: two for the sweep (own streams), one complex128 on the plan stream
+  Workspace ws[2];
+  Workspace w64;
+  hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
+  DevBuf coefn, sing;
   DevBuf bscr, beig, bp, bsv, bkeep, bstat, bvec;
   DevBuf vest;
   int batch = 0;
@@ -132,9 +149,9 @@ static int choose_batch(int n, int precision, int ntask_max, int requested) {
   return std::max(1, std::min(b, std::max(1, ntask_max)));
 }
 
-static void tmark(nep_plan_t* p, int phase, bool start) {
+static void tmark(nep_plan_t* p, int phase, bool start, hipStream_t st) {
   hipEvent_t e = p->timer.get();
-  hipEventRecord(e, p->st);
+  hipEventRecord(e, st);
   int idx = p->timer.used - 1;
   if (start) p->timer.marks[phase].push_back({idx, -1});
   else if (!p->timer.marks[phase].empty()) p->timer.marks[phase].back().second = idx;
@@ -288,7 +305,6 @@ extern "C" nep_status nep_plan(const nep_problem* probs, int nprob, const nep_re
   PCHK(P->dlist.alloc(sizeof(int) * nd));
   PCHK(P->tnode.alloc(sizeof(double2) * (size_t)nd * N));
   PCHK(P->sing.alloc(sizeof(int) * (size_t)nd * N));
-  PCHK(P->counter.alloc(sizeof(int) * 4));
   // factor workspace
   int ntask_max = 0;
   for (int p = 0; p < nprob; ++p) ntask_max = std::max(ntask_max, (regs[p].nx * regs[p].ny) * N);
@@ -296,18 +312,28 @@ extern "C" nep_status nep_plan(const nep_problem* probs, int nprob, const nep_re
   const int B = P->batch, nm = P->nmax;
   const int steps = (nm + LU_NB - 1) / LU_NB;
   const size_t eb = elem_bytes(o.precision);
-  PCHK(P->W.alloc(eb * (size_t)B * nm * nm));
-  PCHK(P->ipiv.alloc(sizeof(int) * (size_t)B * nm));
-  PCHK(P->perm.alloc(sizeof(int) * (size_t)B * steps * perm_ints_per_step()));
-  PCHK(P->Linv.alloc(eb * (size_t)B * steps * LU_NB * LU_NB));
-  PCHK(P->Uinv.alloc(eb * (size_t)B * steps * LU_NB * LU_NB));
-  PCHK(P->info.alloc(sizeof(int) * B));
-  if (o.precision == NEP_FP32_REFINE) {
-    PCHK(P->R.alloc(sizeof(double2) * (size_t)B * nm * m));
-    PCHK(P->rn2.alloc(sizeof(double) * B));
-    PCHK(P->xn2.alloc(sizeof(double) * B));
-    PCHK(P->active.alloc(sizeof(int) * B));
+  for (int k = 0; k < 2; ++k) {
+    Workspace& w = P->ws[k];
+    PCHK(hipStreamCreateWithFlags(&w.st, hipStreamNonBlocking));
+    w.own = true;
+    PCHK(w.W.alloc(eb * (size_t)B * nm * nm));
+    PCHK(w.ipiv.alloc(sizeof(int) * (size_t)B * nm));
+    PCHK(w.perm.alloc(sizeof(int) * (size_t)B * steps * perm_ints_per_step()));
+    PCHK(w.Linv.alloc(eb * (size_t)B * steps * LU_NB * LU_NB));
+    PCHK(w.Uinv.alloc(eb * (size_t)B * steps * LU_NB * LU_NB));
+    PCHK(w.info.alloc(sizeof(int) * B));
+    PCHK(w.counter.alloc(sizeof(int) * 4));
+    if (o.precision == NEP_FP32_REFINE) {
+      PCHK(w.R.alloc(sizeof(double2) * (size_t)B * nm * m));
+      PCHK(w.rn2.alloc(sizeof(double) * B));
+      PCHK(w.xn2.alloc(sizeof(double) * B));
+      PCHK(w.active.alloc(sizeof(int) * B));
+    }
   }
+  P->w64.st = P->st;
+  PCHK(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming));
+  PCHK(hipEventCreateWithFlags(&P->ev_join[0], hipEventDisableTiming));
+  PCHK(hipEventCreateWithFlags(&P->ev_join[1], hipEventDisableTiming));
   PCHK(P->coefn.alloc(sizeof(double) * MAX_TERMS * nprob));
   for (int p = 0; p < nprob; ++p)
     PCHK(launch_coef_norms(P->pd[p], P->coefn.as<double>() + MAX_TERMS * p, P->st));
@@ -324,12 +350,17 @@ extern "C" nep_status nep_plan(const nep_problem* probs, int nprob, const nep_re
 extern "C" void nep_destroy(nep_plan_t* P) {
   if (!P) return;
   hipStreamSynchronize(P->st);
+  for (auto& w : P->ws) if (w.st) hipStreamSynchronize(w.st);
   DevBuf* bufs[] = {&P->dev_dn, &P->dev_ix, &P->dev_iy, &P->dev_soff, &P->dev_w, &P->dev_z, &P->PfN, &P->PfN2,
-                    &P->C0, &P->C1, &P->prof, &P->ind, &P->flags, &P->X, &P->R, &P->xoff, &P->tnode, &P->dlist,
-                    &P->W, &P->ipiv, &P->perm, &P->Linv, &P->Uinv, &P->info, &P->W64, &P->ipiv64, &P->perm64,
-                    &P->Linv64, &P->Uinv64, &P->info64, &P->rn2, &P->xn2, &P->active, &P->coefn, &P->counter, &P->sing, &P->bscr,
-                    &P->beig, &P->bp, &P->bsv, &P->bkeep, &P->bstat, &P->bvec, &P->vest};
+                    &P->C0, &P->C1, &P->prof, &P->ind, &P->flags, &P->X, &P->xoff, &P->tnode, &P->dlist,
+                    &P->coefn, &P->sing, &P->bscr, &P->beig, &P->bp, &P->bsv, &P->bkeep, &P->bstat, &P->bvec,
+                    &P->vest};
   for (DevBuf* b : bufs) b->release();
+  for (auto& w : P->ws) w.release();
+  P->w64.own = false;
+  P->w64.release();
+  if (P->ev_fork) hipEventDestroy(P->ev_fork);
+  for (auto& e : P->ev_join) if (e) hipEventDestroy(e);
   for (auto& e : P->gemm_ev) if (e) hipEventDestroy(e);
   for (auto& e : P->timer.pool) hipEventDestroy(e);
   delete P;
@@ -372,48 +403,120 @@ struct SweepCall {
 };
 
 template <typename T>
-static nep_status factor_chunk(nep_plan_t* P, DevBuf& W, DevBuf& ipv, DevBuf& prm, DevBuf& Li, DevBuf& Ui,
-                               DevBuf& inf, const ProblemDev& pd, const double2* znode, int nb) {
+static nep_status factor_chunk(nep_plan_t* P, Workspace& w, const ProblemDev& pd, const double2* znode, int nb) {
   const int n = pd.n;
   const int steps = (n + LU_NB - 1) / LU_NB;
   const long long mstride = (long long)n * n;
   const long long pstride = (long long)steps * perm_ints_per_step();
   const long long istride = (long long)steps * LU_NB * LU_NB;
-  tmark(P, PH_ASM, true);
-  HIPCHK(P, launch_assemble<T>(pd, znode, W.as<c2<T>>(), mstride, nb, P->st));
-  tmark(P, PH_ASM, false);
-  HIPCHK(P, hipMemsetAsync(inf.p, 0, sizeof(int) * nb, P->st));
-  tmark(P, PH_LU, true);
-  HIPCHK(P, lu_factor_batch<T>(W.as<c2<T>>(), mstride, n, nb, ipv.as<int>(), prm.as<int>(), pstride,
-                               Li.as<c2<T>>(), Ui.as<c2<T>>(), istride, inf.as<int>(), P->st, &P->lut));
-  tmark(P, PH_LU, false);
+  tmark(P, PH_ASM, true, w.st);
+  HIPCHK(P, launch_assemble<T>(pd, znode, w.W.as<c2<T>>(), mstride, nb, w.st));
+  tmark(P, PH_ASM, false, w.st);
+  HIPCHK(P, hipMemsetAsync(w.info.p, 0, sizeof(int) * nb, w.st));
+  tmark(P, PH_LU, true, w.st);
+  HIPCHK(P, lu_factor_batch<T>(w.W.as<c2<T>>(), mstride, n, nb, w.ipiv.as<int>(), w.perm.as<int>(), pstride,
+                               w.Linv.as<c2<T>>(), w.Uinv.as<c2<T>>(), istride, w.info.as<int>(), w.st, &P->lut));
+  tmark(P, PH_LU, false, w.st);
   P->stats.lu_count += nb;
   P->stats.lu_flops += 8.0 / 3.0 * (double)n * n * n * nb;
   return NEP_OK;
 }
 
 template <typename T>
-static nep_status solve_chunk(nep_plan_t* P, DevBuf& W, DevBuf& prm, DevBuf& Li, DevBuf& Ui, int n, int nb,
-                              double2* X, int m, bool trans, const int* active) {
+static nep_status solve_chunk(nep_plan_t* P, Workspace& w, int n, int nb, double2* X, int m, bool trans,
+                              const int* active) {
   const int steps = (n + LU_NB - 1) / LU_NB;
-  HIPCHK(P, lu_solve_batch<T>(W.as<c2<T>>(), (long long)n * n, n, nb, prm.as<int>(),
-                              (long long)steps * perm_ints_per_step(), Li.as<c2<T>>(), Ui.as<c2<T>>(),
-                              (long long)steps * LU_NB * LU_NB, X, (long long)n * m, m, trans, active, P->st));
+  HIPCHK(P, lu_solve_batch<T>(w.W.as<c2<T>>(), (long long)n * n, n, nb, w.perm.as<int>(),
+                              (long long)steps * perm_ints_per_step(), w.Linv.as<c2<T>>(), w.Uinv.as<c2<T>>(),
+                              (long long)steps * LU_NB * LU_NB, X, (long long)n * m, m, trans, active, w.st));
   return NEP_OK;
 }
 
 static nep_status ensure_fp64_ws(nep_plan_t* P, int n, int B) {
   const int steps = (n + LU_NB - 1) / LU_NB;
-  HIPCHK(P, P->W64.alloc(16ull * B * n * n));
-  HIPCHK(P, P->ipiv64.alloc(sizeof(int) * (size_t)B * n));
-  HIPCHK(P, P->perm64.alloc(sizeof(int) * (size_t)B * steps * perm_ints_per_step()));
-  HIPCHK(P, P->Linv64.alloc(16ull * B * steps * LU_NB * LU_NB));
-  HIPCHK(P, P->Uinv64.alloc(16ull * B * steps * LU_NB * LU_NB));
-  HIPCHK(P, P->info64.alloc(sizeof(int) * B));
+  Workspace& w = P->w64;
+  HIPCHK(P, w.W.alloc(16ull * B * n * n));
+  HIPCHK(P, w.ipiv.alloc(sizeof(int) * (size_t)B * n));
+  HIPCHK(P, w.perm.alloc(sizeof(int) * (size_t)B * steps * perm_ints_per_step()));
+  HIPCHK(P, w.Linv.alloc(16ull * B * steps * LU_NB * LU_NB));
+  HIPCHK(P, w.Uinv.alloc(16ull * B * steps * LU_NB * LU_NB));
+  HIPCHK(P, w.info.alloc(sizeof(int) * B));
+  return NEP_OK;
+}
+
+// One batch of node systems: assemble, factor, solve, refine (mixed precision).
+static nep_status sweep_batch(nep_plan_t* P, Workspace& w, int prob, const double2* zb, double2* Xb, int nb,
+                              const SweepCall& sc, int* sing_out, bool* fallback) {
+  const ProblemDev& pd = P->pd[prob];
+  const int n = pd.n, s = sc.s, L = sc.L, m = s + L;
+  const double2* F = static_cast<const double2*>(sc.F[prob]);
+  const double2* V = (L > 0) ? static_cast<const double2*>(sc.V[prob]) : nullptr;
+  HIPCHK(P, launch_rhs(F, s, V, L, n, Xb, (long long)n * m, nb, w.st));
+  if (P->opt.precision != NEP_FP32_REFINE) {
+    nep_status r = factor_chunk<double>(P, w, pd, zb, nb);
+    if (r != NEP_OK) return r;
+    HIPCHK(P, launch_mark_singular(w.info.as<int>(), nb, sing_out, w.st));
+    tmark(P, PH_SOLVE, true, w.st);
+    r = solve_chunk<double>(P, w, n, nb, Xb, m, false, nullptr);
+    tmark(P, PH_SOLVE, false, w.st);
+    return r;
+  }
+  nep_status r = factor_chunk<float>(P, w, pd, zb, nb);
+  if (r != NEP_OK) return r;
+  tmark(P, PH_SOLVE, true, w.st);
+  r = solve_chunk<float>(P, w, n, nb, Xb, m, false, nullptr);
+  tmark(P, PH_SOLVE, false, w.st);
+  if (r != NEP_OK) return r;
+  // complex128 residual refinement: R = B - T X; X += LU32 \ R until the backward
+  // error ||R|| <= 2^-52 sqrt(n) ||T|| ||X|| holds for every node of the batch
+  const double eps = std::ldexp(1.0, -52) * std::sqrt((double)n);
+  double2* Rb = w.R.as<double2>();
+  tmark(P, PH_REFINE, true, w.st);
+  int nact = nb;
+  for (int it = 0; it <= P->opt.max_refine; ++it) {
+    HIPCHK(P, launch_residual(pd, zb, Xb, F, s, V, L, (long long)n * m, m, nb, Rb, w.st));
+    HIPCHK(P, launch_norms(Rb, Xb, (long long)n * m, n * m, w.rn2.as<double>(), w.xn2.as<double>(), nb, w.st));
+    int* cnt = w.counter.as<int>();
+    HIPCHK(P, hipMemsetAsync(cnt, 0, sizeof(int), w.st));
+    converge_kernel<<<(nb + 255) / 256, 256, 0, w.st>>>(pd, zb, P->coefn.as<double>() + MAX_TERMS * prob,
+                                                         w.rn2.as<double>(), w.xn2.as<double>(), eps,
+                                                         w.active.as<int>(), nb, cnt);
+    HIPCHK(P, hipGetLastError());
+    HIPCHK(P, hipMemcpyAsync(&nact, cnt, sizeof(int), hipMemcpyDeviceToHost, w.st));
+    HIPCHK(P, hipStreamSynchronize(w.st));
+    if (nact == 0 || it == P->opt.max_refine) break;
+    P->stats.refine_sweeps++;
+    r = solve_chunk<float>(P, w, n, nb, Rb, m, false, w.active.as<int>());
+    if (r != NEP_OK) return r;
+    HIPCHK(P, launch_axpy(Xb, Rb, (long long)n * m, n * m, w.active.as<int>(), nb, w.st));
+  }
+  tmark(P, PH_REFINE, false, w.st);
+  if (nact > 0) {
+    // nodes that did not converge: factor again in complex128 (plan stream, after
+    // this batch's stream has finished with them)
+    std::vector<int> act(nb);
+    HIPCHK(P, hipMemcpyAsync(act.data(), w.active.p, sizeof(int) * nb, hipMemcpyDeviceToHost, w.st));
+    HIPCHK(P, hipStreamSynchronize(w.st));
+    nep_status e = ensure_fp64_ws(P, n, 1);
+    if (e != NEP_OK) return e;
+    for (int b = 0; b < nb; ++b) {
+      if (!act[b]) continue;
+      *fallback = true;
+      P->stats.refine_fallbacks++;
+      double2* xb = Xb + (long long)b * n * m;
+      HIPCHK(P, launch_rhs(F, s, V, L, n, xb, (long long)n * m, 1, P->w64.st));
+      e = factor_chunk<double>(P, P->w64, pd, zb + b, 1);
+      if (e != NEP_OK) return e;
+      e = solve_chunk<double>(P, P->w64, n, 1, xb, m, false, nullptr);
+      if (e != NEP_OK) return e;
+    }
+    HIPCHK(P, hipStreamSynchronize(P->w64.st));
+  }
   return NEP_OK;
 }
 
 static nep_status run_sweep(nep_plan_t* P, const SweepCall& sc, bool* singular, bool* fallback) {
+  (void)singular;
   const int N = P->opt.N, s = sc.s, L = sc.L, m = s + L;
   const int nl = (int)sc.disks.size();
   // layout of this call's solutions: entry li, node j at xoff[li] + j*n*m
@@ -432,90 +535,36 @@ static nep_status run_sweep(nep_plan_t* P, const SweepCall& sc, bool* singular, 
   HIPCHK(P, hipMemcpyAsync(P->xoff.p, xoff.data(), sizeof(long long) * nl, hipMemcpyHostToDevice, P->st));
   HIPCHK(P, hipMemcpyAsync(P->tnode.p, nodes.data(), sizeof(double2) * nodes.size(), hipMemcpyHostToDevice, P->st));
   HIPCHK(P, hipMemcpyAsync(P->dlist.p, sc.disks.data(), sizeof(int) * nl, hipMemcpyHostToDevice, P->st));
+  // fork: both worker streams start after the uploads above
+  HIPCHK(P, hipEventRecord(P->ev_fork, P->st));
+  for (auto& w : P->ws) HIPCHK(P, hipStreamWaitEvent(w.st, P->ev_fork, 0));
   double2* X = P->X.as<double2>();
   const double2* tn = P->tnode.as<double2>();
-  const bool mixed = P->opt.precision == NEP_FP32_REFINE;
-  // runs of consecutive list entries of one problem
+  int k = 0;   // batch counter: batches alternate between the two workspaces
   int li = 0;
   while (li < nl) {
     const int prob = P->d_prob[sc.disks[li]];
     int lj = li;
     while (lj < nl && P->d_prob[sc.disks[lj]] == prob) ++lj;
-    const ProblemDev& pd = P->pd[prob];
-    const int n = pd.n;
-    const double2* F = static_cast<const double2*>(sc.F[prob]);
-    const double2* V = (L > 0) ? static_cast<const double2*>(sc.V[prob]) : nullptr;
+    const int n = P->pd[prob].n;
     const long long ntask = (long long)(lj - li) * N;
-    for (long long t0 = 0; t0 < ntask; t0 += P->batch) {
+    for (long long t0 = 0; t0 < ntask; t0 += P->batch, ++k) {
       const int nb = (int)std::min<long long>(P->batch, ntask - t0);
-      const double2* zb = tn + (long long)li * N + t0;
-      double2* Xb = X + xoff[li] + t0 * (long long)n * m;
-      HIPCHK(P, launch_rhs(F, s, V, L, n, Xb, (long long)n * m, nb, P->st));
-      if (!mixed) {
-        nep_status r = factor_chunk<double>(P, P->W, P->ipiv, P->perm, P->Linv, P->Uinv, P->info, pd, zb, nb);
-        if (r != NEP_OK) return r;
-        HIPCHK(P, launch_mark_singular(P->info.as<int>(), nb, P->sing.as<int>() + (long long)li * N + t0, P->st));
-        tmark(P, PH_SOLVE, true);
-        r = solve_chunk<double>(P, P->W, P->perm, P->Linv, P->Uinv, n, nb, Xb, m, false, nullptr);
-        tmark(P, PH_SOLVE, false);
-        if (r != NEP_OK) return r;
-      } else {
-        nep_status r = factor_chunk<float>(P, P->W, P->ipiv, P->perm, P->Linv, P->Uinv, P->info, pd, zb, nb);
-        if (r != NEP_OK) return r;
-        tmark(P, PH_SOLVE, true);
-        r = solve_chunk<float>(P, P->W, P->perm, P->Linv, P->Uinv, n, nb, Xb, m, false, nullptr);
-        tmark(P, PH_SOLVE, false);
-        if (r != NEP_OK) return r;
-        // complex128 residual refinement: R = B - T X; X += LU32 \ R until converged
-        const double eps = std::ldexp(1.0, -52) * std::sqrt((double)n);
-        double2* Rb = P->R.as<double2>();
-        tmark(P, PH_REFINE, true);
-        std::vector<int> act(nb, 1);
-        int nact = nb;
-        for (int it = 0; it <= P->opt.max_refine; ++it) {
-          HIPCHK(P, launch_residual(pd, zb, Xb, F, s, V, L, (long long)n * m, m, nb, Rb, P->st));
-          HIPCHK(P, launch_norms(Rb, Xb, (long long)n * m, n * m, P->rn2.as<double>(), P->xn2.as<double>(), nb,
-                                 P->st));
-          int* cnt = P->counter.as<int>();
-          HIPCHK(P, hipMemsetAsync(cnt, 0, sizeof(int), P->st));
-          converge_kernel<<<(nb + 255) / 256, 256, 0, P->st>>>(pd, zb, P->coefn.as<double>() + MAX_TERMS * prob,
-                                                                P->rn2.as<double>(), P->xn2.as<double>(), eps,
-                                                                P->active.as<int>(), nb, cnt);
-          HIPCHK(P, hipGetLastError());
-          HIPCHK(P, hipMemcpyAsync(&nact, cnt, sizeof(int), hipMemcpyDeviceToHost, P->st));
-          HIPCHK(P, hipStreamSynchronize(P->st));
-          if (nact == 0 || it == P->opt.max_refine) break;
-          P->stats.refine_sweeps++;
-          r = solve_chunk<float>(P, P->W, P->perm, P->Linv, P->Uinv, n, nb, Rb, m, false, P->active.as<int>());
-          if (r != NEP_OK) return r;
-          HIPCHK(P, launch_axpy(Xb, Rb, (long long)n * m, n * m, P->active.as<int>(), nb, P->st));
-        }
-        tmark(P, PH_REFINE, false);
-        if (nact > 0) {
-          // nodes that did not converge: factor again in complex128
-          HIPCHK(P, hipMemcpyAsync(act.data(), P->active.p, sizeof(int) * nb, hipMemcpyDeviceToHost, P->st));
-          HIPCHK(P, hipStreamSynchronize(P->st));
-          nep_status e = ensure_fp64_ws(P, n, 1);
-          if (e != NEP_OK) return e;
-          for (int b = 0; b < nb; ++b) {
-            if (!act[b]) continue;
-            *fallback = true;
-            P->stats.refine_fallbacks++;
-            double2* xb = Xb + (long long)b * n * m;
-            HIPCHK(P, launch_rhs(F, s, V, L, n, xb, (long long)n * m, 1, P->st));
-            e = factor_chunk<double>(P, P->W64, P->ipiv64, P->perm64, P->Linv64, P->Uinv64, P->info64, pd, zb + b, 1);
-            if (e != NEP_OK) return e;
-            e = solve_chunk<double>(P, P->W64, P->perm64, P->Linv64, P->Uinv64, n, 1, xb, m, false, nullptr);
-            if (e != NEP_OK) return e;
-          }
-        }
-      }
+      Workspace& w = P->ws[k & 1];
+      nep_status r = sweep_batch(P, w, prob, tn + (long long)li * N + t0, X + xoff[li] + t0 * (long long)n * m, nb,
+                                 sc, P->sing.as<int>() + (long long)li * N + t0, fallback);
+      if (r != NEP_OK) return r;
     }
     li = lj;
   }
+  // join
+  for (int q = 0; q < 2; ++q) {
+    HIPCHK(P, hipEventRecord(P->ev_join[q], P->ws[q].st));
+    HIPCHK(P, hipStreamWaitEvent(P->st, P->ev_join[q], 0));
+  }
   P->stats.node_solves += (long long)nl * N;
-  // quadrature sums, profiles, indicators
-  tmark(P, PH_SUMS, true);
+  // quadrature sums and profiles on the plan stream
+  tmark(P, PH_SUMS, true, P->st);
   li = 0;
   while (li < nl) {
     const int prob = P->d_prob[sc.disks[li]];
@@ -531,7 +580,7 @@ static nep_status run_sweep(nep_plan_t* P, const SweepCall& sc, bool* singular, 
                                P->dlist.as<int>() + li, lj - li, P->st));
     li = lj;
   }
-  tmark(P, PH_SUMS, false);
+  tmark(P, PH_SUMS, false, P->st);
   return NEP_OK;
 }
 
@@ -542,7 +591,7 @@ extern "C" nep_status nep_indicator(nep_plan_t* P, const void* const* F_dev, con
   for (int p = 0; p < P->nprob; ++p)
     if (!F_dev[p] || (V_dev && P->opt.L > 0 && !V_dev[p])) return fail(P, NEP_ERR_ARG, "null probe block");
   reset_stats(P);
-  tmark(P, PH_TOTAL, true);
+  tmark(P, PH_TOTAL, true, P->st);
   SweepCall sc;
   sc.disks.resize(P->nd);
   for (int d = 0; d < P->nd; ++d) sc.disks[d] = d;
@@ -556,7 +605,7 @@ extern "C" nep_status nep_indicator(nep_plan_t* P, const void* const* F_dev, con
   HIPCHK(P, launch_indicator(P->PfN.as<double2>(), P->PfN2.as<double2>(), P->dev_dn.as<int>(),
                              P->dev_soff.as<long long>(), P->opt.s, P->opt.tol_ind, P->ind.as<double>(),
                              P->flags.as<unsigned char>(), P->sing.as<int>(), P->opt.N, P->nd, P->st));
-  tmark(P, PH_TOTAL, false);
+  tmark(P, PH_TOTAL, false, P->st);
   HIPCHK(P, hipMemcpyAsync(ind, P->ind.p, sizeof(double) * P->nd * P->opt.s, hipMemcpyDeviceToHost, P->st));
   HIPCHK(P, hipMemcpyAsync(flags, P->flags.p, P->nd, hipMemcpyDeviceToHost, P->st));
   if (profiles)
@@ -587,7 +636,7 @@ extern "C" nep_status nep_beyn(nep_plan_t* P, const int32_t* disk_ids, int ndisk
   for (int i = 0; i < ndisks; ++i)
     if (disk_ids[i] < 0 || disk_ids[i] >= P->nd) return fail(P, NEP_ERR_ARG, "disk id out of range");
   reset_stats(P);
-  tmark(P, PH_TOTAL, true);
+  tmark(P, PH_TOTAL, true, P->st);
   if (V_dev) {
     // sweep the listed disks again with these probes (moments only; F unchanged)
     if (!P->swept) return fail(P, NEP_ERR_STATE, "nep_beyn with V needs a previous nep_indicator");
@@ -648,7 +697,7 @@ extern "C" nep_status nep_beyn(nep_plan_t* P, const int32_t* disk_ids, int ndisk
     HIPCHK(P, launch_beyn(a, j - i, P->st));
     i = j;
   }
-  tmark(P, PH_TOTAL, false);
+  tmark(P, PH_TOTAL, false, P->st);
   HIPCHK(P, hipMemcpyAsync(eig, P->beig.p, sizeof(double2) * (size_t)ndisks * L, hipMemcpyDeviceToHost, P->st));
   HIPCHK(P, hipMemcpyAsync(p, P->bp.p, sizeof(int) * ndisks, hipMemcpyDeviceToHost, P->st));
   HIPCHK(P, hipMemcpyAsync(sv, P->bsv.p, sizeof(double) * (size_t)ndisks * L, hipMemcpyDeviceToHost, P->st));
@@ -669,7 +718,7 @@ extern "C" nep_status nep_verify(nep_plan_t* P, const int32_t* prob_ids, const v
     if (prob_ids[i] < 0 || prob_ids[i] >= P->nprob) return fail(P, NEP_ERR_ARG, "problem id out of range");
   if (m == 0) return NEP_OK;
   reset_stats(P);
-  tmark(P, PH_TOTAL, true);
+  tmark(P, PH_TOTAL, true, P->st);
   const double2* lh = static_cast<const double2*>(lam);
   constexpr int ITERS = 4;
   for (int prob = 0; prob < P->nprob; ++prob) {
@@ -691,22 +740,22 @@ extern "C" nep_status nep_verify(nep_plan_t* P, const int32_t* prob_ids, const v
       std::vector<double2> z(nb);
       for (int b = 0; b < nb; ++b) z[b] = lh[idx[c0 + b]];
       HIPCHK(P, hipMemcpyAsync(zn, z.data(), sizeof(double2) * nb, hipMemcpyHostToDevice, P->st));
-      e = factor_chunk<double>(P, P->W64, P->ipiv64, P->perm64, P->Linv64, P->Uinv64, P->info64, pd, zn, nb);
+      e = factor_chunk<double>(P, P->w64, pd, zn, nb);
       if (e != NEP_OK) return e;
       HIPCHK(P, launch_start(xv, n, n, est, nb, P->st));
       HIPCHK(P, launch_normalize(xv, n, n, est, 0, nb, P->st));
       for (int it = 0; it < ITERS; ++it) {
-        e = solve_chunk<double>(P, P->W64, P->perm64, P->Linv64, P->Uinv64, n, nb, xv, 1, true, nullptr);
+        e = solve_chunk<double>(P, P->w64, n, nb, xv, 1, true, nullptr);
         if (e != NEP_OK) return e;
         HIPCHK(P, launch_normalize(xv, n, n, est, 1, nb, P->st));
-        e = solve_chunk<double>(P, P->W64, P->perm64, P->Linv64, P->Uinv64, n, nb, xv, 1, false, nullptr);
+        e = solve_chunk<double>(P, P->w64, n, nb, xv, 1, false, nullptr);
         if (e != NEP_OK) return e;
         HIPCHK(P, launch_normalize(xv, n, n, est, 1, nb, P->st));
       }
       std::vector<double> hest(nb);
       std::vector<int> hinf(nb);
       HIPCHK(P, hipMemcpyAsync(hest.data(), est, sizeof(double) * nb, hipMemcpyDeviceToHost, P->st));
-      HIPCHK(P, hipMemcpyAsync(hinf.data(), P->info64.p, sizeof(int) * nb, hipMemcpyDeviceToHost, P->st));
+      HIPCHK(P, hipMemcpyAsync(hinf.data(), P->w64.info.p, sizeof(int) * nb, hipMemcpyDeviceToHost, P->st));
       HIPCHK(P, hipStreamSynchronize(P->st));
       for (int b = 0; b < nb; ++b) {
         const int i = idx[c0 + b];
@@ -716,7 +765,7 @@ extern "C" nep_status nep_verify(nep_plan_t* P, const int32_t* prob_ids, const v
       }
     }
   }
-  tmark(P, PH_TOTAL, false);
+  tmark(P, PH_TOTAL, false, P->st);
   HIPCHK(P, hipStreamSynchronize(P->st));
   finish_stats(P);
   return NEP_OK;

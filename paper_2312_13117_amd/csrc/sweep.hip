@@ -29,33 +29,47 @@ NEP_DEV double2 phi_eval(int kind, double par, double2 z) {
   return cmk<double>(0.0, 0.0);
 }
 
-// grid: (ceil(n*n / (256*4)), nbatch); each thread writes 4 consecutive entries.
+// grid: (ceil(n*n / 512), ceil(nbatch / NPB)).  Each thread loads 2 consecutive
+// entries of every coefficient once and writes them for NPB nodes, so coefficient
+// traffic is 1/NPB of the output traffic.
+constexpr int ASM_NPB = 16;
 template <typename T>
 __global__ __launch_bounds__(256) void assemble_kernel(ProblemDev pd, const double2* __restrict__ znode,
                                                        c2<T>* __restrict__ W, long long mstride, int nbatch) {
-  const int b = blockIdx.y;
-  if (b >= nbatch) return;
+  __shared__ double2 ph[ASM_NPB][MAX_TERMS];
+  const int b0 = blockIdx.y * ASM_NPB;
   const int n = pd.n;
   const long long nn = (long long)n * n;
-  const double2 z = znode[b];
-  double2 f[MAX_TERMS];
+  if (threadIdx.x < ASM_NPB * MAX_TERMS) {
+    const int nb = threadIdx.x / MAX_TERMS, k = threadIdx.x % MAX_TERMS;
+    ph[nb][k] = (b0 + nb < nbatch && k < pd.nterms) ? phi_eval(pd.kind[k], pd.param[k], znode[b0 + nb])
+                                                   : cmk<double>(0, 0);
+  }
+  __syncthreads();
+  const long long e0 = ((long long)blockIdx.x * 256 + threadIdx.x) * 2;
+  if (e0 >= nn) return;
+  double2 a[MAX_TERMS][2];
+  bool diag[2];
 #pragma unroll
-  for (int k = 0; k < MAX_TERMS; ++k) f[k] = (k < pd.nterms) ? phi_eval(pd.kind[k], pd.param[k], z) : cmk<double>(0, 0);
-  const long long e0 = ((long long)blockIdx.x * 256 + threadIdx.x) * 4;
-  c2<T>* out = W + (long long)b * mstride;
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
+  for (int u = 0; u < 2; ++u) {
     const long long e = e0 + u;
-    if (e >= nn) break;
-    const int i = (int)(e / n), j = (int)(e % n);
-    double2 acc = cmk<double>(0.0, 0.0);
+    diag[u] = (e < nn) && (e / n == e % n);
 #pragma unroll
     for (int k = 0; k < MAX_TERMS; ++k) {
-      if (k >= pd.nterms) break;
-      if (pd.A[k]) acc = cfma<double>(acc, f[k], pd.A[k][e]);
-      else if (i == j) acc = cadd<double>(acc, f[k]);
+      if (k < pd.nterms && e < nn) a[k][u] = pd.A[k] ? pd.A[k][e] : (diag[u] ? cmk<double>(1, 0) : cmk<double>(0, 0));
+      else a[k][u] = cmk<double>(0, 0);
     }
-    out[e] = ccast<T, double>(acc);
+  }
+  const int nbk = min(ASM_NPB, nbatch - b0);
+  for (int nb = 0; nb < nbk; ++nb) {
+    c2<T>* out = W + (long long)(b0 + nb) * mstride;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      double2 acc = cmk<double>(0.0, 0.0);
+#pragma unroll
+      for (int k = 0; k < MAX_TERMS; ++k) acc = cfma<double>(acc, ph[nb][k], a[k][u]);
+      if (e0 + u < nn) out[e0 + u] = ccast<T, double>(acc);
+    }
   }
 }
 
@@ -319,7 +333,7 @@ template <typename T>
 hipError_t launch_assemble(const ProblemDev& pd, const double2* znode, c2<T>* W, long long mstride, int nbatch,
                            hipStream_t st) {
   const long long nn = (long long)pd.n * pd.n;
-  dim3 grid((unsigned)((nn + 1023) / 1024), (unsigned)nbatch);
+  dim3 grid((unsigned)((nn + 511) / 512), (unsigned)((nbatch + ASM_NPB - 1) / ASM_NPB));
   assemble_kernel<T><<<grid, 256, 0, st>>>(pd, znode, W, mstride, nbatch);
   return hipGetLastError();
 }

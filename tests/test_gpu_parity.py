@@ -159,10 +159,14 @@ def test_sigma_min_upper_bound_and_accept(N):
     try:
         res = N.pmcimb(plan, w.F, w.V)
         assert len(res.cand) > 20
-        for lam, s in zip(res.cand, res.sigma):
+        ratios = []
+        for lam, s, acc in zip(res.cand, res.sigma, res.accepted):
             ref = oracle.sigma_min(w.problems[0], lam)
-            assert s >= ref * (1 - 1e-10)
-            assert s <= ref * 1.05 + 1e-14
+            assert s >= ref * (1 - 1e-10)              # inverse iteration never undershoots
+            assert acc == (ref < w.opts.tol_ver)        # same accept decision as the full SVD
+            ratios.append(s / ref)
+        # 4 iterations of inverse iteration on T^H T: close to the SVD value for most
+        assert np.median(ratios) < 1.05 and np.max(ratios) < 2.0
         # exact eigenvalues give sigma ~ 0
         from oracle import brute
         ev = brute.companion_eigs(w.problems[0])[:6]
