@@ -193,3 +193,23 @@ def paper_demo_problem() -> Problem:
     T1 = np.array([[0.4, 0, -0.3, 0], [0, 0, 0, 0], [-0.3, 0, 0.5, -0.2], [0, 0, -0.2, 0.2]])
     T0 = np.array([[-7.0, 2, 4, 0], [2, -4, 2, 0], [4, 2, -9, 3], [0, 0, 3, -3]])
     return qep(T0, T1, T2)
+
+
+# ---------------------------------------------------------------- screener MLP inputs
+MLP_LAYERS = [(32, 128), (128, 128), (128, 4)]   # in x out per dense layer
+
+
+def mlp_param_count() -> int:
+    return sum(i * o + o for i, o in MLP_LAYERS)
+
+
+def mlp_init(seed: int = 7) -> np.ndarray:
+    """Initial screener parameters, flat float32: for each layer W (in x out, row-major)
+    then b (out), each entry uniform in [-1/sqrt(in), 1/sqrt(in)] from default_rng(seed)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for i, o in MLP_LAYERS:
+        bound = 1.0 / np.sqrt(i)
+        parts.append(rng.uniform(-bound, bound, size=(i, o)).ravel())
+        parts.append(rng.uniform(-bound, bound, size=o))
+    return np.concatenate(parts).astype(np.float32)

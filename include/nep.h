@@ -38,6 +38,7 @@
 #ifndef NEP_H
 #define NEP_H
 
+#include <stddef.h>
 #include <stdint.h>
 #include <hip/hip_runtime_api.h>
 
@@ -219,6 +220,34 @@ nep_status nep_copy_sums(nep_plan_t* plan, int first, int count, void* PfN, void
  * one with the smaller sigma keeps its slot (the final list of Step 3 after values found
  * from two neighbouring disks).  Host only; keep[i] = 1 for survivors.             */
 nep_status nep_dedup(const void* lam, const double* sigma, int m, double rel, uint8_t* keep);
+
+/* ---------------------------------------------------------------- learned screener
+ * A small network (not part of the paper's method) that orders the screening of the
+ * four children of a flagged parent cell from the parent's node profile
+ * ||T(z_j)^{-1} f||, j = 1..32.  It never decides a flag: every child is still swept.
+ * Network: 32 -> 128 -> 128 -> 4, ReLU after the hidden layers, sigmoid outputs, fp32.
+ * Parameters (nep_mlp_param_count() = 21252 floats, device): for each layer W
+ * (in x out, row-major) then b (out).  Samples are rows of 32 features; targets are
+ * rows of 4 values in {0, 1}.  idx (device int32, B entries) selects the rows of X (and
+ * Y) that form the batch, or NULL for rows 0..B-1.  work is caller-allocated device
+ * memory of nep_mlp_workspace_floats(B) floats.  All calls run on `stream`.          */
+int nep_mlp_param_count(void);
+size_t nep_mlp_workspace_floats(int B);
+/* probs (device, B x 4) = sigmoid(network(X[idx]))                                    */
+nep_status nep_mlp_forward(const float* params_dev, const float* X_dev, const int32_t* idx_dev, int B,
+                           float* probs_dev, float* work_dev, hipStream_t stream);
+/* grad (device, 21252) = gradient of the mean binary cross-entropy over the batch and
+ * the 4 outputs; *loss (host, or NULL) receives that mean (the call then synchronises) */
+nep_status nep_mlp_grad(const float* params_dev, const float* X_dev, const float* Y_dev, const int32_t* idx_dev,
+                        int B, float* grad_dev, float* loss, float* work_dev, hipStream_t stream);
+/* one Adam step (bias-corrected, step counts from 1) on params with moments m, v      */
+nep_status nep_mlp_adam(float* params_dev, const float* grad_dev, float* m_dev, float* v_dev, int step, float lr,
+                        float beta1, float beta2, float eps, hipStream_t stream);
+/* X (device, rows x ncol) = (log10(profiles) - mean) / sd per column; when stat_rows is
+ * given, mean and sd are first computed over those rows (the training rows), otherwise
+ * the given mean/sd (device, ncol) are used                                          */
+nep_status nep_mlp_features(const double* profiles_dev, int rows, int ncol, const int32_t* stat_rows_dev,
+                            int nstat, float* mean_dev, float* sd_dev, float* X_dev, hipStream_t stream);
 
 /* Sizes of a plan: total disks, and the first global disk of problem p.             */
 int nep_total_disks(const nep_plan_t* plan);

@@ -650,11 +650,12 @@ __global__ __launch_bounds__(256) void lu_solve_kernel(const c2<T>* __restrict__
   const c2<T>* A = W + (long long)b * mstride;
   double2* Xb = X + (long long)b * xstride;
   const int nsteps = (n + NB - 1) / NB;
-  __shared__ c2<T> Ash[NB][KC + 1];
-  __shared__ c2<T> Bsh[NB][MMAX];
+  // Ash and Bsh form one contiguous block (the row exchange uses it as a flat buffer)
+  __shared__ c2<T> tiles[NB * (KC + 1) + NB * MMAX];
+  c2<T> (*Ash)[KC + 1] = reinterpret_cast<c2<T>(*)[KC + 1]>(tiles);
+  c2<T> (*Bsh)[MMAX] = reinterpret_cast<c2<T>(*)[MMAX]>(tiles + NB * (KC + 1));
   __shared__ int s_pos[2 * NB], s_src[2 * NB];
   __shared__ int s_cnt;
-  constexpr int GMAX = (2 * NB * MMAX + 255) / 256;
   SolveTile<T> tile;
 
   auto load_perm = [&](int s) {
@@ -664,22 +665,21 @@ __global__ __launch_bounds__(256) void lu_solve_kernel(const c2<T>* __restrict__
     for (int i = t; i < 2 * NB; i += 256) { s_pos[i] = P[1 + i]; s_src[i] = P[1 + 2 * NB + i]; }
     __syncthreads();
   };
-  // new[pos[i]] = old[src[i]] (forward) or new[src[i]] = old[pos[i]] (inverse)
+  // new[pos[i]] = old[src[i]] (forward) or new[src[i]] = old[pos[i]] (inverse); the old
+  // rows are gathered into the LDS tiles (as one flat buffer) before any row is written
   auto permute = [&](bool inverse) {
     const int cnt = s_cnt;
-    c2<T> g[GMAX];
-#pragma unroll
-    for (int q = 0; q < GMAX; ++q) {
-      const int e = t + q * 256;
+    c2<T>* buf = &Ash[0][0];
+    constexpr int CAP = NB * (KC + 1) + NB * MMAX;   // Ash and Bsh are contiguous
+    static_assert(2 * NB * MMAX <= CAP, "permutation buffer");
+    for (int e = t; e < cnt * m; e += 256) {
       const int i = e / m, c = e % m;
-      g[q] = (e < cnt * m) ? ccast<T, double>(Xb[(long long)(inverse ? s_pos[i] : s_src[i]) * m + c]) : czero<T>();
+      buf[e] = ccast<T, double>(Xb[(long long)(inverse ? s_pos[i] : s_src[i]) * m + c]);
     }
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < GMAX; ++q) {
-      const int e = t + q * 256;
+    for (int e = t; e < cnt * m; e += 256) {
       const int i = e / m, c = e % m;
-      if (e < cnt * m) Xb[(long long)(inverse ? s_src[i] : s_pos[i]) * m + c] = ccast<double, T>(g[q]);
+      Xb[(long long)(inverse ? s_src[i] : s_pos[i]) * m + c] = ccast<double, T>(buf[e]);
     }
     __syncthreads();
   };
@@ -742,16 +742,38 @@ __global__ __launch_bounds__(256) void lu_solve_kernel(const c2<T>* __restrict__
       store_acc_B();                       // y for the trailing rows
       store_acc_X(k0, nbk);
       __syncthreads();
-      for (int r = kend; r < n; r += NB) {
-        const int nr = min(NB, n - r);
-        load_acc_X(r, nr);
-        for (int kc = 0; kc < nbk; kc += KC) {
+      // rest rows in blocks of 64, operand chunks of 64 x KC; the next chunk is loaded
+      // into registers while the current one is multiplied out of LDS
+      {
+        const int nkc = (nbk + KC - 1) / KC;
+        const int nrb = (n - kend + NB - 1) / NB;
+        const int nch = nrb * nkc;
+        c2<T> pre[NB * KC / 256];
+        auto fetch = [&](int c) {
+          const int r = kend + (c / nkc) * NB, kc = (c % nkc) * KC;
+          const int nr = min(NB, n - r), kk = min(KC, nbk - kc);
+#pragma unroll
+          for (int q = 0; q < NB * KC / 256; ++q) {
+            const int e = t + q * 256, i = e / KC, k = e % KC;
+            pre[q] = (i < nr && k < kk) ? A[(long long)(r + i) * n + k0 + kc + k] : czero<T>();
+          }
+        };
+        if (nch > 0) fetch(0);
+        for (int c = 0; c < nch; ++c) {
+          const int r = kend + (c / nkc) * NB, kc = (c % nkc) * KC;
+          const int nr = min(NB, n - r), kk = min(KC, nbk - kc);
+          if (kc == 0) load_acc_X(r, nr);
           __syncthreads();
-          stage_A(A + (long long)r * n + k0 + kc, n, nr, min(KC, nbk - kc));
+#pragma unroll
+          for (int q = 0; q < NB * KC / 256; ++q) {
+            const int e = t + q * 256;
+            Ash[e / KC][e % KC] = pre[q];
+          }
+          if (c + 1 < nch) fetch(c + 1);
           __syncthreads();
-          tile.template mma<true>(Ash, Bsh, kc, min(KC, nbk - kc));
+          tile.template mma<true>(Ash, Bsh, kc, kk);
+          if (kc + KC >= nbk) store_acc_X(r, nr);
         }
-        store_acc_X(r, nr);
       }
       __syncthreads();
     }
@@ -759,14 +781,40 @@ __global__ __launch_bounds__(256) void lu_solve_kernel(const c2<T>* __restrict__
     for (int s = nsteps - 1; s >= 0; --s) {
       const int k0 = s * NB, nbk = min(NB, n - k0), kend = k0 + nbk;
       load_acc_X(k0, nbk);
-      for (int kc = kend; kc < n; kc += KC) {
-        const int kk = min(KC, n - kc);
-        __syncthreads();
-        stage_A(A + (long long)k0 * n + kc, n, nbk, kk);
-        stage_X(kc, kk, 0);
-        for (int i = kk + t / MMAX; i < KC; i += 256 / MMAX) Bsh[i][t % MMAX] = czero<T>();
-        __syncthreads();
-        tile.template mma<true>(Ash, Bsh, 0, kk);
+      {
+        // K chunks of U12 (64 x KC) and X (KC x m), next chunk prefetched into registers
+        c2<T> pa[NB * KC / 256], pb[KC * MMAX / 256];
+        auto fetch = [&](int kc) {
+          const int kk = min(KC, n - kc);
+#pragma unroll
+          for (int q = 0; q < NB * KC / 256; ++q) {
+            const int e = t + q * 256, i = e / KC, k = e % KC;
+            pa[q] = (i < nbk && k < kk) ? A[(long long)(k0 + i) * n + kc + k] : czero<T>();
+          }
+#pragma unroll
+          for (int q = 0; q < KC * MMAX / 256; ++q) {
+            const int e = t + q * 256, i = e / MMAX, c = e % MMAX;
+            pb[q] = (i < kk && c < m) ? ccast<T, double>(Xb[(long long)(kc + i) * m + c]) : czero<T>();
+          }
+        };
+        if (kend < n) fetch(kend);
+        for (int kc = kend; kc < n; kc += KC) {
+          const int kk = min(KC, n - kc);
+          __syncthreads();
+#pragma unroll
+          for (int q = 0; q < NB * KC / 256; ++q) {
+            const int e = t + q * 256;
+            Ash[e / KC][e % KC] = pa[q];
+          }
+#pragma unroll
+          for (int q = 0; q < KC * MMAX / 256; ++q) {
+            const int e = t + q * 256;
+            Bsh[e / MMAX][e % MMAX] = pb[q];
+          }
+          if (kc + KC < n) fetch(kc + KC);
+          __syncthreads();
+          tile.template mma<true>(Ash, Bsh, 0, kk);
+        }
       }
       __syncthreads();
       store_acc_B();                       // z

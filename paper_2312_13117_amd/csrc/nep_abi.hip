@@ -102,7 +102,7 @@ struct nep_plan {
   Workspace ws[2];
   Workspace w64;
   hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
-  DevBuf coefn, sing;
+  DevBuf sing;
   DevBuf bscr, beig, bp, bsv, bkeep, bstat, bvec;
   DevBuf vest;
   int batch = 0;
@@ -327,16 +327,24 @@ extern "C" nep_status nep_plan(const nep_problem* probs, int nprob, const nep_re
       PCHK(w.R.alloc(sizeof(double2) * (size_t)B * nm * m));
       PCHK(w.rn2.alloc(sizeof(double) * B));
       PCHK(w.xn2.alloc(sizeof(double) * B));
-      PCHK(w.active.alloc(sizeof(int) * B));
+      PCHK(w.active.alloc(sizeof(int) * 2 * B));
     }
   }
   P->w64.st = P->st;
   PCHK(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming));
   PCHK(hipEventCreateWithFlags(&P->ev_join[0], hipEventDisableTiming));
   PCHK(hipEventCreateWithFlags(&P->ev_join[1], hipEventDisableTiming));
-  PCHK(P->coefn.alloc(sizeof(double) * MAX_TERMS * nprob));
-  for (int p = 0; p < nprob; ++p)
-    PCHK(launch_coef_norms(P->pd[p], P->coefn.as<double>() + MAX_TERMS * p, P->st));
+  {
+    DevBuf rf;
+    PCHK(rf.alloc(sizeof(int) * MAX_TERMS));
+    for (int p = 0; p < nprob; ++p) {
+      int h[MAX_TERMS] = {0, 0, 0, 0};
+      PCHK(launch_is_real(P->pd[p], rf.as<int>(), P->st));
+      PCHK(hipMemcpy(h, rf.p, sizeof(int) * P->pd[p].nterms, hipMemcpyDeviceToHost));
+      for (int k = 0; k < P->pd[p].nterms; ++k) P->pd[p].real[k] = h[k];
+    }
+    rf.release();
+  }
   P->gemm_ev.resize(2 * LuTimers::MAXP);
   for (auto& e : P->gemm_ev) PCHK(hipEventCreate(&e));
   P->lut.ev = P->gemm_ev.data();
@@ -353,7 +361,7 @@ extern "C" void nep_destroy(nep_plan_t* P) {
   for (auto& w : P->ws) if (w.st) hipStreamSynchronize(w.st);
   DevBuf* bufs[] = {&P->dev_dn, &P->dev_ix, &P->dev_iy, &P->dev_soff, &P->dev_w, &P->dev_z, &P->PfN, &P->PfN2,
                     &P->C0, &P->C1, &P->prof, &P->ind, &P->flags, &P->X, &P->xoff, &P->tnode, &P->dlist,
-                    &P->coefn, &P->sing, &P->bscr, &P->beig, &P->bp, &P->bsv, &P->bkeep, &P->bstat, &P->bvec,
+                    &P->sing, &P->bscr, &P->beig, &P->bp, &P->bsv, &P->bkeep, &P->bstat, &P->bvec,
                     &P->vest};
   for (DevBuf* b : bufs) b->release();
   for (auto& w : P->ws) w.release();
@@ -367,34 +375,6 @@ extern "C" void nep_destroy(nep_plan_t* P) {
 }
 
 // ---------------------------------------------------------------------------- factor + solve
-// Mixed-precision convergence: active[b] = ||R_b|| > eps * ||T(z_b)|| * ||X_b||, with
-// ||T(z)||_F bounded by sum_k |phi_k(z)| ||A_k||_F.
-__global__ void converge_kernel(ProblemDev pd, const double2* znode, const double* coefn, const double* rn2,
-                                const double* xn2, double eps, int* active, int nb, int* count) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nb) return;
-  const double2 z = znode[b];
-  double tn = 0;
-  for (int k = 0; k < pd.nterms; ++k) {
-    double2 f;
-    switch (pd.kind[k]) {
-      case PHI_ONE: f = make_double2(1, 0); break;
-      case PHI_Z: f = z; break;
-      case PHI_Z2: f = make_double2(z.x * z.x - z.y * z.y, 2 * z.x * z.y); break;
-      case PHI_NEG_Z: f = make_double2(-z.x, -z.y); break;
-      default: {
-        const double e = exp(-pd.param[k] * z.x);
-        f = make_double2(e, 0);
-      }
-    }
-    tn += hypot(f.x, f.y) * coefn[k];
-  }
-  const double r = sqrt(rn2[b]), x = sqrt(xn2[b]);
-  const int a = (r > eps * tn * x || !(r == r)) ? 1 : 0;
-  active[b] = a;
-  if (a) atomicAdd(count, 1);
-}
-
 struct SweepCall {
   std::vector<int> disks;   // global disk ids of this sweep
   int s, L;                 // columns of F and V used
@@ -467,51 +447,55 @@ static nep_status sweep_batch(nep_plan_t* P, Workspace& w, int prob, const doubl
   r = solve_chunk<float>(P, w, n, nb, Xb, m, false, nullptr);
   tmark(P, PH_SOLVE, false, w.st);
   if (r != NEP_OK) return r;
-  // complex128 residual refinement: R = B - T X; X += LU32 \ R until the backward
-  // error ||R|| <= 2^-52 sqrt(n) ||T|| ||X|| holds for every node of the batch
-  const double eps = std::ldexp(1.0, -52) * std::sqrt((double)n);
+  // complex128 residual refinement: R = B - T(z) X in complex128, X += LU32 \ R.  A node
+  // stops once its correction is below 2^-26 ||X|| (the error left after it is then
+  // below 2^-26 kappa u32); a correction that does not halve, or is not finite, marks
+  // the node for a complex128 re-solve.
+  const double tol = std::ldexp(1.0, -26);
   double2* Rb = w.R.as<double2>();
   tmark(P, PH_REFINE, true, w.st);
+  HIPCHK(P, launch_fill_int(w.active.as<int>(), 1, nb, w.st));
+  HIPCHK(P, launch_fill_int(w.active.as<int>() + nb, 0, nb, w.st));   // diverged flags
   int nact = nb;
-  for (int it = 0; it <= P->opt.max_refine; ++it) {
-    HIPCHK(P, launch_residual(pd, zb, Xb, F, s, V, L, (long long)n * m, m, nb, Rb, w.st));
-    HIPCHK(P, launch_norms(Rb, Xb, (long long)n * m, n * m, w.rn2.as<double>(), w.xn2.as<double>(), nb, w.st));
-    int* cnt = w.counter.as<int>();
-    HIPCHK(P, hipMemsetAsync(cnt, 0, sizeof(int), w.st));
-    converge_kernel<<<(nb + 255) / 256, 256, 0, w.st>>>(pd, zb, P->coefn.as<double>() + MAX_TERMS * prob,
-                                                         w.rn2.as<double>(), w.xn2.as<double>(), eps,
-                                                         w.active.as<int>(), nb, cnt);
-    HIPCHK(P, hipGetLastError());
-    HIPCHK(P, hipMemcpyAsync(&nact, cnt, sizeof(int), hipMemcpyDeviceToHost, w.st));
-    HIPCHK(P, hipStreamSynchronize(w.st));
-    if (nact == 0 || it == P->opt.max_refine) break;
+  for (int it = 0; it < P->opt.max_refine && nact > 0; ++it) {
     P->stats.refine_sweeps++;
+    HIPCHK(P, launch_residual(pd, zb, Xb, F, s, V, L, (long long)n * m, m, nb, Rb, w.active.as<int>(), w.st));
     r = solve_chunk<float>(P, w, n, nb, Rb, m, false, w.active.as<int>());
     if (r != NEP_OK) return r;
     HIPCHK(P, launch_axpy(Xb, Rb, (long long)n * m, n * m, w.active.as<int>(), nb, w.st));
+    int* cnt = w.counter.as<int>();
+    HIPCHK(P, hipMemsetAsync(cnt, 0, sizeof(int), w.st));
+    HIPCHK(P, launch_refine_check(Rb, Xb, (long long)n * m, n * m, tol, w.rn2.as<double>(), it == 0,
+                                  w.active.as<int>(), w.active.as<int>() + nb, nb, cnt, w.st));
+    HIPCHK(P, hipMemcpyAsync(&nact, cnt, sizeof(int), hipMemcpyDeviceToHost, w.st));
+    HIPCHK(P, hipStreamSynchronize(w.st));
+  }
+  {
+    // still active after max_refine sweeps, or diverged: re-solve in complex128
+    std::vector<int> act(2 * (size_t)nb);
+    HIPCHK(P, hipMemcpyAsync(act.data(), w.active.p, sizeof(int) * 2 * nb, hipMemcpyDeviceToHost, w.st));
+    HIPCHK(P, hipStreamSynchronize(w.st));
+    for (int b = 0; b < nb; ++b) act[b] = act[b] || act[nb + b];
+    nact = 0;
+    for (int b = 0; b < nb; ++b) nact += act[b];
+    if (nact > 0) {
+      nep_status e = ensure_fp64_ws(P, n, 1);
+      if (e != NEP_OK) return e;
+      for (int b = 0; b < nb; ++b) {
+        if (!act[b]) continue;
+        *fallback = true;
+        P->stats.refine_fallbacks++;
+        double2* xb = Xb + (long long)b * n * m;
+        HIPCHK(P, launch_rhs(F, s, V, L, n, xb, (long long)n * m, 1, P->w64.st));
+        e = factor_chunk<double>(P, P->w64, pd, zb + b, 1);
+        if (e != NEP_OK) return e;
+        e = solve_chunk<double>(P, P->w64, n, 1, xb, m, false, nullptr);
+        if (e != NEP_OK) return e;
+      }
+      HIPCHK(P, hipStreamSynchronize(P->w64.st));
+    }
   }
   tmark(P, PH_REFINE, false, w.st);
-  if (nact > 0) {
-    // nodes that did not converge: factor again in complex128 (plan stream, after
-    // this batch's stream has finished with them)
-    std::vector<int> act(nb);
-    HIPCHK(P, hipMemcpyAsync(act.data(), w.active.p, sizeof(int) * nb, hipMemcpyDeviceToHost, w.st));
-    HIPCHK(P, hipStreamSynchronize(w.st));
-    nep_status e = ensure_fp64_ws(P, n, 1);
-    if (e != NEP_OK) return e;
-    for (int b = 0; b < nb; ++b) {
-      if (!act[b]) continue;
-      *fallback = true;
-      P->stats.refine_fallbacks++;
-      double2* xb = Xb + (long long)b * n * m;
-      HIPCHK(P, launch_rhs(F, s, V, L, n, xb, (long long)n * m, 1, P->w64.st));
-      e = factor_chunk<double>(P, P->w64, pd, zb + b, 1);
-      if (e != NEP_OK) return e;
-      e = solve_chunk<double>(P, P->w64, n, 1, xb, m, false, nullptr);
-      if (e != NEP_OK) return e;
-    }
-    HIPCHK(P, hipStreamSynchronize(P->w64.st));
-  }
   return NEP_OK;
 }
 

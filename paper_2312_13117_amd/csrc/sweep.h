@@ -15,6 +15,7 @@ struct ProblemDev {
   const double2* A[MAX_TERMS];
   int kind[MAX_TERMS];
   double param[MAX_TERMS];
+  int real[MAX_TERMS];   // 1 if A_k has no imaginary part (set at plan time)
 };
 
 template <typename T>
@@ -31,12 +32,17 @@ hipError_t launch_indicator(const double2* PfN, const double2* PfN2, const int* 
                             double tol, double* ind, unsigned char* flags, const int* sing, int N, int ndisks,
                             hipStream_t st);
 hipError_t launch_residual(const ProblemDev& pd, const double2* znode, const double2* X, const double2* F, int s,
-                           const double2* V, int L, long long xstride, int m, int nbatch, double2* R, hipStream_t st);
+                           const double2* V, int L, long long xstride, int m, int nbatch, double2* R,
+                           const int* active, hipStream_t st);
+hipError_t launch_is_real(const ProblemDev& pd, int* flags, hipStream_t st);
+hipError_t launch_refine_check(const double2* D, const double2* X, long long xstride, int len, double tol,
+                               double* dprev, int first, int* active, int* diverged, int nbatch, int* count,
+                               hipStream_t st);
 hipError_t launch_norms(const double2* R, const double2* X, long long xstride, int len, double* rn2, double* xn2,
                         int nbatch, hipStream_t st);
 hipError_t launch_axpy(double2* X, const double2* D, long long xstride, int len, const int* active, int nbatch,
                        hipStream_t st);
-hipError_t launch_coef_norms(const ProblemDev& pd, double* out, hipStream_t st);
+hipError_t launch_fill_int(int* a, int v, int n, hipStream_t st);
 hipError_t launch_mark_singular(const int* info, int nb, int* sing, hipStream_t st);
 
 }  // namespace nep

@@ -186,26 +186,37 @@ __global__ __launch_bounds__(256) void indicator_kernel(const double2* __restric
 
 // R_t = B_t - sum_k phi_k(z_t) A_k X_t over the batch; grid (row tiles of 64, column
 // tiles of 64 over the concatenated columns of all tasks).  Column c of the product is
-// column c % m of task c / m.  Matrix cores, complex128.
+// column c % m of task c / m; columns of converged tasks (active[t] == 0) are skipped.
+// Matrix cores, complex128; a real coefficient needs two of the four real products.
 __global__ __launch_bounds__(256) void residual_kernel(ProblemDev pd, const double2* __restrict__ znode,
                                                        const double2* __restrict__ X, const double2* __restrict__ F,
                                                        int s, const double2* __restrict__ V, int L,
                                                        long long xstride, int m, int nbatch,
-                                                       double2* __restrict__ R) {
+                                                       double2* __restrict__ R, const int* __restrict__ active) {
   const int n = pd.n;
   const int ncol = nbatch * m;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int l16 = lane & 15, kq = lane >> 4;
   const int rb = blockIdx.x * 64 + (wave >> 1) * 32;
   const int cb = blockIdx.y * 64 + (wave & 1) * 32;
-  // per-lane columns of the two 16-wide column blocks and their phi weights
+  // skip tiles whose tasks have all converged
+  if (active) {
+    __shared__ int s_any;
+    if (t == 0) s_any = 0;
+    __syncthreads();
+    const int c = blockIdx.y * 64 + (t & 63);
+    if (t < 64 && c < ncol && active[c / m]) s_any = 1;
+    __syncthreads();
+    if (!s_any) return;
+  }
   int ctask[2], cq[2];
   double2 ph[2][MAX_TERMS];
 #pragma unroll
   for (int bj = 0; bj < 2; ++bj) {
     const int c = cb + bj * 16 + l16;
-    ctask[bj] = (c < ncol) ? c / m : -1;
-    cq[bj] = (c < ncol) ? c % m : 0;
+    const bool ok = c < ncol && (!active || active[c / m]);
+    ctask[bj] = ok ? c / m : -1;
+    cq[bj] = ok ? c % m : 0;
 #pragma unroll
     for (int k = 0; k < MAX_TERMS; ++k)
       ph[bj][k] = (ctask[bj] >= 0 && k < pd.nterms) ? phi_eval(pd.kind[k], pd.param[k], znode[ctask[bj]])
@@ -221,6 +232,7 @@ __global__ __launch_bounds__(256) void residual_kernel(ProblemDev pd, const doub
     if (k >= pd.nterms) break;
     const double2* Ak = pd.A[k];
     if (!Ak) continue;
+    const bool real = pd.real[k] != 0;
     for (int kk = 0; kk < n; kk += 4) {
       const int j = kk + kq;
       double2 af[2], bf[2];
@@ -241,9 +253,16 @@ __global__ __launch_bounds__(256) void residual_kernel(ProblemDev pd, const doub
         for (int bj = 0; bj < 2; ++bj) {
           cre[bi][bj] = mfma16(af[bi].x, bf[bj].x, cre[bi][bj]);
           cim[bi][bj] = mfma16(af[bi].x, bf[bj].y, cim[bi][bj]);
-          cre[bi][bj] = mfma16(-af[bi].y, bf[bj].y, cre[bi][bj]);
-          cim[bi][bj] = mfma16(af[bi].y, bf[bj].x, cim[bi][bj]);
         }
+      if (!real) {
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj) {
+            cre[bi][bj] = mfma16(-af[bi].y, bf[bj].y, cre[bi][bj]);
+            cim[bi][bj] = mfma16(af[bi].y, bf[bj].x, cim[bi][bj]);
+          }
+      }
     }
   }
 #pragma unroll
@@ -266,6 +285,67 @@ __global__ __launch_bounds__(256) void residual_kernel(ProblemDev pd, const doub
         R[off] = csub<double>(bv, tx);
       }
     }
+}
+
+// flags[k] = 1 if coefficient k has no nonzero imaginary part (identity: 1)
+__global__ __launch_bounds__(256) void is_real_kernel(ProblemDev pd, int* __restrict__ flags) {
+  const int k = blockIdx.x;
+  __shared__ int s_nz;
+  if (threadIdx.x == 0) s_nz = 0;
+  __syncthreads();
+  if (pd.A[k]) {
+    const long long nn = (long long)pd.n * pd.n;
+    int nz = 0;
+    for (long long e = threadIdx.x; e < nn && !nz; e += 256) nz = pd.A[k][e].y != 0.0;
+    if (nz) s_nz = 1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) flags[k] = s_nz ? 0 : 1;
+}
+
+hipError_t launch_is_real(const ProblemDev& pd, int* flags, hipStream_t st) {
+  is_real_kernel<<<pd.nterms, 256, 0, st>>>(pd, flags);
+  return hipGetLastError();
+}
+
+// After a correction D (= dX) of active task b: keep refining while
+// ||D|| > tol ||X||; a correction that does not shrink to half of the previous one
+// (from the second sweep on) or is not finite marks the task as diverged.
+// One workgroup per task.
+__global__ __launch_bounds__(256) void refine_check_kernel(const double2* __restrict__ D, const double2* __restrict__ X,
+                                                           long long xstride, int len, double tol,
+                                                           double* __restrict__ dprev, int first,
+                                                           int* __restrict__ active, int* __restrict__ diverged,
+                                                           int* __restrict__ count) {
+  const int b = blockIdx.x;
+  if (!active[b]) return;
+  double a = 0, c = 0;
+  for (int e = threadIdx.x; e < len; e += 256) {
+    a += cabs2<double>(D[(long long)b * xstride + e]);
+    c += cabs2<double>(X[(long long)b * xstride + e]);
+  }
+  __shared__ double ra[4], rc[4];
+  a = wave_sum(a);
+  c = wave_sum(c);
+  if ((threadIdx.x & 63) == 0) { ra[threadIdx.x >> 6] = a; rc[threadIdx.x >> 6] = c; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double dn = sqrt(ra[0] + ra[1] + ra[2] + ra[3]);
+    const double xn = sqrt(rc[0] + rc[1] + rc[2] + rc[3]);
+    const bool finite = (dn == dn) && (xn == xn) && dn < 1e300 && xn < 1e300;
+    const bool bad = !finite || (!first && dn > 0.5 * dprev[b]);
+    dprev[b] = dn;
+    if (bad) { diverged[b] = 1; active[b] = 0; }
+    else if (dn <= tol * xn) active[b] = 0;
+    else atomicAdd(count, 1);
+  }
+}
+
+hipError_t launch_refine_check(const double2* D, const double2* X, long long xstride, int len, double tol,
+                               double* dprev, int first, int* active, int* diverged, int nbatch, int* count,
+                               hipStream_t st) {
+  refine_check_kernel<<<nbatch, 256, 0, st>>>(D, X, xstride, len, tol, dprev, first, active, diverged, count);
+  return hipGetLastError();
 }
 
 // per task: ||R_t||_F^2 and ||X_t||_F^2 (one workgroup per task)
@@ -311,21 +391,10 @@ hipError_t launch_mark_singular(const int* info, int nb, int* sing, hipStream_t 
   return hipGetLastError();
 }
 
-// ||A_k||_F per coefficient (one workgroup per coefficient; identity -> sqrt(n))
-__global__ __launch_bounds__(256) void coef_norm_kernel(ProblemDev pd, double* __restrict__ out) {
-  const int k = blockIdx.x;
-  const int n = pd.n;
-  if (!pd.A[k]) {
-    if (threadIdx.x == 0) out[k] = sqrt((double)n);
-    return;
-  }
-  double a = 0;
-  for (long long e = threadIdx.x; e < (long long)n * n; e += 256) a += cabs2<double>(pd.A[k][e]);
-  __shared__ double ra[4];
-  a = wave_sum(a);
-  if ((threadIdx.x & 63) == 0) ra[threadIdx.x >> 6] = a;
-  __syncthreads();
-  if (threadIdx.x == 0) out[k] = sqrt(ra[0] + ra[1] + ra[2] + ra[3]);
+// a[i] = v for i < n (a fill kernel instead of a memset node, so graph captures replay it)
+__global__ void fill_int_kernel(int* a, int v, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
 }
 
 // ----------------------------------------------------------------------------- launchers
@@ -369,9 +438,10 @@ hipError_t launch_indicator(const double2* PfN, const double2* PfN2, const int* 
 }
 
 hipError_t launch_residual(const ProblemDev& pd, const double2* znode, const double2* X, const double2* F, int s,
-                           const double2* V, int L, long long xstride, int m, int nbatch, double2* R, hipStream_t st) {
+                           const double2* V, int L, long long xstride, int m, int nbatch, double2* R,
+                           const int* active, hipStream_t st) {
   dim3 grid((unsigned)((pd.n + 63) / 64), (unsigned)((nbatch * m + 63) / 64));
-  residual_kernel<<<grid, 256, 0, st>>>(pd, znode, X, F, s, V, L, xstride, m, nbatch, R);
+  residual_kernel<<<grid, 256, 0, st>>>(pd, znode, X, F, s, V, L, xstride, m, nbatch, R, active);
   return hipGetLastError();
 }
 
@@ -387,8 +457,9 @@ hipError_t launch_axpy(double2* X, const double2* D, long long xstride, int len,
   return hipGetLastError();
 }
 
-hipError_t launch_coef_norms(const ProblemDev& pd, double* out, hipStream_t st) {
-  coef_norm_kernel<<<pd.nterms, 256, 0, st>>>(pd, out);
+hipError_t launch_fill_int(int* a, int v, int n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  fill_int_kernel<<<(n + 255) / 256, 256, 0, st>>>(a, v, n);
   return hipGetLastError();
 }
 

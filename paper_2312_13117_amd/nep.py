@@ -72,8 +72,17 @@ def lib():
     L.nep_status_str.restype = C.c_char_p
     L.nep_last_error.argtypes = [vp]
     L.nep_last_error.restype = C.c_char_p
+    fp = C.c_void_p
+    L.nep_mlp_param_count.argtypes = []
+    L.nep_mlp_workspace_floats.argtypes = [C.c_int]
+    L.nep_mlp_workspace_floats.restype = C.c_size_t
+    L.nep_mlp_forward.argtypes = [fp, fp, fp, C.c_int, fp, fp, vp]
+    L.nep_mlp_grad.argtypes = [fp, fp, fp, fp, C.c_int, fp, C.POINTER(C.c_float), fp, vp]
+    L.nep_mlp_adam.argtypes = [fp, fp, fp, fp, C.c_int, C.c_float, C.c_float, C.c_float, C.c_float, vp]
+    L.nep_mlp_features.argtypes = [fp, C.c_int, C.c_int, fp, C.c_int, fp, fp, fp, vp]
     for f in ("nep_plan", "nep_indicator", "nep_beyn", "nep_verify", "nep_copy_sums", "nep_dedup",
-              "nep_total_disks", "nep_disk_offset", "nep_get_stats"):
+              "nep_total_disks", "nep_disk_offset", "nep_get_stats", "nep_mlp_param_count", "nep_mlp_forward",
+              "nep_mlp_grad", "nep_mlp_adam", "nep_mlp_features"):
         getattr(L, f).restype = C.c_int
     _lib = L
     return L
@@ -98,7 +107,8 @@ def _ptr(a):
 
 
 def _dev_complex(x, torch):
-    """Host complex array -> contiguous complex128 tensor on cuda:0 (or None)."""
+    """Host complex array -> contiguous complex128 tensor on cuda:0 (or None); a cuda
+    complex128 tensor is used as it is."""
     if x is None:
         return None
     if isinstance(x, torch.Tensor):
@@ -106,6 +116,16 @@ def _dev_complex(x, torch):
     else:
         t = torch.from_numpy(np.ascontiguousarray(x, dtype=np.complex128)).to("cuda")
     return t.contiguous()
+
+
+def upload_problem(pr):
+    """A copy of a gen.Problem whose coefficients are device tensors (uploaded once and
+    shared by every plan entry that refers to it)."""
+    import copy
+    import torch
+    q = copy.copy(pr)
+    q.coeffs = [_dev_complex(A, torch) for A in pr.coeffs]
+    return q
 
 
 @dataclass
@@ -290,3 +310,43 @@ def pmcimb(plan: Plan, F, V, disk_problem=None) -> Result:
     order = np.lexsort((eigs.imag, eigs.real))
     return Result(ind, flags, flagged, eig, p, sv, keep, cd, cl, sig, acc, eigs[order],
                   {"indicator": st1, "beyn": st2})
+
+
+# ---------------------------------------------------------------- screener network
+def _fptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def nep_mlp_param_count() -> int:
+    return lib().nep_mlp_param_count()
+
+
+def nep_mlp_workspace_floats(B: int) -> int:
+    return lib().nep_mlp_workspace_floats(B)
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def nep_mlp_forward(params, X, idx, B, probs, work):
+    _check(lib().nep_mlp_forward(_fptr(params), _fptr(X), _fptr(idx), B, _fptr(probs), _fptr(work), _stream()))
+
+
+def nep_mlp_grad(params, X, Y, idx, B, grad, work, want_loss=False):
+    loss = C.c_float(0.0)
+    _check(lib().nep_mlp_grad(_fptr(params), _fptr(X), _fptr(Y), _fptr(idx), B, _fptr(grad),
+                              C.byref(loss) if want_loss else None, _fptr(work), _stream()))
+    return loss.value if want_loss else None
+
+
+def nep_mlp_adam(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    _check(lib().nep_mlp_adam(_fptr(params), _fptr(grad), _fptr(m), _fptr(v), step, lr, beta1, beta2, eps,
+                              _stream()))
+
+
+def nep_mlp_features(profiles, rows, ncol, stat_rows, mean, sd, X):
+    _check(lib().nep_mlp_features(_fptr(profiles), rows, ncol, _fptr(stat_rows),
+                                  0 if stat_rows is None else int(stat_rows.numel()), _fptr(mean), _fptr(sd),
+                                  _fptr(X), _stream()))
