@@ -1,16 +1,25 @@
 """Benchmark of the pmCIMb quadrature sweep on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload dense|small|...]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload dense|dense_mixed|small|delay]
 
-A step is one pass of the whole path over the workload: assembly + LU + block solve
-+ quadrature sums + indicators for every (disk, node), Beyn's extraction on the
-flagged disks, and sigma_min verification of the kept candidates.  Inputs are seeded
-synthetic matrices already resident in HBM when the timed region starts.
+A step is one pass of the whole path over the workload:
+- assembly + LU + block solve + quadrature sums + indicators for every (disk, node);
+- Beyn's extraction on the flagged disks;
+- sigma_min verification of the kept candidates, then the merge.
+Inputs are seeded synthetic matrices already resident in HBM when the timed region
+starts.
 
-Prints ONE JSON line (rank 0).  `value` = node solves per second of the whole step.
-`roofline` reports the dominant kernel (the trailing-update kernel of the batched LU)
-from the library's own per-launch HIP events on the stream it runs on.
-`cpu_baseline` times the FP64 CPU oracle on a bounded sample of the same workload.
+Prints ONE JSON line.
+- `value` = node solves per second of the whole step on the dense n = 1024 QEP in
+  complex128.
+- `mixed` = the same workload with complex64 LUs and complex128 refinement: its
+  rate, speedup, and agreement with the complex128 sweep.
+- `eigenpairs_unsaturated` = eigenpairs/s where the rank test is not cut by the probe
+  count (the workload as configured saturates every flagged disk).
+- `roofline` = the dominant kernel (trailing-update kernel of the batched LU). Its
+  durations come from the library's own HIP events recorded on the stream the
+  kernel runs on.
+- `cpu_baseline` = the FP64 CPU oracle on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -28,7 +37,7 @@ sys.path.insert(0, ROOT)
 PEAK = {"fp64": 78.6e12, "fp32": 157.3e12}
 
 
-def build_workload(name: str):
+def build_workload(name: str, delay_count: int = 8):
     import gen
     if name == "dense":
         return gen.workload_dense_qep(1024, precision=0)
@@ -36,60 +45,94 @@ def build_workload(name: str):
         return gen.workload_dense_qep(1024, precision=1)
     if name == "small":
         return gen.workload_small_qep()
+    if name == "small_L31":
+        w = gen.workload_small_qep()
+        w.opts = gen.Options(N=32, s=1, L=31)
+        w.V = [gen.probes(3, 64, 31)]
+        w.name = "qep_n64_4x4_L31"
+        return w
+    if name == "delay":
+        full = gen.workload_delay(64, precision=1)
+        full.problems = full.problems[:delay_count]
+        full.regions = full.regions[:delay_count]
+        full.F = full.F[:delay_count]
+        full.V = full.V[:delay_count]
+        full.name = f"delay_uneven_first{delay_count}"
+        return full
     raise SystemExit(f"unknown workload {name}")
 
 
-def run_gpu(w, steps: int, warmup: int):
-    import torch
-    from paper_2312_13117_amd import nep as N
-    plan = N.nep_plan(w.problems, w.regions, w.opts)
-    F = [N._dev_complex(f, torch) for f in w.F]
-    V = [N._dev_complex(v, torch) if v is not None else None for v in w.V]
-    Vl = V if all(v is not None for v in V) else None
-    disk_prob = np.zeros(plan.total_disks, np.int32)
-    for p in range(len(w.problems)):
-        first = N.lib().nep_disk_offset(plan.handle, p)
-        last = N.lib().nep_disk_offset(plan.handle, p + 1) if p + 1 < len(w.problems) else plan.total_disks
-        disk_prob[first:last] = p
-    res = None
-    for _ in range(warmup):
-        res = N.pmcimb(plan, F, Vl, disk_prob)
-    torch.cuda.synchronize()
-    times, sweep_stats = [], []
-    for _ in range(steps):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ind, flags, _, _ = N.nep_indicator(plan, F, Vl)
-        st_sweep = N.nep_get_stats(plan)
+class Runner:
+    """Plan + device inputs for one workload; step() runs the whole path once."""
+
+    def __init__(self, w):
+        import torch
+        from paper_2312_13117_amd import nep as N
+        self.N, self.w = N, w
+        self.plan = N.nep_plan(w.problems, w.regions, w.opts)
+        self.F = [N._dev_complex(f, torch) for f in w.F]
+        V = [N._dev_complex(v, torch) if v is not None else None for v in w.V]
+        self.V = V if all(v is not None for v in V) else None
+        self.disk_prob = np.zeros(self.plan.total_disks, np.int32)
+        for p in range(len(w.problems)):
+            first = N.lib().nep_disk_offset(self.plan.handle, p)
+            last = N.lib().nep_disk_offset(self.plan.handle, p + 1) if p + 1 < len(w.problems) else \
+                self.plan.total_disks
+            self.disk_prob[first:last] = p
+
+    def step(self):
+        N = self.N
+        ind, flags, _, _ = N.nep_indicator(self.plan, self.F, self.V)
+        st = N.nep_get_stats(self.plan)
         flagged = np.nonzero(flags)[0]
         cand, cdisk = [], []
-        if Vl is not None and len(flagged):
-            eig, p, sv, keep, _, _ = N.nep_beyn(plan, flagged)
+        if self.V is not None and len(flagged):
+            eig, p, sv, keep, _, _ = N.nep_beyn(self.plan, flagged)
             for i, d in enumerate(flagged):
                 for k in range(int(p[i])):
                     if keep[i, k]:
                         cand.append(eig[i, k])
                         cdisk.append(d)
-        nver = 0
+        eigs = np.zeros(0, np.complex128)
         if cand:
-            sig, acc = N.nep_verify(plan, disk_prob[np.asarray(cdisk)], cand)
+            sig, acc = N.nep_verify(self.plan, self.disk_prob[np.asarray(cdisk)], cand)
             al = np.asarray(cand)[acc]
-            nver = int(N.nep_dedup(al, sig[acc]).sum()) if len(al) else 0
+            if len(al):
+                eigs = al[N.nep_dedup(al, sig[acc])]
+        return {"flags": flags, "ind": ind, "ncand": len(cand), "eigs": eigs, "stats": st}
+
+    def sums(self):
+        if len(self.w.problems) != 1:
+            return None
+        return self.N.nep_copy_sums(self.plan, 0, self.plan.total_disks)
+
+    def close(self):
+        self.N.nep_destroy(self.plan)
+
+
+def timed(runner, steps: int, warmup: int):
+    import torch
+    for _ in range(warmup):
+        runner.step()
+    torch.cuda.synchronize()
+    times, outs = [], []
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        o = runner.step()
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
-        sweep_stats.append(st_sweep)
-        res = (flags, len(cand), nver)
-    N.nep_destroy(plan)
-    return times, sweep_stats, res
+        outs.append(o)
+    k = int(np.argsort(times)[len(times) // 2])
+    return float(np.median(times)), outs[k]
 
 
 def cpu_baseline(w, max_disks: int):
-    """FP64 CPU oracle on a bounded sample: the first `max_disks` disks of problem 0."""
+    """FP64 CPU oracle on a bounded sample: `max_disks` disks spread over problem 0."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     prob, reg = w.problems[0], w.regions[0]
     disks = oracle.cover(reg)
-    # sample disks spread over the region
     idx = np.linspace(0, len(disks) - 1, max_disks).round().astype(int)
     t0 = time.perf_counter()
     for d in idx:
@@ -97,10 +140,23 @@ def cpu_baseline(w, max_disks: int):
         oracle.sweep_disk(prob, dk.c, dk.r, w.opts.N, w.F[0], w.V[0])
     dt = time.perf_counter() - t0
     solves = len(idx) * w.opts.N
+    nrhs = w.F[0].shape[1] + (0 if w.V[0] is None else w.V[0].shape[1])
     return {"value": solves / dt, "unit": "solves/s", "cores": threads, "kind": "oracle",
-            "sample": f"{len(idx)} disks x {w.opts.N} nodes of problem 0 (n={prob.n}, "
-                      f"{w.F[0].shape[1]}+{0 if w.V[0] is None else w.V[0].shape[1]} right-hand sides), "
-                      f"{dt:.1f} s"}
+            "sample": f"{len(idx)} disks x {w.opts.N} nodes of problem 0 (n={prob.n}, {nrhs} right-hand sides, "
+                      f"complex128 LAPACK gesv per node), {dt:.1f} s"}
+
+
+def phase_dict(st):
+    return {k: st[k] for k in ("ms_assemble", "ms_lu", "ms_solve", "ms_refine", "ms_sums", "ms_total")}
+
+
+def roofline(st, prec):
+    achieved = st["gemm_flops"] / (st["ms_gemm"] * 1e-3) if st["ms_gemm"] > 0 else 0.0
+    return {"kernel": "lu_gemm_kernel<update> (trailing update of the batched LU)", "bound": "mfma",
+            "achieved": achieved / 1e12, "peak": PEAK[prec] / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / PEAK[prec], "traffic": None, "launches": st["gemm_launches"],
+            "avg_launch_ms": st["ms_gemm"] / max(1, st["gemm_launches"]),
+            "flops_per_launch": st["gemm_flops"] / max(1, st["gemm_launches"])}
 
 
 def main():
@@ -109,23 +165,27 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="dense")
+    ap.add_argument("--delay-count", type=int, default=8)
     ap.add_argument("--cpu-disks", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-eigen", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
-    w = build_workload(args.workload)
-    times, stats, (flags, ncand, nver) = run_gpu(w, args.steps, args.warmup)
-    T = float(np.median(times))
-    st = stats[len(stats) // 2]
-    nsolves = st["node_solves"]
+    w = build_workload(args.workload, args.delay_count)
     prec = "fp32" if w.opts.precision == 1 else "fp64"
-    achieved = st["gemm_flops"] / (st["ms_gemm"] * 1e-3) if st["ms_gemm"] > 0 else 0.0
+    r = Runner(w)
+    T, o = timed(r, args.steps, args.warmup)
+    sums64 = r.sums() if (args.workload == "dense" and not args.no_mixed) else None
+    r.close()
+    st = o["stats"]
     lu_rate = st["lu_flops"] / (st["ms_lu"] * 1e-3) if st["ms_lu"] > 0 else 0.0
     out = {
-        "metric": "quadrature solves/s (node LU + block solve + sums) of the whole pmCIMb step",
-        "value": nsolves / T,
+        "metric": "quadrature solves/s (node assembly + LU + block solve + sums per (disk, node)) over the "
+                  "whole pmCIMb step; eigenpairs/s alongside",
+        "value": st["node_solves"] / T,
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -136,20 +196,51 @@ def main():
         "vs_baseline": None,
         "dtype": "c128" if prec == "fp64" else "c64+c128",
         "data": "synthetic (seeded Gaussian coefficients and probes)",
-        "config": {"workload": w.name, "n": w.problems[0].n, "disks": int(len(flags)), "nodes_per_disk": w.opts.N,
-                   "probes": w.opts.s, "beyn_columns": w.opts.L, "precision": prec},
-        "eigenpairs_per_s": nver / T,
-        "verified_eigenpairs": nver,
-        "flagged_disks": int(np.sum(flags)),
-        "candidates": ncand,
-        "phase_ms": {k: st[k] for k in ("ms_assemble", "ms_lu", "ms_solve", "ms_refine", "ms_sums", "ms_total")},
+        "config": {"workload": w.name, "n": sorted(set(p.n for p in w.problems)), "disks": int(len(o["flags"])),
+                   "nodes_per_disk": w.opts.N, "probes": w.opts.s, "beyn_columns": w.opts.L, "precision": prec,
+                   "problems": len(w.problems)},
+        "eigenpairs_per_s": len(o["eigs"]) / T,
+        "verified_eigenpairs": int(len(o["eigs"])),
+        "flagged_disks": int(np.sum(o["flags"])),
+        "candidates": o["ncand"],
+        "phase_ms": phase_dict(st),
         "lu_tflops": lu_rate / 1e12,
         "lu_frac_of_peak": lu_rate / PEAK[prec],
-        "roofline": {"kernel": "lu_gemm_kernel<update> (trailing update of the batched LU)", "bound": "mfma",
-                     "achieved": achieved / 1e12, "peak": PEAK[prec] / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK[prec], "traffic": None,
-                     "launches": st["gemm_launches"], "avg_launch_ms": st["ms_gemm"] / max(1, st["gemm_launches"])},
+        "roofline": roofline(st, prec),
     }
+    if args.workload == "dense" and not args.no_mixed:
+        wm = build_workload("dense_mixed")
+        rm = Runner(wm)
+        Tm, om = timed(rm, args.steps, args.warmup)
+        sm = rm.sums()
+        rm.close()
+        stm = om["stats"]
+        # agreement of the mixed sweep with the complex128 sweep: moments of flagged
+        # disks (no cancellation there) and identical flags
+        fl = np.nonzero(o["flags"])[0]
+        rel = 0.0
+        for d in fl:
+            for a, b in ((sm[2][d], sums64[2][d]), (sm[3][d], sums64[3][d])):
+                rel = max(rel, float(np.linalg.norm(a - b) / np.linalg.norm(b)))
+        lu_m = stm["lu_flops"] / (stm["ms_lu"] * 1e-3) if stm["ms_lu"] > 0 else 0.0
+        out["mixed"] = {"workload": wm.name, "value": stm["node_solves"] / Tm, "ms_per_step": Tm * 1e3,
+                        "speedup_vs_fp64": T / Tm, "flags_identical": bool(np.array_equal(om["flags"], o["flags"])),
+                        "max_rel_moment_diff_vs_fp64_flagged": rel, "refine_sweeps": stm["refine_sweeps"],
+                        "refine_fallbacks": stm["refine_fallbacks"], "phase_ms": phase_dict(stm),
+                        "lu_tflops": lu_m / 1e12, "lu_frac_of_peak": lu_m / PEAK["fp32"],
+                        "roofline": roofline(stm, "fp32"), "verified_eigenpairs": int(len(om["eigs"]))}
+    if args.workload in ("dense", "dense_mixed") and not args.no_eigen:
+        # eigenpairs where the rank test is not saturated (31 probe columns, n = 64)
+        eo = {}
+        for tag, precision in (("fp64", 0), ("mixed", 1)):
+            we = build_workload("small_L31")
+            we.opts.precision = precision
+            re_ = Runner(we)
+            Te, oe = timed(re_, max(3, args.steps), 1)
+            re_.close()
+            eo[tag] = {"eigenpairs": int(len(oe["eigs"])), "ms_per_step": Te * 1e3,
+                       "eigenpairs_per_s": len(oe["eigs"]) / Te}
+        out["eigenpairs_unsaturated"] = {"workload": "qep_n64_4x4_L31", **eo}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_disks)
     print(json.dumps(out))
