@@ -140,8 +140,8 @@ typedef struct nep_stats {
   double ms_solve;           /* triangular solves                                     */
   double ms_refine;          /* residuals + correction solves                         */
   double ms_sums;            /* quadrature sums, profiles, indicators                 */
-  double ms_gemm;            /* the trailing-update kernel alone                      */
-  int64_t gemm_launches;     /* its launch count                                      */
+  double ms_gemm;            /* the trailing-update kernel alone (timed launches)     */
+  int64_t gemm_launches;     /* its timed launches (the first 2048 of the call)       */
   double gemm_flops;         /* its algorithmic flops over those launches             */
 } nep_stats;
 
@@ -168,7 +168,9 @@ nep_status nep_plan(const nep_problem* probs, int nprob, const nep_region* regs,
  *   V_dev      NULL, or V_dev[p] = device complex128 n_p x L (Beyn probes)
  *   ind        host double [total_disks * s]: I_q of eq (3.1) per probe column, read
  *              as || P f|_N ./ P f|_{N/2} ||_2 / sqrt(n) (elementwise ratio); a
- *              non-finite ratio is reported as +inf
+ *              non-finite ratio is reported as +inf; a column whose half-rule sum is at
+ *              most 1e-9 S_q, S_q = sum_j |w_j| ||x_j[:, q]||, is reported as 0 (both sums
+ *              are then rounding noise, and so is their ratio)
  *   flags      host uint8 [total_disks]: 1 iff max_q I_q > tol_ind (or non-finite)
  *   profiles   host double [total_disks * N * s] or NULL: ||x_j[:, q]||_2 per node
  * The half rule uses the 1-based even nodes x_2, x_4, ..., x_N with weights 2 w_j.

@@ -129,6 +129,7 @@ class DiskSweep:
     C0: Optional[np.ndarray]  # n x L : eq (3.2)
     C1: Optional[np.ndarray]  # n x L : eq (3.3)
     profile: np.ndarray      # N x s : ||x_j|| per node and probe column
+    scale: np.ndarray        # s : sum_j |w_j| ||x_j[:, q]||, the size of the summands
 
 
 def sweep_disk(prob: Problem, c: complex, r: float, N: int, F: np.ndarray,
@@ -161,19 +162,32 @@ def sweep_disk(prob: Problem, c: complex, r: float, N: int, F: np.ndarray,
             C0 += w[j] * XV
             C1 += (w[j] * z[j]) * XV
         profile[j] = np.linalg.norm(x, axis=0)
-    return DiskSweep(PfN, PfN2, C0, C1, profile)
+    scale = (np.abs(w)[:, None] * profile).sum(axis=0)
+    return DiskSweep(PfN, PfN2, C0, C1, profile, scale)
 
 
-def indicator(PfN: np.ndarray, PfN2: np.ndarray) -> Tuple[float, np.ndarray]:
+# A half-rule sum below this fraction of its summand scale is rounding noise.
+NOISE_FLOOR = 1e-9
+
+
+def indicator(PfN: np.ndarray, PfN2: np.ndarray, scale: Optional[np.ndarray] = None,
+              floor: float = NOISE_FLOOR) -> Tuple[float, np.ndarray]:
     """Ratio indicator of eq (3.1), read as in the appendix's indicator routine: the
     elementwise ratio P f|_N ./ P f|_{N/2}, its 2-norm, divided by sqrt(n).  With s > 1
     probe columns the disk's indicator is the maximum over columns.  A non-finite
-    column (0/0 or x/0) gives +inf, which flags the disk."""
+    column (0/0 or x/0) gives +inf, which flags the disk.
+
+    Reading (floating point): for a disk far from every eigenvalue both sums fall below
+    the rounding level of their summands, and their ratio is noise of order one, which
+    contradicts the stated I ~ e^{-CN/2}.  A column whose half-rule sum is at most
+    floor * scale_q (scale_q = sum_j |w_j| ||x_j[:, q]||) therefore has I_q = 0."""
     n = PfN.shape[0]
     with np.errstate(divide="ignore", invalid="ignore"):
         ratio = PfN / PfN2
         Iq = np.linalg.norm(ratio, axis=0) / math.sqrt(n)
     Iq = np.where(np.isfinite(Iq), Iq, np.inf)
+    if scale is not None:
+        Iq = np.where(np.linalg.norm(PfN2, axis=0) <= floor * np.asarray(scale), 0.0, Iq)
     return float(np.max(Iq)), Iq
 
 
@@ -292,7 +306,7 @@ def pmcimb(prob: Problem, reg: Region, opts: Options, F: np.ndarray,
     for d in idx:
         dk = disks[d]
         sw = sweep_disk(prob, dk.c, dk.r, opts.N, F, V)
-        I, Iq = indicator(sw.PfN, sw.PfN2)
+        I, Iq = indicator(sw.PfN, sw.PfN2, sw.scale)
         sweeps.append(sw)
         ind.append(I)
         ind_cols.append(Iq)

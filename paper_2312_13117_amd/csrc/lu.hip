@@ -906,9 +906,10 @@ hipError_t lu_factor_batch(c2<T>* W, long long mstride, int n, int nbatch, int* 
     if (timed) hipEventRecord(tm->ev[2 * tm->npairs], st);
     lu_gemm_kernel<T, GEMM_UPDATE><<<dim3((unsigned)(groups * 8 * tc * tc)), 256, 0, st>>>(
         W, mstride, n, k0, nbk, s, nbatch, tc, tc, perm, perm_stride, Linv, inv_stride);
-    if (timed) { hipEventRecord(tm->ev[2 * tm->npairs + 1], st); tm->npairs++; }
-    if (tm) {
-      tm->gemm_launches += 1;
+    if (timed) {
+      hipEventRecord(tm->ev[2 * tm->npairs + 1], st);
+      tm->npairs++;
+      tm->gemm_launches += 1;   // launches and flops of the timed launches only
       tm->gemm_flops += 8.0 * (double)m * (double)m * (double)nbk * (double)nbatch;
     }
   }

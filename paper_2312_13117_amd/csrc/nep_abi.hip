@@ -95,7 +95,7 @@ struct nep_plan {
   std::vector<double2> h_z, h_w;      // nodes and weights, nd x N
   int nmax = 0;
   // device copies
-  DevBuf dev_dn, dev_ix, dev_iy, dev_soff, dev_w, dev_z;
+  DevBuf dev_dn, dev_ix, dev_iy, dev_soff, dev_w, dev_z, dev_r;
   DevBuf PfN, PfN2, C0, C1, prof, ind, flags;
   DevBuf X, xoff, tnode, dlist;
   // LU workspaces: two for the sweep (own streams), one complex128 on the plan stream
@@ -286,6 +286,7 @@ extern "C" nep_status nep_plan(const nep_problem* probs, int nprob, const nep_re
   PCHK(up(P->dev_ix, P->d_ix.data(), sizeof(int) * nd));
   PCHK(up(P->dev_iy, P->d_iy.data(), sizeof(int) * nd));
   PCHK(up(P->dev_soff, P->d_soff.data(), sizeof(long long) * nd));
+  PCHK(up(P->dev_r, P->d_r.data(), sizeof(double) * nd));
   PCHK(up(P->dev_w, P->h_w.data(), sizeof(double2) * nd * N));
   PCHK(up(P->dev_z, P->h_z.data(), sizeof(double2) * nd * N));
   PCHK(P->PfN.alloc(sizeof(double2) * P->sum_rows * s));
@@ -359,7 +360,7 @@ extern "C" void nep_destroy(nep_plan_t* P) {
   if (!P) return;
   hipStreamSynchronize(P->st);
   for (auto& w : P->ws) if (w.st) hipStreamSynchronize(w.st);
-  DevBuf* bufs[] = {&P->dev_dn, &P->dev_ix, &P->dev_iy, &P->dev_soff, &P->dev_w, &P->dev_z, &P->PfN, &P->PfN2,
+  DevBuf* bufs[] = {&P->dev_dn, &P->dev_ix, &P->dev_iy, &P->dev_soff, &P->dev_w, &P->dev_z, &P->dev_r, &P->PfN, &P->PfN2,
                     &P->C0, &P->C1, &P->prof, &P->ind, &P->flags, &P->X, &P->xoff, &P->tnode, &P->dlist,
                     &P->sing, &P->bscr, &P->beig, &P->bp, &P->bsv, &P->bkeep, &P->bstat, &P->bvec,
                     &P->vest};
@@ -588,7 +589,8 @@ extern "C" nep_status nep_indicator(nep_plan_t* P, const void* const* F_dev, con
   if (r != NEP_OK) return r;
   HIPCHK(P, launch_indicator(P->PfN.as<double2>(), P->PfN2.as<double2>(), P->dev_dn.as<int>(),
                              P->dev_soff.as<long long>(), P->opt.s, P->opt.tol_ind, P->ind.as<double>(),
-                             P->flags.as<unsigned char>(), P->sing.as<int>(), P->opt.N, P->nd, P->st));
+                             P->flags.as<unsigned char>(), P->sing.as<int>(), P->opt.N, P->prof.as<double>(),
+                             P->dev_r.as<double>(), INDICATOR_NOISE_FLOOR, P->nd, P->st));
   tmark(P, PH_TOTAL, false, P->st);
   HIPCHK(P, hipMemcpyAsync(ind, P->ind.p, sizeof(double) * P->nd * P->opt.s, hipMemcpyDeviceToHost, P->st));
   HIPCHK(P, hipMemcpyAsync(flags, P->flags.p, P->nd, hipMemcpyDeviceToHost, P->st));

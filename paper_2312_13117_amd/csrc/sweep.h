@@ -29,8 +29,10 @@ hipError_t launch_sums(const double2* X, long long xstride, const double2* wts, 
 hipError_t launch_profile(const double2* X, long long xstride, int N, int n, int s, int m, double* prof,
                           const int* disk_ids, int ndisks, hipStream_t st);
 hipError_t launch_indicator(const double2* PfN, const double2* PfN2, const int* dn, const long long* soff, int s,
-                            double tol, double* ind, unsigned char* flags, const int* sing, int N, int ndisks,
-                            hipStream_t st);
+                            double tol, double* ind, unsigned char* flags, const int* sing, int N,
+                            const double* prof, const double* rad, double floor, int ndisks, hipStream_t st);
+// a half-rule sum at or below this fraction of its summand scale is rounding noise
+constexpr double INDICATOR_NOISE_FLOOR = 1e-9;
 hipError_t launch_residual(const ProblemDev& pd, const double2* znode, const double2* X, const double2* F, int s,
                            const double2* V, int L, long long xstride, int m, int nbatch, double2* R,
                            const int* active, hipStream_t st);

@@ -146,28 +146,34 @@ __global__ __launch_bounds__(256) void profile_kernel(const double2* __restrict_
   }
 }
 
-// one workgroup per disk: I_q = ||PfN[:,q] ./ PfN2[:,q]||_2 / sqrt(n); +inf if not finite
+// one workgroup per disk: I_q = ||PfN[:,q] ./ PfN2[:,q]||_2 / sqrt(n); +inf if not
+// finite; 0 when ||PfN2[:,q]|| <= floor * S_q with S_q = (r/N) sum_j ||x_j[:,q]|| the size
+// of the summands (both sums are then rounding noise and their ratio carries no
+// information about eigenvalues inside)
 __global__ __launch_bounds__(256) void indicator_kernel(const double2* __restrict__ PfN,
                                                         const double2* __restrict__ PfN2, const int* __restrict__ dn,
                                                         const long long* __restrict__ soff, int s, double tol,
                                                         double* __restrict__ ind, unsigned char* __restrict__ flags,
-                                                        const int* __restrict__ sing, int N) {
+                                                        const int* __restrict__ sing, int N,
+                                                        const double* __restrict__ prof,
+                                                        const double* __restrict__ rad, double floor) {
   const int d = blockIdx.x;
   const int n = dn[d];
   const double2* a = PfN + soff[d] * s;
   const double2* b = PfN2 + soff[d] * s;
-  __shared__ double red[4][8];
-  double acc[8];
-  for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+  __shared__ double red[4][16];
+  double acc[8], den[8];
+  for (int q = 0; q < 8; ++q) { acc[q] = 0.0; den[q] = 0.0; }
   for (int i = threadIdx.x; i < n; i += 256)
     for (int q = 0; q < s; ++q) {
-      const double2 num = a[(long long)i * s + q], den = b[(long long)i * s + q];
+      const double2 num = a[(long long)i * s + q], dd = b[(long long)i * s + q];
       // |num / den|^2 = |num|^2 / |den|^2 (0/0 and x/0 give NaN / inf, caught below)
-      acc[q] += cabs2<double>(num) / cabs2<double>(den);
+      acc[q] += cabs2<double>(num) / cabs2<double>(dd);
+      den[q] += cabs2<double>(dd);
     }
   for (int q = 0; q < s; ++q) {
-    const double v = wave_sum(acc[q]);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][q] = v;
+    const double v = wave_sum(acc[q]), w = wave_sum(den[q]);
+    if ((threadIdx.x & 63) == 0) { red[threadIdx.x >> 6][q] = v; red[threadIdx.x >> 6][8 + q] = w; }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -175,6 +181,13 @@ __global__ __launch_bounds__(256) void indicator_kernel(const double2* __restric
     for (int q = 0; q < s; ++q) {
       double v = sqrt((red[0][q] + red[1][q] + red[2][q] + red[3][q]) / (double)n);
       if (!(v <= 1.7976931348623157e308)) v = __builtin_inf();
+      if (prof) {
+        double S = 0.0;
+        for (int j = 0; j < N; ++j) S += prof[((long long)d * N + j) * s + q];
+        S *= rad[d] / N;
+        const double nb = sqrt(red[0][8 + q] + red[1][8 + q] + red[2][8 + q] + red[3][8 + q]);
+        if (nb <= floor * S) v = 0.0;
+      }
       ind[(long long)d * s + q] = v;
       if (v > tol) flag = true;
     }
@@ -431,9 +444,9 @@ hipError_t launch_profile(const double2* X, long long xstride, int N, int n, int
 }
 
 hipError_t launch_indicator(const double2* PfN, const double2* PfN2, const int* dn, const long long* soff, int s,
-                            double tol, double* ind, unsigned char* flags, const int* sing, int N, int ndisks,
-                            hipStream_t st) {
-  indicator_kernel<<<ndisks, 256, 0, st>>>(PfN, PfN2, dn, soff, s, tol, ind, flags, sing, N);
+                            double tol, double* ind, unsigned char* flags, const int* sing, int N,
+                            const double* prof, const double* rad, double floor, int ndisks, hipStream_t st) {
+  indicator_kernel<<<ndisks, 256, 0, st>>>(PfN, PfN2, dn, soff, s, tol, ind, flags, sing, N, prof, rad, floor);
   return hipGetLastError();
 }
 

@@ -84,7 +84,7 @@ def test_sums_ragged_sizes(N, n, Nn, s, L, prec):
         check_sums(N, plan, prob, reg, opts, F, V, 1e-12 if prec == 0 else 1e-11)
         for d, dk in enumerate(oracle.cover(reg)):
             sw = oracle.sweep_disk(prob, dk.c, dk.r, Nn, F, None)
-            I, Iq = oracle.indicator(sw.PfN, sw.PfN2)
+            I, Iq = oracle.indicator(sw.PfN, sw.PfN2, sw.scale)
             assert flags[d] == (I > opts.tol_ind)
             assert np.allclose(prof[d], sw.profile, rtol=1e-10 if prec == 0 else 1e-9)
     finally:
@@ -283,12 +283,12 @@ def test_dense_workload_sampled(N):
     try:
         ind, flags, _, st = N.nep_indicator(plan, w.F, w.V)
         assert plan.total_disks == 256
-        sample = [119, 0]   # next to the origin (flagged) and the empty corner disk
-        check_sums(N, plan, w.problems[0], w.regions[0], w.opts, w.F[0], w.V[0], 1e-12, disks=sample)
+        sample = [119, 0, 255, 15]   # next to the origin (flagged) and the four far corners
+        check_sums(N, plan, w.problems[0], w.regions[0], w.opts, w.F[0], w.V[0], 1e-12, disks=sample[:2])
         cov = oracle.cover(w.regions[0])
         for d in sample:
             sw = oracle.sweep_disk(w.problems[0], cov[d].c, cov[d].r, 32, w.F[0], None)
-            I, _ = oracle.indicator(sw.PfN, sw.PfN2)
+            I, _ = oracle.indicator(sw.PfN, sw.PfN2, sw.scale)
             assert flags[d] == (I > 0.1)
     finally:
         N.nep_destroy(plan)

@@ -142,3 +142,25 @@ def test_cover_geometry():
     assert d[0].r == pytest.approx(np.hypot(0.25, 0.375))
     assert (d[17].ix, d[17].iy) == (1, 1)
     assert d[17].cx == pytest.approx(-3 + 0.75) and d[17].cy == pytest.approx(-6 + 0.375 * 3)
+
+
+def test_indicator_noise_floor():
+    # all roots far outside: both sums sink below the rounding level of the summands
+    # (q^N ~ 1e-40), their raw ratio is noise of order one, the floor reports 0; a disk
+    # with a root inside is unaffected by the floor
+    n = 12
+    roots = 4.0 + 0.3 * np.arange(n) + 0.1j
+    prob = gen.rotated_diagonal(roots, 5)
+    F = gen.probes(6, n, 2)
+    sw = oracle.sweep_disk(prob, 0j, 0.25, 32, F, None)
+    assert np.all(np.linalg.norm(sw.PfN2, axis=0) < 1e-12 * sw.scale)
+    I_raw, _ = oracle.indicator(sw.PfN, sw.PfN2)
+    I, Iq = oracle.indicator(sw.PfN, sw.PfN2, sw.scale)
+    assert I == 0.0 and np.all(Iq == 0.0)
+    roots2 = roots.copy()
+    roots2[0] = 0.05 - 0.02j
+    prob2 = gen.rotated_diagonal(roots2, 5)
+    sw2 = oracle.sweep_disk(prob2, 0j, 0.25, 32, F, None)
+    a, _ = oracle.indicator(sw2.PfN, sw2.PfN2)
+    b, _ = oracle.indicator(sw2.PfN, sw2.PfN2, sw2.scale)
+    assert a == b and b > 0.1
