@@ -66,6 +66,8 @@ class Options:
     tol_ver: float = 1e-6
     precision: int = 0   # 0 = complex128 LU, 1 = complex64 LU + complex128 refinement
     max_refine: int = 3
+    batch: int = 0       # node matrices per batch (0 = library default)
+    streams: int = 0     # worker streams (0 = library default)
 
 
 @dataclass

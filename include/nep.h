@@ -112,7 +112,9 @@ typedef struct nep_region {
  *   tol_ver    accept lambda iff sigma_min(T(lambda)) < tol_ver (Step 3)
  *   precision  NEP_FP64 or NEP_FP32_REFINE
  *   max_refine maximum refinement sweeps for NEP_FP32_REFINE (0..8)
- *   batch      node matrices factored together (0 = chosen by the library)  */
+ *   batch      node matrices factored together (0 = chosen by the library)
+ *   streams    worker streams the batches alternate over (1 or 2; 0 = 2): with two,
+ *              one batch's panel steps overlap the other batch's trailing updates  */
 typedef struct nep_options {
   int N;
   int s;
@@ -123,6 +125,7 @@ typedef struct nep_options {
   int precision;
   int max_refine;
   int batch;
+  int streams;
 } nep_options;
 
 /* Counters and phase timings of the last call on a plan (device time measured with

@@ -494,9 +494,8 @@ __global__ __launch_bounds__(256) void lu_gemm_kernel(c2<T>* __restrict__ W, lon
     Li = Linv + (long long)b * inv_stride + (long long)step * NBMAX * NBMAX;
   }
 
-  // C tile (update mode) fetched up front; the product accumulates from zero and is
-  // subtracted at the end, so the C loads overlap the matrix-core work.
-  c2<T> cv[2][2][4];
+  // accumulators start from C (update: C - A B) or zero (TRSM: A B); the C loads are in
+  // flight together with the first operand chunks
   acc4<T> cre[2][2], cim[2][2];
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
@@ -504,11 +503,17 @@ __global__ __launch_bounds__(256) void lu_gemm_kernel(c2<T>* __restrict__ W, lon
     for (int bj = 0; bj < 2; ++bj) {
       cre[bi][bj] = acc_zero<T>();
       cim[bi][bj] = acc_zero<T>();
-      const int col = cb + bj * 16 + l16;
+      if (MODE == GEMM_UPDATE) {
+        const int col = cb + bj * 16 + l16;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = rb + bi * 16 + acc_row<T>(lane, r);
-        cv[bi][bj][r] = (MODE == GEMM_UPDATE && row < n && col < n) ? A[(long long)row * n + col] : czero<T>();
+        for (int r = 0; r < 4; ++r) {
+          const int row = rb + bi * 16 + acc_row<T>(lane, r);
+          if (row < n && col < n) {
+            const c2<T> v = A[(long long)row * n + col];
+            cre[bi][bj][r] = v.x;
+            cim[bi][bj][r] = v.y;
+          }
+        }
       }
     }
 
@@ -526,48 +531,80 @@ __global__ __launch_bounds__(256) void lu_gemm_kernel(c2<T>* __restrict__ W, lon
     }
   }
 
-  auto load_frags = [&](int kk, c2<T>* af, c2<T>* bf) {
-    const int k = kk + kq;
+  // Operand chunks of KC = 16 columns of A (64 x 16) and rows of B (16 x 64) are loaded
+  // cooperatively (4 entries per thread each), double-buffered in LDS, one chunk ahead.
+  constexpr int KC = 16, AP = KC + 1;
+  __shared__ c2<T> As[2][64][AP];
+  __shared__ c2<T> Bs[2][KC][64];
+  const int wr = wave >> 1, wc = wave & 1;
+  const int arow = t >> 2, akq = (t & 3) * 4;     // A chunk: row, first of 4 k
+  const int bk = t >> 4, bcq = (t & 15) * 4;      // B chunk: k row, first of 4 columns
+  c2<T> ra[4], rbv[4];
+  auto load_chunk = [&](int kc) {
+    const int row = R0 + arow;
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi) {
-      const int row = rb + bi * 16 + l16;
+    for (int u = 0; u < 4; ++u) {
+      const int k = kc + akq + u;
       if (MODE == GEMM_UPDATE)
-        af[bi] = (row < n && k < nbk) ? A[(long long)row * n + k0 + k] : czero<T>();
+        ra[u] = (row < n && k < nbk) ? A[(long long)row * n + k0 + k] : czero<T>();
       else
-        af[bi] = (row < kend && k < nbk) ? Li[(row - k0) * NBMAX + k] : czero<T>();
+        ra[u] = (row < kend && k < nbk) ? Li[(row - k0) * NBMAX + k] : czero<T>();
     }
+    const int k = kc + bk;
+    const int srow = (k < nbk) ? ((MODE == GEMM_UPDATE) ? (k0 + k) : s_src[k]) : 0;
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj) {
-      const int col = cb + bj * 16 + l16;
-      if (k < nbk && col < n) {
-        const int srow = (MODE == GEMM_UPDATE) ? (k0 + k) : s_src[k];
-        bf[bj] = A[(long long)srow * n + col];
-      } else {
-        bf[bj] = czero<T>();
-      }
+    for (int u = 0; u < 4; ++u) {
+      const int col = C0 + bcq + u;
+      rbv[u] = (k < nbk && col < n) ? A[(long long)srow * n + col] : czero<T>();
     }
   };
-  c2<T> af[2], bf[2], an[2], bn[2];
-  load_frags(0, af, bf);
-  for (int kk = 0; kk < nbk; kk += 4) {
-    if (kk + 4 < nbk) load_frags(kk + 4, an, bn);
-    // real parts of A first, then imaginary parts: dependent products 8 apart
+  auto store_chunk = [&](int buf) {
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+    for (int u = 0; u < 4; ++u) {
+      As[buf][arow][akq + u] = ra[u];
+      Bs[buf][bk][bcq + u] = rbv[u];
+    }
+  };
+  const int nch = (nbk + KC - 1) / KC;
+  load_chunk(0);
+  store_chunk(0);
+  if (nch > 1) load_chunk(KC);
+  __syncthreads();
+  for (int c = 0; c < nch; ++c) {
+    const int buf = c & 1;
 #pragma unroll
-      for (int bj = 0; bj < 2; ++bj) {
-        cre[bi][bj] = mfma16(af[bi].x, bf[bj].x, cre[bi][bj]);
-        cim[bi][bj] = mfma16(af[bi].x, bf[bj].y, cim[bi][bj]);
+    for (int ks = 0; ks < KC / 4; ++ks) {
+      const int k = ks * 4 + kq;
+      c2<T> af[2], bf[2];
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi) af[bi] = As[buf][wr * 32 + bi * 16 + l16][k];
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) bf[bj] = Bs[buf][k][wc * 32 + bj * 16 + l16];
+      if (MODE == GEMM_UPDATE) {
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi) af[bi] = cmk<T>(-af[bi].x, -af[bi].y);   // C - A B
       }
+      // real parts of A first, then imaginary parts: dependent products 8 apart
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+      for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-      for (int bj = 0; bj < 2; ++bj) {
-        cre[bi][bj] = mfma16(-af[bi].y, bf[bj].y, cre[bi][bj]);
-        cim[bi][bj] = mfma16(af[bi].y, bf[bj].x, cim[bi][bj]);
-      }
+        for (int bj = 0; bj < 2; ++bj) {
+          cre[bi][bj] = mfma16(af[bi].x, bf[bj].x, cre[bi][bj]);
+          cim[bi][bj] = mfma16(af[bi].x, bf[bj].y, cim[bi][bj]);
+        }
 #pragma unroll
-    for (int u = 0; u < 2; ++u) { af[u] = an[u]; bf[u] = bn[u]; }
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+          cre[bi][bj] = mfma16(-af[bi].y, bf[bj].y, cre[bi][bj]);
+          cim[bi][bj] = mfma16(af[bi].y, bf[bj].x, cim[bi][bj]);
+        }
+    }
+    if (c + 1 < nch) {
+      store_chunk(buf ^ 1);                  // chunk c+1 (its readers finished at the last barrier)
+      if (c + 2 < nch) load_chunk((c + 2) * KC);
+    }
+    __syncthreads();
   }
   if (MODE == GEMM_TRSM) __syncthreads();   // every wave has read its operands
 
@@ -579,12 +616,7 @@ __global__ __launch_bounds__(256) void lu_gemm_kernel(c2<T>* __restrict__ W, lon
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = rb + bi * 16 + acc_row<T>(lane, r);
-        if (row < rlim && col < n) {
-          const c2<T> o = (MODE == GEMM_UPDATE)
-                              ? cmk<T>(cv[bi][bj][r].x - cre[bi][bj][r], cv[bi][bj][r].y - cim[bi][bj][r])
-                              : cmk<T>(cre[bi][bj][r], cim[bi][bj][r]);
-          A[(long long)row * n + col] = o;
-        }
+        if (row < rlim && col < n) A[(long long)row * n + col] = cmk<T>(cre[bi][bj][r], cim[bi][bj][r]);
       }
     }
   if (MODE == GEMM_TRSM) {
@@ -832,48 +864,66 @@ __global__ __launch_bounds__(256) void lu_solve_kernel(const c2<T>* __restrict__
     }
   } else {
     // A = P_0^T L_0 ... P_{S-1}^T L_{S-1} U  =>  A^H x = b:  w = U^{-H} b, then for
-    // s = S-1..0: w_blk = inv(L11)^H (w_blk - L21^H w_rest), w = P_s^T w.
-    __shared__ c2<T> Z[NB][MMAX];
+    // s = S-1..0: w_blk = inv(L11)^H (w_blk - L21^H w_rest), w = P_s^T w.  The
+    // operands are staged conjugate-transposed into the same LDS tiles.
+    auto stage_AH = [&](const c2<T>* src, long long ld, int nr, int kc) {
+      // Ash[i][k] = conj(src[k * ld + i]) for i < nr, k < kc
+      for (int e = t; e < NB * KC; e += 256) {
+        const int k = e / NB, i = e % NB;
+        const c2<T> v = (i < nr && k < kc) ? src[(long long)k * ld + i] : czero<T>();
+        Ash[i][k] = cmk<T>(v.x, -v.y);
+      }
+    };
     for (int s = 0; s < nsteps; ++s) {   // U^H is lower triangular: forward over steps
       const int k0 = s * NB, nbk = min(NB, n - k0);
-      for (int e = t; e < nbk * m; e += 256) {
-        const int i = e / m, c = e % m;
-        c2<T> acc = ccast<T, double>(Xb[(long long)(k0 + i) * m + c]);
-        for (int j = 0; j < k0; ++j) {
-          const c2<T> u = A[(long long)j * n + k0 + i];
-          acc = csub<T>(acc, cconjmul<T>(u, ccast<T, double>(Xb[(long long)j * m + c])));
-        }
-        Z[i][c] = acc;
+      // z_blk = b_blk - sum_{j < k0} U[j, blk]^H w_j
+      load_acc_X(k0, nbk);
+      for (int kc = 0; kc < k0; kc += KC) {
+        const int kk = min(KC, k0 - kc);
+        __syncthreads();
+        stage_AH(A + (long long)kc * n + k0, n, nbk, kk);
+        stage_X(kc, kk, 0);
+        __syncthreads();
+        tile.template mma<true>(Ash, Bsh, 0, kk);
       }
       __syncthreads();
+      store_acc_B();
+      for (int i = nbk + t / MMAX; i < NB; i += 256 / MMAX) Bsh[i][t % MMAX] = czero<T>();
       const c2<T>* Ui = Uinv + (long long)b * inv_stride + (long long)s * NB * NB;
-      for (int e = t; e < nbk * m; e += 256) {
-        const int i = e / m, c = e % m;
-        c2<T> acc = czero<T>();
-        for (int j = 0; j <= i; ++j) acc = cadd<T>(acc, cconjmul<T>(Ui[j * NB + i], Z[j][c]));
-        Xb[(long long)(k0 + i) * m + c] = ccast<double, T>(acc);
+      tile.zero();
+      for (int kc = 0; kc < nbk; kc += KC) {
+        __syncthreads();
+        stage_AH(Ui + (long long)kc * NB, NB, nbk, min(KC, nbk - kc));   // (inv U11)^H
+        __syncthreads();
+        tile.template mma<false>(Ash, Bsh, kc, min(KC, nbk - kc));
       }
+      store_acc_X(k0, nbk);
       __syncthreads();
     }
     for (int s = nsteps - 1; s >= 0; --s) {
       const int k0 = s * NB, nbk = min(NB, n - k0), kend = k0 + nbk;
-      for (int e = t; e < nbk * m; e += 256) {
-        const int i = e / m, c = e % m;
-        c2<T> acc = ccast<T, double>(Xb[(long long)(k0 + i) * m + c]);
-        for (int r = kend; r < n; ++r) {
-          const c2<T> l = A[(long long)r * n + k0 + i];
-          acc = csub<T>(acc, cconjmul<T>(l, ccast<T, double>(Xb[(long long)r * m + c])));
-        }
-        Z[i][c] = acc;
+      // z = w_blk - L21^H w_rest
+      load_acc_X(k0, nbk);
+      for (int kc = kend; kc < n; kc += KC) {
+        const int kk = min(KC, n - kc);
+        __syncthreads();
+        stage_AH(A + (long long)kc * n + k0, n, nbk, kk);
+        stage_X(kc, kk, 0);
+        __syncthreads();
+        tile.template mma<true>(Ash, Bsh, 0, kk);
       }
       __syncthreads();
+      store_acc_B();
+      for (int i = nbk + t / MMAX; i < NB; i += 256 / MMAX) Bsh[i][t % MMAX] = czero<T>();
       const c2<T>* Li = Linv + (long long)b * inv_stride + (long long)s * NB * NB;
-      for (int e = t; e < nbk * m; e += 256) {
-        const int i = e / m, c = e % m;
-        c2<T> acc = czero<T>();
-        for (int j = i; j < nbk; ++j) acc = cadd<T>(acc, cconjmul<T>(Li[j * NB + i], Z[j][c]));
-        Xb[(long long)(k0 + i) * m + c] = ccast<double, T>(acc);
+      tile.zero();
+      for (int kc = 0; kc < nbk; kc += KC) {
+        __syncthreads();
+        stage_AH(Li + (long long)kc * NB, NB, nbk, min(KC, nbk - kc));   // (inv L11)^H
+        __syncthreads();
+        tile.template mma<false>(Ash, Bsh, kc, min(KC, nbk - kc));
       }
+      store_acc_X(k0, nbk);
       load_perm(s);
       permute(true);
     }

@@ -106,6 +106,7 @@ struct nep_plan {
   DevBuf bscr, beig, bp, bsv, bkeep, bstat, bvec;
   DevBuf vest;
   int batch = 0;
+  int nstreams = 2;
   bool swept = false, swept_with_V = false;
   const void* const* last_V = nullptr;
   std::vector<const void*> last_F;
@@ -208,6 +209,7 @@ extern "C" nep_status nep_plan(const nep_problem* probs, int nprob, const nep_re
   if (o.L < 0 || o.L > 32 || o.s + o.L > 32) return bad("L must be 0..32 with s + L <= 32");
   if (o.precision != NEP_FP64 && o.precision != NEP_FP32_REFINE) return bad("unknown precision");
   if (o.max_refine < 0 || o.max_refine > 8) return bad("max_refine must be 0..8");
+  if (o.streams < 0 || o.streams > 2) return bad("streams must be 0, 1 or 2");
   if (!(o.tol_ind >= 0) || !(o.tol_svd >= 0) || !(o.tol_ver >= 0)) return bad("tolerances must be >= 0");
   for (int p = 0; p < nprob; ++p) {
     const nep_problem& q = probs[p];
@@ -313,7 +315,8 @@ extern "C" nep_status nep_plan(const nep_problem* probs, int nprob, const nep_re
   const int B = P->batch, nm = P->nmax;
   const int steps = (nm + LU_NB - 1) / LU_NB;
   const size_t eb = elem_bytes(o.precision);
-  for (int k = 0; k < 2; ++k) {
+  P->nstreams = (o.streams == 1) ? 1 : 2;
+  for (int k = 0; k < P->nstreams; ++k) {
     Workspace& w = P->ws[k];
     PCHK(hipStreamCreateWithFlags(&w.st, hipStreamNonBlocking));
     w.own = true;
@@ -522,7 +525,7 @@ static nep_status run_sweep(nep_plan_t* P, const SweepCall& sc, bool* singular, 
   HIPCHK(P, hipMemcpyAsync(P->dlist.p, sc.disks.data(), sizeof(int) * nl, hipMemcpyHostToDevice, P->st));
   // fork: both worker streams start after the uploads above
   HIPCHK(P, hipEventRecord(P->ev_fork, P->st));
-  for (auto& w : P->ws) HIPCHK(P, hipStreamWaitEvent(w.st, P->ev_fork, 0));
+  for (int q = 0; q < P->nstreams; ++q) HIPCHK(P, hipStreamWaitEvent(P->ws[q].st, P->ev_fork, 0));
   double2* X = P->X.as<double2>();
   const double2* tn = P->tnode.as<double2>();
   int k = 0;   // batch counter: batches alternate between the two workspaces
@@ -535,7 +538,7 @@ static nep_status run_sweep(nep_plan_t* P, const SweepCall& sc, bool* singular, 
     const long long ntask = (long long)(lj - li) * N;
     for (long long t0 = 0; t0 < ntask; t0 += P->batch, ++k) {
       const int nb = (int)std::min<long long>(P->batch, ntask - t0);
-      Workspace& w = P->ws[k & 1];
+      Workspace& w = P->ws[P->nstreams == 2 ? (k & 1) : 0];
       nep_status r = sweep_batch(P, w, prob, tn + (long long)li * N + t0, X + xoff[li] + t0 * (long long)n * m, nb,
                                  sc, P->sing.as<int>() + (long long)li * N + t0, fallback);
       if (r != NEP_OK) return r;
@@ -543,7 +546,7 @@ static nep_status run_sweep(nep_plan_t* P, const SweepCall& sc, bool* singular, 
     li = lj;
   }
   // join
-  for (int q = 0; q < 2; ++q) {
+  for (int q = 0; q < P->nstreams; ++q) {
     HIPCHK(P, hipEventRecord(P->ev_join[q], P->ws[q].st));
     HIPCHK(P, hipStreamWaitEvent(P->st, P->ev_join[q], 0));
   }
