@@ -37,7 +37,13 @@ sys.path.insert(0, ROOT)
 PEAK = {"fp64": 78.6e12, "fp32": 157.3e12}
 
 
-def build_workload(name: str, delay_count: int = 8):
+def build_workload(name: str, delay_count: int = 8, pivot: int = 0):
+    w = _workload(name, delay_count)
+    w.opts.pivot = pivot
+    return w
+
+
+def _workload(name: str, delay_count: int):
     import gen
     if name == "dense":
         return gen.workload_dense_qep(1024, precision=0)
@@ -170,11 +176,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-eigen", action="store_true")
+    ap.add_argument("--pivot", choices=("partial", "tournament"), default="partial",
+                    help="pivot choice of the node LU panels")
     args = ap.parse_args()
+    pivot = 0 if args.pivot == "partial" else 1
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
-    w = build_workload(args.workload, args.delay_count)
+    w = build_workload(args.workload, args.delay_count, pivot)
     prec = "fp32" if w.opts.precision == 1 else "fp64"
     r = Runner(w)
     T, o = timed(r, args.steps, args.warmup)
@@ -198,7 +207,7 @@ def main():
         "data": "synthetic (seeded Gaussian coefficients and probes)",
         "config": {"workload": w.name, "n": sorted(set(p.n for p in w.problems)), "disks": int(len(o["flags"])),
                    "nodes_per_disk": w.opts.N, "probes": w.opts.s, "beyn_columns": w.opts.L, "precision": prec,
-                   "problems": len(w.problems)},
+                   "problems": len(w.problems), "pivot": args.pivot},
         "eigenpairs_per_s": len(o["eigs"]) / T,
         "verified_eigenpairs": int(len(o["eigs"])),
         "flagged_disks": int(np.sum(o["flags"])),
@@ -209,7 +218,7 @@ def main():
         "roofline": roofline(st, prec),
     }
     if args.workload == "dense" and not args.no_mixed:
-        wm = build_workload("dense_mixed")
+        wm = build_workload("dense_mixed", pivot=pivot)
         rm = Runner(wm)
         Tm, om = timed(rm, args.steps, args.warmup)
         sm = rm.sums()
@@ -233,7 +242,7 @@ def main():
         # eigenpairs where the rank test is not saturated (31 probe columns, n = 64)
         eo = {}
         for tag, precision in (("fp64", 0), ("mixed", 1)):
-            we = build_workload("small_L31")
+            we = build_workload("small_L31", pivot=pivot)
             we.opts.precision = precision
             re_ = Runner(we)
             Te, oe = timed(re_, max(3, args.steps), 1)

@@ -68,6 +68,7 @@ class Options:
     max_refine: int = 3
     batch: int = 0       # node matrices per batch (0 = library default)
     streams: int = 0     # worker streams (0 = library default)
+    pivot: int = 0       # 0 = partial pivoting, 1 = tournament pivoting
 
 
 @dataclass

@@ -73,8 +73,20 @@ enum {
 
 /* Arithmetic of the node LU factorisations. */
 enum {
-  NEP_FP64 = 0,        /* complex128 LU with partial pivoting                          */
+  NEP_FP64 = 0,        /* complex128 LU                                                */
   NEP_FP32_REFINE = 1  /* complex64 LU, then complex128 residual iterative refinement    */
+};
+
+/* Pivot choice of the node LU factorisations (both give P T(z_j) = L U).
+ *   NEP_PIVOT_PARTIAL     LAPACK-style partial pivoting (largest |Re|+|Im| in the
+ *                         column, first row on ties), one workgroup per panel
+ *   NEP_PIVOT_TOURNAMENT  each 64-column panel picks its pivot rows by a tournament:
+ *                         128-row chunks run partial pivoting in parallel and their
+ *                         winners are merged pairwise (communication-avoiding LU);
+ *                         pays off when few matrices are factored at once        */
+enum {
+  NEP_PIVOT_PARTIAL = 0,
+  NEP_PIVOT_TOURNAMENT = 1
 };
 
 /* The nonlinear eigenvalue problem T(lambda) x = 0 (eq (1.1)) in split form
@@ -114,7 +126,8 @@ typedef struct nep_region {
  *   max_refine maximum refinement sweeps for NEP_FP32_REFINE (0..8)
  *   batch      node matrices factored together (0 = chosen by the library)
  *   streams    worker streams the batches alternate over (1 or 2; 0 = 2): with two,
- *              one batch's panel steps overlap the other batch's trailing updates  */
+ *              one batch's panel steps overlap the other batch's trailing updates
+ *   pivot      NEP_PIVOT_PARTIAL (0) or NEP_PIVOT_TOURNAMENT (1)                   */
 typedef struct nep_options {
   int N;
   int s;
@@ -126,6 +139,7 @@ typedef struct nep_options {
   int max_refine;
   int batch;
   int streams;
+  int pivot;
 } nep_options;
 
 /* Counters and phase timings of the last call on a plan (device time measured with

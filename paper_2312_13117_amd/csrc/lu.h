@@ -21,10 +21,19 @@ struct LuTimers {
   double gemm_flops = 0;
 };
 
+// Pivot choice of the panel factorisation: LAPACK-style partial pivoting (one
+// workgroup per panel), or tournament pivoting (row chunks factored in parallel,
+// their pivot candidates merged pairwise; the factors then satisfy P A = L U with
+// the tournament's pivot rows).
+enum { LU_PIVOT_PARTIAL = 0, LU_PIVOT_TOURNAMENT = 1 };
+
+// Scratch bytes per matrix for lu_factor_batch (either pivot choice).
+size_t lu_factor_scratch_bytes(int n, size_t elem_bytes);
+
 template <typename T>
-hipError_t lu_factor_batch(c2<T>* W, long long mstride, int n, int nbatch, int* ipiv, int* perm,
+hipError_t lu_factor_batch(c2<T>* W, long long mstride, int n, int nbatch, void* scratch, int* perm,
                            long long perm_stride, c2<T>* Linv, c2<T>* Uinv, long long inv_stride, int* info,
-                           hipStream_t st, LuTimers* tm);
+                           int pivot, hipStream_t st, LuTimers* tm);
 
 template <typename T>
 hipError_t lu_solve_batch(const c2<T>* W, long long mstride, int n, int nbatch, const int* perm,

@@ -454,18 +454,362 @@ __global__ __launch_bounds__(NT) void lu_panel_kernel(c2<T>* __restrict__ W, lon
   }
 }
 
+
+// ----------------------------------------------------------------------------- tournament panel
+// Panel factorisation with tournament pivoting (communication-avoiding LU: partial
+// pivoting inside row chunks, winners merged pairwise, the final 64 rows factored).
+// The pivot rows differ from plain partial pivoting; the result is still P A = L U
+// with |multipliers| bounded in practice, and every pass over the panel is parallel.
+//
+// gepp_chunk: partial pivoting on up to 128 candidate rows x nbk <= 64 panel columns
+// held in registers: 512 threads, thread t owns chunk row i = t/4 and the 16 columns
+// 16*(t&3) .. +15, so the four threads of a row form a quad of lanes.  Rows are never
+// moved; a row is marked when chosen.  Produces the pivot rows in order (win) and,
+// for the chosen rows, the factored values in place (multipliers left of the row's
+// pivot column, U from it on).  Every value read is an original panel value.
+//
+// One workgroup barrier per column: each wave reduces its best row for column j to a
+// packed key (magnitude bits | row), and the lanes holding that row publish it to LDS;
+// after the barrier every thread picks the best of the 8 keys and reads the pivot row
+// from that wave's slot.  Slots are double-buffered by column parity.
+//
+// Key: the upper bits of |Re| + |Im| (IEEE bits of a non-negative value order like
+// unsigned integers), 12 (double) / 15 (float) mantissa bits kept, and 255 - i in the
+// low byte so that equal magnitudes go to the lowest row; 0 = no candidate.  The pivot
+// is therefore the row of largest magnitude up to a relative 2^-12 (threshold
+// pivoting), the first such row on ties.
+constexpr int GEPP_ROWS = 128, GEPP_Q = 4, GEPP_NT = GEPP_ROWS * GEPP_Q, GEPP_H = 64 / GEPP_Q,
+              GEPP_NW = GEPP_NT / 64;
+
+template <typename T>
+struct Gepp {
+  c2<T> a[GEPP_H];
+  int row;       // global row id of this thread's candidate row (-1: none)
+  bool chosen;
+};
+
+template <typename T>
+struct GeppShared {
+  c2<T> rowbuf[2][GEPP_NW][64];
+  c2<T> rinv[2][GEPP_NW];          // 1 / (the wave candidate's column-j entry)
+  unsigned keys[2][GEPP_NW];
+  int win[64];
+  int singular;
+};
+
+__device__ inline unsigned gepp_key(double m, int i) {
+  const unsigned hi = (unsigned)((unsigned long long)__double_as_longlong(m) >> 32);
+  return (hi & ~255u) | (unsigned)(255 - i);
+}
+__device__ inline unsigned gepp_key(float m, int i) {
+  return ((unsigned)__float_as_uint(m) & ~255u) | (unsigned)(255 - i);
+}
+
+__device__ inline unsigned dpp_max(unsigned v, int ctrl_sel) {
+  // ctrl_sel picks a constant DPP control: quad xor 1, quad xor 2, half-row mirror, row mirror
+  unsigned o;
+  switch (ctrl_sel) {
+    case 0: o = (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xf, 0xf, false); break;
+    case 1: o = (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xf, 0xf, false); break;
+    case 2: o = (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xf, 0xf, false); break;
+    default: o = (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xf, 0xf, false); break;
+  }
+  return v > o ? v : o;
+}
+
+// maximum over the 64 lanes, returned to every lane (all lanes must be active)
+__device__ inline unsigned wave_max_u32(unsigned v) {
+  v = dpp_max(v, 0);
+  v = dpp_max(v, 1);
+  v = dpp_max(v, 2);
+  v = dpp_max(v, 3);
+  const unsigned a = (unsigned)__builtin_amdgcn_readlane((int)v, 0), b = (unsigned)__builtin_amdgcn_readlane((int)v, 16);
+  const unsigned c = (unsigned)__builtin_amdgcn_readlane((int)v, 32), d = (unsigned)__builtin_amdgcn_readlane((int)v, 48);
+  const unsigned x = a > b ? a : b, y = c > d ? c : d;
+  return x > y ? x : y;
+}
+
+// value of lane `src` (0..3, uniform) of each quad, to all four lanes of the quad
+__device__ inline int quad_bcast(int v, int src) {
+  switch (src) {
+    case 0: return __builtin_amdgcn_update_dpp(0, v, 0x00, 0xf, 0xf, false);
+    case 1: return __builtin_amdgcn_update_dpp(0, v, 0x55, 0xf, 0xf, false);
+    case 2: return __builtin_amdgcn_update_dpp(0, v, 0xAA, 0xf, 0xf, false);
+    default: return __builtin_amdgcn_update_dpp(0, v, 0xFF, 0xf, 0xf, false);
+  }
+}
+__device__ inline double quad_bcast(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = quad_bcast((int)(b & 0xffffffffll), src), hi = quad_bcast((int)(b >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ inline float quad_bcast(float v, int src) { return __int_as_float(quad_bcast(__float_as_int(v), src)); }
+
+template <typename T>
+__device__ __forceinline__ void gepp_chunk(Gepp<T>& g, int nbk, GeppShared<T>& sh) {
+  constexpr int H = GEPP_H;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int h = t & (GEPP_Q - 1), i = t / GEPP_Q;
+  g.chosen = false;
+  bool done = false;
+  for (int jb = 0; jb < GEPP_Q && !done; ++jb) {        // column quarter, owned by lanes h == jb
+#pragma clang loop unroll(full)
+    for (int ju = 0; ju < H; ++ju) {                    // static register index of column j
+      const int j = jb * H + ju;
+      if (done || j >= nbk) continue;                   // uniform
+      const int buf = j & 1;
+      const bool live = g.row >= 0 && !g.chosen;
+      const c2<T> ajj = g.a[ju];
+      unsigned key = 0;
+      if (h == jb && live) key = gepp_key(cabs1<T>(ajj), i);
+      // the reciprocal is formed by every owner lane while the reduction runs, so
+      // that no division sits between the barrier and the update
+      const bool nzj = ajj.x != T(0) || ajj.y != T(0);
+      const c2<T> r = nzj ? crcp<T>(ajj) : czero<T>();
+      const unsigned wk = wave_max_u32(key);
+      if (wk != 0 && i == 255 - (int)(wk & 255u)) {
+#pragma unroll
+        for (int u = 0; u < H; ++u) sh.rowbuf[buf][wave][h * H + u] = g.a[u];
+        if (h == jb) sh.rinv[buf][wave] = r;
+      }
+      if (lane == 0) sh.keys[buf][wave] = wk;
+      __syncthreads();
+      unsigned best = 0;
+      int bw = 0;
+#pragma unroll
+      for (int w = 0; w < GEPP_NW; ++w) {
+        const unsigned k = sh.keys[buf][w];
+        if (k > best) { best = k; bw = w; }
+      }
+      if (best == 0) { done = true; continue; }         // no candidate rows left (uniform)
+      const int pi = 255 - (int)(best & 255u);
+      if ((best & ~255u) == 0u && t == 0) sh.singular = 1;
+      if (i == pi) {
+        g.chosen = true;
+        if (h == 0) sh.win[j] = g.row;
+      }
+      const c2<T>* prow = sh.rowbuf[buf][bw];
+      const c2<T> rp = sh.rinv[buf][bw];
+      const bool upd = g.row >= 0 && !g.chosen;
+      // multiplier of this row (zero for rows not updated and for a zero pivot)
+      c2<T> l = (h == jb && upd) ? cmul<T>(ajj, rp) : czero<T>();
+      l.x = quad_bcast(l.x, jb);
+      l.y = quad_bcast(l.y, jb);
+      // rank-1 correction of the columns right of j (u > ju in the owner's quarter,
+      // every column of the quarters after it); column j takes the multiplier
+      if (upd) {
+#pragma unroll
+        for (int u = 0; u < H; ++u) {
+          if (u == ju && h == jb) {
+            g.a[u] = l;
+          } else if ((u > ju ? h >= jb : h > jb) && h * H + u < nbk) {
+            const c2<T> p = prow[h * H + u];
+            g.a[u].x = fma(-l.x, p.x, fma(l.y, p.y, g.a[u].x));
+            g.a[u].y = fma(-l.x, p.y, fma(-l.y, p.x, g.a[u].y));
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();                                      // win / singular complete
+}
+
+template <typename T>
+__device__ __forceinline__ void gepp_load(Gepp<T>& g, const c2<T>* A, int n, int k0, int nbk, int row) {
+  const int h = threadIdx.x % GEPP_Q;
+  g.row = row;
+#pragma unroll
+  for (int u = 0; u < GEPP_H; ++u) {
+    const int c = h * GEPP_H + u;
+    g.a[u] = (row >= 0 && c < nbk) ? A[(long long)row * n + k0 + c] : czero<T>();
+  }
+}
+
+template <typename T>
+__device__ void gepp_init(GeppShared<T>& sh) {
+  const int t = threadIdx.x;
+  if (t < 64) sh.win[t] = -1;
+  if (t == 0) sh.singular = 0;
+}
+
+// T1: grid nbatch x nch, chunk c of matrix b: rows k0 + 128c .. +127 -> 64 nominations
+template <typename T>
+__global__ __launch_bounds__(GEPP_NT) void tslu_local_kernel(const c2<T>* __restrict__ W, long long mstride,
+                                                             int n, int k0, int nbk, int nch,
+                                                             int* __restrict__ cand) {
+  const int b = blockIdx.x / nch, c = blockIdx.x % nch;
+  const c2<T>* A = W + (long long)b * mstride;
+  __shared__ GeppShared<T> sh;
+  const int t = threadIdx.x;
+  gepp_init<T>(sh);
+  Gepp<T> g;
+  const int r = k0 + c * GEPP_ROWS + t / GEPP_Q;
+  gepp_load<T>(g, A, n, k0, nbk, r < n ? r : -1);
+  __syncthreads();
+  gepp_chunk<T>(g, nbk, sh);
+  if (t < 64) cand[((long long)b * 64 + c) * 64 + t] = sh.win[t];
+}
+
+// T2: grid nbatch x npair, merge candidate sets 2p and 2p+1 (of nin) -> set p
+template <typename T>
+__global__ __launch_bounds__(GEPP_NT) void tslu_merge_kernel(const c2<T>* __restrict__ W, long long mstride,
+                                                             int n, int k0, int nbk, int nin,
+                                                             const int* __restrict__ cin, int* __restrict__ cout) {
+  const int npair = (nin + 1) / 2;
+  const int b = blockIdx.x / npair, p = blockIdx.x % npair;
+  const c2<T>* A = W + (long long)b * mstride;
+  __shared__ GeppShared<T> sh;
+  const int t = threadIdx.x;
+  gepp_init<T>(sh);
+  const int i = t / GEPP_Q;
+  const int set = 2 * p + (i >> 6);
+  const int row = (set < nin) ? cin[((long long)b * 64 + set) * 64 + (i & 63)] : -1;
+  Gepp<T> g;
+  gepp_load<T>(g, A, n, k0, nbk, row);
+  __syncthreads();
+  gepp_chunk<T>(g, nbk, sh);
+  if (t < 64) cout[((long long)b * 64 + p) * 64 + t] = sh.win[t];
+}
+
+// T3: one workgroup per matrix: partial pivoting on the final <= 128 candidates (the
+// union of <= 2 sets, or all rows when m <= 128), then
+//   - the step's row exchange as a compact permutation (top rows k0+k <- winner k;
+//     the displaced top rows fill the positions the winners vacate below kend),
+//   - the displaced top rows' panel values saved (the L21 pass reads them there),
+//   - the winners' factored rows (L11 \ U11) written to the top rows,
+//   - inv(L11) and inv(U11).
+template <typename T, int NB>
+__global__ __launch_bounds__(GEPP_NT) void tslu_root_kernel(c2<T>* __restrict__ W, long long mstride, int n, int k0,
+                                                        int nbk, int step, int nin, const int* __restrict__ cin,
+                                                        int* __restrict__ perm, long long perm_stride,
+                                                        c2<T>* __restrict__ saved, c2<T>* __restrict__ Linv,
+                                                        c2<T>* __restrict__ Uinv, long long inv_stride,
+                                                        int* __restrict__ info) {
+  const int b = blockIdx.x;
+  c2<T>* A = W + (long long)b * mstride;
+  // the GEPP state and the triangle workspace are used one after the other
+  union RootShared {
+    GeppShared<T> g;
+    struct { c2<T> M[NB][NB + 1]; c2<T> S[TB][NB]; } tri;
+  };
+  __shared__ RootShared shu;
+  __shared__ int win[64];
+  __shared__ int s_pos[2 * NB], s_src[2 * NB], s_cnt, s_sing;
+  __shared__ unsigned char s_top[NB];
+  auto Mtri = shu.tri.M;
+  auto Stmp = shu.tri.S;
+  const int t = threadIdx.x;
+  gepp_init<T>(shu.g);
+  const int i = t / GEPP_Q;
+  int row;
+  if (nin == 0) {
+    row = (k0 + i < n) ? k0 + i : -1;    // m <= 128: all rows are candidates
+  } else {
+    const int set = i >> 6;
+    row = (set < nin) ? cin[((long long)b * 64 + set) * 64 + (i & 63)] : -1;
+  }
+  Gepp<T> g;
+  gepp_load<T>(g, A, n, k0, nbk, row);
+  __syncthreads();
+  gepp_chunk<T>(g, nbk, shu.g);
+  if (t < 64) win[t] = shu.g.win[t];
+  if (t == 0) s_sing = shu.g.singular;
+  __syncthreads();
+  // ---- compact permutation
+  if (t == 0) {
+    const int kend = k0 + nbk;
+    for (int k = 0; k < nbk; ++k) s_top[k] = 0;
+    for (int k = 0; k < nbk; ++k)
+      if (win[k] >= k0 && win[k] < kend) s_top[win[k] - k0] = 1;
+    int cnt = nbk, d = 0;
+    for (int k = 0; k < nbk; ++k) { s_pos[k] = k0 + k; s_src[k] = win[k]; }
+    for (int k = 0; k < nbk; ++k) {
+      if (win[k] >= kend) {
+        while (d < nbk - 1 && s_top[d]) ++d;   // next top row that was not chosen
+        s_pos[cnt] = win[k];
+        s_src[cnt] = k0 + d;
+        ++d;
+        ++cnt;
+      }
+    }
+    s_cnt = cnt;
+    if (s_sing && info[b] == 0) info[b] = k0 + 1;
+  }
+  __syncthreads();
+  {
+    int* P = perm + (long long)b * perm_stride + (long long)step * (1 + 4 * NB);
+    for (int e = t; e < 2 * NB; e += GEPP_NT) {
+      P[1 + e] = (e < s_cnt) ? s_pos[e] : -1;
+      P[1 + 2 * NB + e] = (e < s_cnt) ? s_src[e] : -1;
+    }
+    if (t == 0) P[0] = s_cnt;
+  }
+  // ---- save the displaced top rows (original panel values), slot e - nbk
+  c2<T>* sv = saved + (long long)b * NB * NB;
+  for (int e = t; e < (s_cnt - nbk) * nbk; e += GEPP_NT) {
+    const int q = e / nbk, c = e % nbk;
+    sv[q * NB + c] = A[(long long)s_src[nbk + q] * n + k0 + c];
+  }
+  __syncthreads();
+  // ---- winners' factored rows -> top rows; the inverses of L11 and U11 are taken
+  // from the registers (the written rows are not read back)
+  int k = -1;
+  if (g.chosen)
+    for (int q = 0; q < nbk; ++q)
+      if (win[q] == g.row) k = q;
+  const int h = t % GEPP_Q;
+  auto fill = [&]() {
+    if (k >= 0) {
+#pragma unroll
+      for (int u = 0; u < GEPP_H; ++u) {
+        const int c = h * GEPP_H + u;
+        if (c < nbk) Mtri[k][c] = g.a[u];
+      }
+    }
+  };
+  if (k >= 0) {
+#pragma unroll
+    for (int u = 0; u < GEPP_H; ++u) {
+      const int c = h * GEPP_H + u;
+      if (c < nbk) A[(long long)(k0 + k) * n + k0 + c] = g.a[u];
+    }
+  }
+  fill();
+  __syncthreads();
+  c2<T>* Li = Linv + (long long)b * inv_stride + (long long)step * NB * NB;
+  c2<T>* Ui = Uinv + (long long)b * inv_stride + (long long)step * NB * NB;
+  inv_unit_lower<T, NB, GEPP_NT>(Mtri, Stmp, nbk);
+  for (int e = t; e < NB * NB; e += GEPP_NT) {
+    const int r = e / NB, c = e % NB;
+    c2<T> v = czero<T>();
+    if (r < nbk && c < nbk) v = (r == c) ? cmk<T>(T(1), T(0)) : (c < r ? Mtri[r][c] : czero<T>());
+    Li[e] = v;
+  }
+  __syncthreads();
+  fill();
+  __syncthreads();
+  inv_upper<T, NB, GEPP_NT>(Mtri, Stmp, nbk);
+  for (int e = t; e < NB * NB; e += GEPP_NT) {
+    const int r = e / NB, c = e % NB;
+    Ui[e] = (r < nbk && c < nbk && c >= r) ? Mtri[r][c] : czero<T>();
+  }
+}
+
 // ----------------------------------------------------------------------------- matrix-core steps
 // 256 threads = 4 waves; a workgroup owns a 64 x 64 tile, a wave a 32 x 32 quarter
 // (2 x 2 blocks of 16 x 16, real and imaginary accumulators).  Workgroup ids are
 // spread round-robin over the 8 XCDs; all tiles of one matrix are mapped to one XCD
 // so the panels L21 / U12 it re-reads stay in that XCD's L2.
-enum { GEMM_UPDATE = 0, GEMM_TRSM = 1 };
+// GEMM_PANEL (tournament panel): rows below the diagonal block, L21 = A21 inv(U11),
+// A21 read from the row's source under the step's row exchange.
+enum { GEMM_UPDATE = 0, GEMM_TRSM = 1, GEMM_PANEL = 2 };
 
 template <typename T, int MODE>
 __global__ __launch_bounds__(256) void lu_gemm_kernel(c2<T>* __restrict__ W, long long mstride, int n, int k0,
                                                       int nbk, int step, int nbatch, int tiles_r, int tiles_c,
                                                       const int* __restrict__ perm, long long perm_stride,
-                                                      const c2<T>* __restrict__ Linv, long long inv_stride) {
+                                                      const c2<T>* __restrict__ Linv, long long inv_stride,
+                                                      const c2<T>* __restrict__ saved = nullptr) {
   constexpr int NBMAX = 64;
   const int wg = blockIdx.x;
   const int xcd = wg & 7, slot = wg >> 3;
@@ -477,9 +821,10 @@ __global__ __launch_bounds__(256) void lu_gemm_kernel(c2<T>* __restrict__ W, lon
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   c2<T>* A = W + (long long)b * mstride;
   const int kend = k0 + nbk;
-  const int R0 = (MODE == GEMM_UPDATE ? kend : k0) + tr * 64;
-  const int C0 = kend + tcn * 64;
-  const int rlim = (MODE == GEMM_UPDATE) ? n : kend;
+  const int R0 = (MODE == GEMM_TRSM ? k0 : kend) + tr * 64;
+  const int C0 = (MODE == GEMM_PANEL ? k0 : kend) + tcn * 64;
+  const int rlim = (MODE == GEMM_TRSM) ? kend : n;
+  const int clim = (MODE == GEMM_PANEL) ? kend : n;
   const int rb = R0 + (wave >> 1) * 32, cb = C0 + (wave & 1) * 32;
   const int l16 = lane & 15, kq = lane >> 4;
 
@@ -492,6 +837,22 @@ __global__ __launch_bounds__(256) void lu_gemm_kernel(c2<T>* __restrict__ W, lon
     for (int i = t; i < 2 * NBMAX; i += 256) { s_pos[i] = P[1 + i]; s_src[i] = P[1 + 2 * NBMAX + i]; }
     __syncthreads();
     Li = Linv + (long long)b * inv_stride + (long long)step * NBMAX * NBMAX;
+  }
+  // GEMM_PANEL: Linv carries inv(U11); s_slot[i] = saved-row slot of tile row i, or -1
+  __shared__ int s_slot[64];
+  const c2<T>* sv = nullptr;
+  if (MODE == GEMM_PANEL) {
+    const int* P = perm + (long long)b * perm_stride + (long long)step * (1 + 4 * NBMAX);
+    if (t < 64) s_slot[t] = -1;
+    __syncthreads();
+    const int cnt = P[0];
+    if (t < cnt - nbk) {
+      const int pos = P[1 + nbk + t];
+      if (pos >= R0 && pos < R0 + 64) s_slot[pos - R0] = t;
+    }
+    __syncthreads();
+    Li = Linv + (long long)b * inv_stride + (long long)step * NBMAX * NBMAX;
+    sv = saved + (long long)b * NBMAX * NBMAX;
   }
 
   // accumulators start from C (update: C - A B) or zero (TRSM: A B); the C loads are in
@@ -547,10 +908,19 @@ __global__ __launch_bounds__(256) void lu_gemm_kernel(c2<T>* __restrict__ W, lon
       const int k = kc + akq + u;
       if (MODE == GEMM_UPDATE)
         ra[u] = (row < n && k < nbk) ? A[(long long)row * n + k0 + k] : czero<T>();
-      else
+      else if (MODE == GEMM_TRSM)
         ra[u] = (row < kend && k < nbk) ? Li[(row - k0) * NBMAX + k] : czero<T>();
+      else if (row < n && k < nbk)
+        ra[u] = s_slot[arow] >= 0 ? sv[s_slot[arow] * NBMAX + k] : A[(long long)row * n + k0 + k];
+      else
+        ra[u] = czero<T>();
     }
     const int k = kc + bk;
+    if (MODE == GEMM_PANEL) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) rbv[u] = (k < nbk) ? Li[k * NBMAX + bcq + u] : czero<T>();
+      return;
+    }
     const int srow = (k < nbk) ? ((MODE == GEMM_UPDATE) ? (k0 + k) : s_src[k]) : 0;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -616,7 +986,7 @@ __global__ __launch_bounds__(256) void lu_gemm_kernel(c2<T>* __restrict__ W, lon
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = rb + bi * 16 + acc_row<T>(lane, r);
-        if (row < rlim && col < n) A[(long long)row * n + col] = cmk<T>(cre[bi][bj][r], cim[bi][bj][r]);
+        if (row < rlim && col < clim) A[(long long)row * n + col] = cmk<T>(cre[bi][bj][r], cim[bi][bj][r]);
       }
     }
   if (MODE == GEMM_TRSM) {
@@ -932,36 +1302,89 @@ __global__ __launch_bounds__(256) void lu_solve_kernel(const c2<T>* __restrict__
 
 // ----------------------------------------------------------------------------- launchers
 template <typename T>
-hipError_t lu_factor_batch(c2<T>* W, long long mstride, int n, int nbatch, int* ipiv, int* perm,
+static void launch_trailing(c2<T>* W, long long mstride, int n, int nbatch, int k0, int nbk, int s, int* perm,
+                            long long perm_stride, c2<T>* Linv, long long inv_stride, hipStream_t st,
+                            LuTimers* tm) {
+  const int m = n - k0 - nbk;
+  if (m <= 0) return;
+  const int tc = (m + 63) / 64;
+  const long long groups = (nbatch + 7) / 8;
+  lu_gemm_kernel<T, GEMM_TRSM><<<dim3((unsigned)(groups * 8 * tc)), 256, 0, st>>>(
+      W, mstride, n, k0, nbk, s, nbatch, 1, tc, perm, perm_stride, Linv, inv_stride);
+  const bool timed = tm && tm->ev_enabled && tm->npairs < LuTimers::MAXP;
+  if (timed) hipEventRecord(tm->ev[2 * tm->npairs], st);
+  lu_gemm_kernel<T, GEMM_UPDATE><<<dim3((unsigned)(groups * 8 * tc * tc)), 256, 0, st>>>(
+      W, mstride, n, k0, nbk, s, nbatch, tc, tc, perm, perm_stride, Linv, inv_stride);
+  if (timed) {
+    hipEventRecord(tm->ev[2 * tm->npairs + 1], st);
+    tm->npairs++;
+    tm->gemm_launches += 1;   // launches and flops of the timed launches only
+    tm->gemm_flops += 8.0 * (double)m * (double)m * (double)nbk * (double)nbatch;
+  }
+}
+
+size_t lu_factor_scratch_bytes(int n, size_t elem_bytes) {
+  const size_t partial = sizeof(int) * (size_t)n;
+  const size_t tournament = 2 * sizeof(int) * 64 * 64 + elem_bytes * (size_t)LU_NB * LU_NB;
+  return partial > tournament ? partial : tournament;
+}
+
+template <typename T>
+hipError_t lu_factor_batch(c2<T>* W, long long mstride, int n, int nbatch, void* scratch, int* perm,
                            long long perm_stride, c2<T>* Linv, c2<T>* Uinv, long long inv_stride, int* info,
-                           hipStream_t st, LuTimers* tm) {
+                           int pivot, hipStream_t st, LuTimers* tm) {
   constexpr int NB = LU_NB, IB = 8;
   if (n > 4096 || n < 1) return hipErrorInvalidValue;
   const int nsteps = (n + NB - 1) / NB;
-  for (int s = 0; s < nsteps; ++s) {
-    const int k0 = s * NB, nbk = min(NB, n - k0), m = n - k0 - nbk;
-    // panel rows n - k0 <= threads * rows-per-thread
-    if (n <= 1024)
-      lu_panel_kernel<T, NB, IB, 512, 2><<<nbatch, 512, 0, st>>>(W, mstride, n, k0, s, ipiv, perm, perm_stride, Linv, Uinv, inv_stride, info);
-    else if (n <= 2048)
-      lu_panel_kernel<T, NB, IB, 1024, 2><<<nbatch, 1024, 0, st>>>(W, mstride, n, k0, s, ipiv, perm, perm_stride, Linv, Uinv, inv_stride, info);
-    else
-      lu_panel_kernel<T, NB, IB, 1024, 4><<<nbatch, 1024, 0, st>>>(W, mstride, n, k0, s, ipiv, perm, perm_stride, Linv, Uinv, inv_stride, info);
-    if (m <= 0) continue;
-    const int tc = (m + 63) / 64;
-    const long long groups = (nbatch + 7) / 8;
-    lu_gemm_kernel<T, GEMM_TRSM><<<dim3((unsigned)(groups * 8 * tc)), 256, 0, st>>>(
-        W, mstride, n, k0, nbk, s, nbatch, 1, tc, perm, perm_stride, Linv, inv_stride);
-    const bool timed = tm && tm->ev_enabled && tm->npairs < LuTimers::MAXP;
-    if (timed) hipEventRecord(tm->ev[2 * tm->npairs], st);
-    lu_gemm_kernel<T, GEMM_UPDATE><<<dim3((unsigned)(groups * 8 * tc * tc)), 256, 0, st>>>(
-        W, mstride, n, k0, nbk, s, nbatch, tc, tc, perm, perm_stride, Linv, inv_stride);
-    if (timed) {
-      hipEventRecord(tm->ev[2 * tm->npairs + 1], st);
-      tm->npairs++;
-      tm->gemm_launches += 1;   // launches and flops of the timed launches only
-      tm->gemm_flops += 8.0 * (double)m * (double)m * (double)nbk * (double)nbatch;
+  if (pivot == LU_PIVOT_PARTIAL) {
+    int* ipiv = static_cast<int*>(scratch);
+    for (int s = 0; s < nsteps; ++s) {
+      const int k0 = s * NB, nbk = min(NB, n - k0);
+      // panel rows n - k0 <= threads * rows-per-thread
+      if (n <= 1024)
+        lu_panel_kernel<T, NB, IB, 512, 2><<<nbatch, 512, 0, st>>>(W, mstride, n, k0, s, ipiv, perm, perm_stride, Linv, Uinv, inv_stride, info);
+      else if (n <= 2048)
+        lu_panel_kernel<T, NB, IB, 1024, 2><<<nbatch, 1024, 0, st>>>(W, mstride, n, k0, s, ipiv, perm, perm_stride, Linv, Uinv, inv_stride, info);
+      else
+        lu_panel_kernel<T, NB, IB, 1024, 4><<<nbatch, 1024, 0, st>>>(W, mstride, n, k0, s, ipiv, perm, perm_stride, Linv, Uinv, inv_stride, info);
+      launch_trailing<T>(W, mstride, n, nbatch, k0, nbk, s, perm, perm_stride, Linv, inv_stride, st, tm);
     }
+    return hipGetLastError();
+  }
+  if (pivot != LU_PIVOT_TOURNAMENT) return hipErrorInvalidValue;
+  // per-matrix scratch: two candidate-set buffers (64 sets x 64 rows) and the saved
+  // displaced rows (NB x NB), laid out as [nbatch][...] each
+  int* cand0 = static_cast<int*>(scratch);
+  int* cand1 = cand0 + (size_t)nbatch * 64 * 64;
+  c2<T>* saved = reinterpret_cast<c2<T>*>(cand1 + (size_t)nbatch * 64 * 64);
+  for (int s = 0; s < nsteps; ++s) {
+    const int k0 = s * NB, nbk = min(NB, n - k0), rows = n - k0;
+    int nin = 0;
+    const int* cin = cand0;
+    if (rows > 128) {
+      const int nch = (rows + 127) / 128;     // <= 32 for n <= 4096
+      tslu_local_kernel<T><<<dim3((unsigned)(nbatch * nch)), GEPP_NT, 0, st>>>(W, mstride, n, k0, nbk, nch, cand0);
+      nin = nch;
+      int* a = cand0;
+      int* b = cand1;
+      while (nin > 2) {
+        const int npair = (nin + 1) / 2;
+        tslu_merge_kernel<T><<<dim3((unsigned)(nbatch * npair)), GEPP_NT, 0, st>>>(W, mstride, n, k0, nbk, nin, a, b);
+        nin = npair;
+        int* x = a; a = b; b = x;
+      }
+      cin = a;
+    }
+    tslu_root_kernel<T, NB><<<nbatch, GEPP_NT, 0, st>>>(W, mstride, n, k0, nbk, s, nin, cin, perm, perm_stride, saved,
+                                                    Linv, Uinv, inv_stride, info);
+    const int m = n - k0 - nbk;
+    if (m > 0) {
+      const int tr = (m + 63) / 64;
+      const long long groups = (nbatch + 7) / 8;
+      lu_gemm_kernel<T, GEMM_PANEL><<<dim3((unsigned)(groups * 8 * tr)), 256, 0, st>>>(
+          W, mstride, n, k0, nbk, s, nbatch, tr, 1, perm, perm_stride, Uinv, inv_stride, saved);
+    }
+    launch_trailing<T>(W, mstride, n, nbatch, k0, nbk, s, perm, perm_stride, Linv, inv_stride, st, tm);
   }
   return hipGetLastError();
 }
@@ -978,10 +1401,10 @@ hipError_t lu_solve_batch(const c2<T>* W, long long mstride, int n, int nbatch, 
   return hipGetLastError();
 }
 
-template hipError_t lu_factor_batch<double>(c2<double>*, long long, int, int, int*, int*, long long, c2<double>*,
-                                            c2<double>*, long long, int*, hipStream_t, LuTimers*);
-template hipError_t lu_factor_batch<float>(c2<float>*, long long, int, int, int*, int*, long long, c2<float>*,
-                                           c2<float>*, long long, int*, hipStream_t, LuTimers*);
+template hipError_t lu_factor_batch<double>(c2<double>*, long long, int, int, void*, int*, long long, c2<double>*,
+                                            c2<double>*, long long, int*, int, hipStream_t, LuTimers*);
+template hipError_t lu_factor_batch<float>(c2<float>*, long long, int, int, void*, int*, long long, c2<float>*,
+                                           c2<float>*, long long, int*, int, hipStream_t, LuTimers*);
 template hipError_t lu_solve_batch<double>(const c2<double>*, long long, int, int, const int*, long long,
                                            const c2<double>*, const c2<double>*, long long, double2*, long long, int,
                                            bool, const int*, hipStream_t);

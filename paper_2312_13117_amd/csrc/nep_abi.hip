@@ -66,9 +66,9 @@ enum { PH_ASM = 0, PH_LU = 1, PH_SOLVE = 2, PH_REFINE = 3, PH_SUMS = 4, PH_TOTAL
 struct Workspace {
   hipStream_t st = 0;
   bool own = false;
-  DevBuf W, ipiv, perm, Linv, Uinv, info, R, rn2, xn2, active, counter;
+  DevBuf W, scratch, perm, Linv, Uinv, info, R, rn2, xn2, active, counter;
   void release() {
-    DevBuf* b[] = {&W, &ipiv, &perm, &Linv, &Uinv, &info, &R, &rn2, &xn2, &active, &counter};
+    DevBuf* b[] = {&W, &scratch, &perm, &Linv, &Uinv, &info, &R, &rn2, &xn2, &active, &counter};
     for (DevBuf* x : b) x->release();
     if (own && st) hipStreamDestroy(st);
     st = 0;
@@ -210,6 +210,7 @@ extern "C" nep_status nep_plan(const nep_problem* probs, int nprob, const nep_re
   if (o.precision != NEP_FP64 && o.precision != NEP_FP32_REFINE) return bad("unknown precision");
   if (o.max_refine < 0 || o.max_refine > 8) return bad("max_refine must be 0..8");
   if (o.streams < 0 || o.streams > 2) return bad("streams must be 0, 1 or 2");
+  if (o.pivot != NEP_PIVOT_TOURNAMENT && o.pivot != NEP_PIVOT_PARTIAL) return bad("pivot must be 0 or 1");
   if (!(o.tol_ind >= 0) || !(o.tol_svd >= 0) || !(o.tol_ver >= 0)) return bad("tolerances must be >= 0");
   for (int p = 0; p < nprob; ++p) {
     const nep_problem& q = probs[p];
@@ -321,7 +322,7 @@ extern "C" nep_status nep_plan(const nep_problem* probs, int nprob, const nep_re
     PCHK(hipStreamCreateWithFlags(&w.st, hipStreamNonBlocking));
     w.own = true;
     PCHK(w.W.alloc(eb * (size_t)B * nm * nm));
-    PCHK(w.ipiv.alloc(sizeof(int) * (size_t)B * nm));
+    PCHK(w.scratch.alloc(lu_factor_scratch_bytes(nm, eb) * (size_t)B));
     PCHK(w.perm.alloc(sizeof(int) * (size_t)B * steps * perm_ints_per_step()));
     PCHK(w.Linv.alloc(eb * (size_t)B * steps * LU_NB * LU_NB));
     PCHK(w.Uinv.alloc(eb * (size_t)B * steps * LU_NB * LU_NB));
@@ -398,8 +399,9 @@ static nep_status factor_chunk(nep_plan_t* P, Workspace& w, const ProblemDev& pd
   tmark(P, PH_ASM, false, w.st);
   HIPCHK(P, hipMemsetAsync(w.info.p, 0, sizeof(int) * nb, w.st));
   tmark(P, PH_LU, true, w.st);
-  HIPCHK(P, lu_factor_batch<T>(w.W.as<c2<T>>(), mstride, n, nb, w.ipiv.as<int>(), w.perm.as<int>(), pstride,
-                               w.Linv.as<c2<T>>(), w.Uinv.as<c2<T>>(), istride, w.info.as<int>(), w.st, &P->lut));
+  HIPCHK(P, lu_factor_batch<T>(w.W.as<c2<T>>(), mstride, n, nb, w.scratch.p, w.perm.as<int>(), pstride,
+                               w.Linv.as<c2<T>>(), w.Uinv.as<c2<T>>(), istride, w.info.as<int>(), P->opt.pivot,
+                               w.st, &P->lut));
   tmark(P, PH_LU, false, w.st);
   P->stats.lu_count += nb;
   P->stats.lu_flops += 8.0 / 3.0 * (double)n * n * n * nb;
@@ -420,7 +422,7 @@ static nep_status ensure_fp64_ws(nep_plan_t* P, int n, int B) {
   const int steps = (n + LU_NB - 1) / LU_NB;
   Workspace& w = P->w64;
   HIPCHK(P, w.W.alloc(16ull * B * n * n));
-  HIPCHK(P, w.ipiv.alloc(sizeof(int) * (size_t)B * n));
+  HIPCHK(P, w.scratch.alloc(lu_factor_scratch_bytes(n, 16) * (size_t)B));
   HIPCHK(P, w.perm.alloc(sizeof(int) * (size_t)B * steps * perm_ints_per_step()));
   HIPCHK(P, w.Linv.alloc(16ull * B * steps * LU_NB * LU_NB));
   HIPCHK(P, w.Uinv.alloc(16ull * B * steps * LU_NB * LU_NB));

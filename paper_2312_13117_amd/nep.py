@@ -32,7 +32,8 @@ class nep_region(C.Structure):
 class nep_options(C.Structure):
     _fields_ = [("N", C.c_int), ("s", C.c_int), ("L", C.c_int), ("tol_ind", C.c_double),
                 ("tol_svd", C.c_double), ("tol_ver", C.c_double), ("precision", C.c_int),
-                ("max_refine", C.c_int), ("batch", C.c_int), ("streams", C.c_int)]
+                ("max_refine", C.c_int), ("batch", C.c_int), ("streams", C.c_int),
+                ("pivot", C.c_int)]
 
 
 class nep_stats(C.Structure):
@@ -162,7 +163,8 @@ def nep_plan(problems, regions, opts, stream=None) -> Plan:
     for i, r in enumerate(regions):
         cr[i] = nep_region(r.x0, r.x1, r.y0, r.y1, r.nx, r.ny)
     co = nep_options(opts.N, opts.s, opts.L, opts.tol_ind, opts.tol_svd, opts.tol_ver, opts.precision,
-                     opts.max_refine, int(getattr(opts, "batch", 0) or 0), int(getattr(opts, "streams", 0) or 0))
+                     opts.max_refine, int(getattr(opts, "batch", 0) or 0), int(getattr(opts, "streams", 0) or 0),
+                     int(getattr(opts, "pivot", 0) or 0))
     if stream is None:
         stream = torch.cuda.current_stream().cuda_stream
     h = C.c_void_p()

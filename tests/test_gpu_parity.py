@@ -67,15 +67,20 @@ def check_sums(N, plan, prob, reg, opts, F, V, tol, disks=None):
             assert np.linalg.norm(C1[d] - sw.C1) <= tol * S, (d, "C1")
 
 
-@pytest.mark.parametrize("n,Nn,s,L,prec", [(4, 8, 1, 2, 0), (37, 8, 1, 4, 0), (100, 16, 2, 6, 0),
-                                           (200, 16, 1, 8, 0), (200, 16, 1, 8, 1), (130, 12, 3, 5, 1)])
-def test_sums_ragged_sizes(N, n, Nn, s, L, prec):
-    say(f"case sums n={n} N={Nn} s={s} L={L} precision={prec}")
+# pivot 0 = partial pivoting, 1 = tournament (panels of > 128 rows go through the
+# chunk/merge tree: n = 300 and 700 take one and two merge levels)
+@pytest.mark.parametrize("n,Nn,s,L,prec,pivot", [(4, 8, 1, 2, 0, 0), (37, 8, 1, 4, 0, 0), (100, 16, 2, 6, 0, 0),
+                                                 (200, 16, 1, 8, 0, 0), (200, 16, 1, 8, 1, 0),
+                                                 (130, 12, 3, 5, 1, 0), (300, 8, 1, 4, 0, 0), (700, 8, 1, 4, 1, 0),
+                                                 (4, 8, 1, 2, 0, 1), (200, 16, 1, 8, 0, 1), (130, 12, 3, 5, 1, 1),
+                                                 (300, 8, 1, 4, 0, 1), (700, 8, 1, 4, 1, 1)])
+def test_sums_ragged_sizes(N, n, Nn, s, L, prec, pivot):
+    say(f"case sums n={n} N={Nn} s={s} L={L} precision={prec} pivot={pivot}")
     A = gen.gaussian(100 + n, n)
     B = gen.gaussian(200 + n, n)
     prob = gen.qep(A + A.T, 0.1 * B, None)
     reg = gen.Region(-1.0, 1.0, -0.5, 0.5, 2, 1)
-    opts = gen.Options(N=Nn, s=s, L=L, precision=prec)
+    opts = gen.Options(N=Nn, s=s, L=L, precision=prec, pivot=pivot)
     F, V = gen.probes(1, n, s), gen.probes(2, n, L)
     plan = N.nep_plan([prob], [reg], opts)
     try:
