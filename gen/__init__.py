@@ -69,6 +69,7 @@ class Options:
     batch: int = 0       # node matrices per batch (0 = library default)
     streams: int = 0     # worker streams (0 = library default)
     pivot: int = 0       # 0 = partial pivoting, 1 = tournament pivoting
+    graph: int = 0       # 1 = capture the indicator sweep in a HIP graph and replay it
 
 
 @dataclass

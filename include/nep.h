@@ -127,7 +127,14 @@ typedef struct nep_region {
  *   batch      node matrices factored together (0 = chosen by the library)
  *   streams    worker streams the batches alternate over (1 or 2; 0 = 2): with two,
  *              one batch's panel steps overlap the other batch's trailing updates
- *   pivot      NEP_PIVOT_PARTIAL (0) or NEP_PIVOT_TOURNAMENT (1)                   */
+ *   pivot      NEP_PIVOT_PARTIAL (0) or NEP_PIVOT_TOURNAMENT (1)
+ *   graph      1: nep_indicator captures its device work (every batch on both worker
+ *              streams, the sums and the indicator) into a HIP graph on its first
+ *              call and replays it while the probe pointers stay the same; the
+ *              mixed-precision refinement then always runs max_refine masked sweeps
+ *              and the complex128 re-solves it asks for run after the replay.
+ *              Results equal the eager path's bit for bit; per-phase timings are
+ *              not available (only ms_total).  0: eager launches.              */
 typedef struct nep_options {
   int N;
   int s;
@@ -140,6 +147,7 @@ typedef struct nep_options {
   int batch;
   int streams;
   int pivot;
+  int graph;
 } nep_options;
 
 /* Counters and phase timings of the last call on a plan (device time measured with

@@ -103,7 +103,7 @@ struct nep_plan {
   Workspace w64;
   hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
   DevBuf sing;
-  DevBuf bscr, beig, bp, bsv, bkeep, bstat, bvec;
+  DevBuf bscr, beig, bp, bsv, bkeep, bstat, bvec, bids;
   DevBuf vest;
   int batch = 0;
   int nstreams = 2;
@@ -115,6 +115,14 @@ struct nep_plan {
   PhaseTimer timer;
   LuTimers lut;
   std::vector<hipEvent_t> gemm_ev;
+  // graph mode: the full indicator sweep captured once and replayed
+  bool capturing = false;
+  hipStream_t cap_st = nullptr;       // capture origin (the plan stream may be the null stream)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<const void*> graph_F, graph_V;
+  nep_stats graph_stats{};
+  DevBuf fbflag;                      // per task: complex128 re-solve needed (mixed precision)
 };
 
 static nep_status fail(nep_plan_t* p, nep_status s, const char* fmt, ...) {
@@ -151,6 +159,7 @@ static int choose_batch(int n, int precision, int ntask_max, int requested) {
 }
 
 static void tmark(nep_plan_t* p, int phase, bool start, hipStream_t st) {
+  if (p->capturing) return;            // phase events are not recorded into a graph
   hipEvent_t e = p->timer.get();
   hipEventRecord(e, st);
   int idx = p->timer.used - 1;
@@ -211,6 +220,7 @@ extern "C" nep_status nep_plan(const nep_problem* probs, int nprob, const nep_re
   if (o.max_refine < 0 || o.max_refine > 8) return bad("max_refine must be 0..8");
   if (o.streams < 0 || o.streams > 2) return bad("streams must be 0, 1 or 2");
   if (o.pivot != NEP_PIVOT_TOURNAMENT && o.pivot != NEP_PIVOT_PARTIAL) return bad("pivot must be 0 or 1");
+  if (o.graph != 0 && o.graph != 1) return bad("graph must be 0 or 1");
   if (!(o.tol_ind >= 0) || !(o.tol_svd >= 0) || !(o.tol_ver >= 0)) return bad("tolerances must be >= 0");
   for (int p = 0; p < nprob; ++p) {
     const nep_problem& q = probs[p];
@@ -308,6 +318,7 @@ extern "C" nep_status nep_plan(const nep_problem* probs, int nprob, const nep_re
   PCHK(P->xoff.alloc(sizeof(long long) * nd));
   PCHK(P->dlist.alloc(sizeof(int) * nd));
   PCHK(P->tnode.alloc(sizeof(double2) * (size_t)nd * N));
+  PCHK(P->fbflag.alloc(sizeof(int) * (size_t)nd * N));
   PCHK(P->sing.alloc(sizeof(int) * (size_t)nd * N));
   // factor workspace
   int ntask_max = 0;
@@ -366,12 +377,16 @@ extern "C" void nep_destroy(nep_plan_t* P) {
   for (auto& w : P->ws) if (w.st) hipStreamSynchronize(w.st);
   DevBuf* bufs[] = {&P->dev_dn, &P->dev_ix, &P->dev_iy, &P->dev_soff, &P->dev_w, &P->dev_z, &P->dev_r, &P->PfN, &P->PfN2,
                     &P->C0, &P->C1, &P->prof, &P->ind, &P->flags, &P->X, &P->xoff, &P->tnode, &P->dlist,
-                    &P->sing, &P->bscr, &P->beig, &P->bp, &P->bsv, &P->bkeep, &P->bstat, &P->bvec,
+                    &P->sing, &P->bscr, &P->beig, &P->bp, &P->bsv, &P->bkeep, &P->bstat, &P->bvec, &P->bids,
                     &P->vest};
   for (DevBuf* b : bufs) b->release();
   for (auto& w : P->ws) w.release();
   P->w64.own = false;
   P->w64.release();
+  if (P->gexec) hipGraphExecDestroy(P->gexec);
+  if (P->graph) hipGraphDestroy(P->graph);
+  if (P->cap_st) hipStreamDestroy(P->cap_st);
+  P->fbflag.release();
   if (P->ev_fork) hipEventDestroy(P->ev_fork);
   for (auto& e : P->ev_join) if (e) hipEventDestroy(e);
   for (auto& e : P->gemm_ev) if (e) hipEventDestroy(e);
@@ -397,7 +412,7 @@ static nep_status factor_chunk(nep_plan_t* P, Workspace& w, const ProblemDev& pd
   tmark(P, PH_ASM, true, w.st);
   HIPCHK(P, launch_assemble<T>(pd, znode, w.W.as<c2<T>>(), mstride, nb, w.st));
   tmark(P, PH_ASM, false, w.st);
-  HIPCHK(P, hipMemsetAsync(w.info.p, 0, sizeof(int) * nb, w.st));
+  HIPCHK(P, launch_fill_int(w.info.as<int>(), 0, nb, w.st));
   tmark(P, PH_LU, true, w.st);
   HIPCHK(P, lu_factor_batch<T>(w.W.as<c2<T>>(), mstride, n, nb, w.scratch.p, w.perm.as<int>(), pstride,
                                w.Linv.as<c2<T>>(), w.Uinv.as<c2<T>>(), istride, w.info.as<int>(), P->opt.pivot,
@@ -432,7 +447,7 @@ static nep_status ensure_fp64_ws(nep_plan_t* P, int n, int B) {
 
 // One batch of node systems: assemble, factor, solve, refine (mixed precision).
 static nep_status sweep_batch(nep_plan_t* P, Workspace& w, int prob, const double2* zb, double2* Xb, int nb,
-                              const SweepCall& sc, int* sing_out, bool* fallback) {
+                              const SweepCall& sc, int* sing_out, int* fb_out, bool* fallback) {
   const ProblemDev& pd = P->pd[prob];
   const int n = pd.n, s = sc.s, L = sc.L, m = s + L;
   const double2* F = static_cast<const double2*>(sc.F[prob]);
@@ -462,6 +477,24 @@ static nep_status sweep_batch(nep_plan_t* P, Workspace& w, int prob, const doubl
   tmark(P, PH_REFINE, true, w.st);
   HIPCHK(P, launch_fill_int(w.active.as<int>(), 1, nb, w.st));
   HIPCHK(P, launch_fill_int(w.active.as<int>() + nb, 0, nb, w.st));   // diverged flags
+  if (P->capturing) {
+    // graph mode: every sweep is recorded (tasks that have converged are masked
+    // off inside the kernels, so the result equals the eager loop's), no host
+    // decisions; the tasks needing a complex128 re-solve are listed for the host
+    for (int it = 0; it < P->opt.max_refine; ++it) {
+      P->stats.refine_sweeps++;
+      HIPCHK(P, launch_residual(pd, zb, Xb, F, s, V, L, (long long)n * m, m, nb, Rb, w.active.as<int>(), w.st));
+      r = solve_chunk<float>(P, w, n, nb, Rb, m, false, w.active.as<int>());
+      if (r != NEP_OK) return r;
+      HIPCHK(P, launch_axpy(Xb, Rb, (long long)n * m, n * m, w.active.as<int>(), nb, w.st));
+      int* cnt = w.counter.as<int>();
+      HIPCHK(P, launch_fill_int(cnt, 0, 1, w.st));
+      HIPCHK(P, launch_refine_check(Rb, Xb, (long long)n * m, n * m, tol, w.rn2.as<double>(), it == 0,
+                                    w.active.as<int>(), w.active.as<int>() + nb, nb, cnt, w.st));
+    }
+    HIPCHK(P, launch_or_flags(w.active.as<int>(), w.active.as<int>() + nb, nb, fb_out, w.st));
+    return NEP_OK;
+  }
   int nact = nb;
   for (int it = 0; it < P->opt.max_refine && nact > 0; ++it) {
     P->stats.refine_sweeps++;
@@ -470,7 +503,7 @@ static nep_status sweep_batch(nep_plan_t* P, Workspace& w, int prob, const doubl
     if (r != NEP_OK) return r;
     HIPCHK(P, launch_axpy(Xb, Rb, (long long)n * m, n * m, w.active.as<int>(), nb, w.st));
     int* cnt = w.counter.as<int>();
-    HIPCHK(P, hipMemsetAsync(cnt, 0, sizeof(int), w.st));
+    HIPCHK(P, launch_fill_int(cnt, 0, 1, w.st));
     HIPCHK(P, launch_refine_check(Rb, Xb, (long long)n * m, n * m, tol, w.rn2.as<double>(), it == 0,
                                   w.active.as<int>(), w.active.as<int>() + nb, nb, cnt, w.st));
     HIPCHK(P, hipMemcpyAsync(&nact, cnt, sizeof(int), hipMemcpyDeviceToHost, w.st));
@@ -505,47 +538,92 @@ static nep_status sweep_batch(nep_plan_t* P, Workspace& w, int prob, const doubl
   return NEP_OK;
 }
 
-static nep_status run_sweep(nep_plan_t* P, const SweepCall& sc, bool* singular, bool* fallback) {
-  (void)singular;
-  const int N = P->opt.N, s = sc.s, L = sc.L, m = s + L;
+// Host layout of one sweep: per listed disk the offset of its solutions, the node
+// list, and the order in which the problems' batches are issued.
+struct SweepLayout {
+  std::vector<long long> xoff;   // entry li: node j of disk sc.disks[li] at xoff[li] + j n m
+  struct Group { int li, lj, n; };
+  std::vector<Group> groups;     // runs of disks of one problem, largest n first
+};
+
+static nep_status upload_layout(nep_plan_t* P, const SweepCall& sc, SweepLayout& lay) {
+  const int N = P->opt.N, m = sc.s + sc.L;
   const int nl = (int)sc.disks.size();
-  // layout of this call's solutions: entry li, node j at xoff[li] + j*n*m
-  std::vector<long long> xoff(nl);
+  lay.xoff.assign(nl, 0);
   std::vector<double2> nodes((size_t)nl * N);
   long long acc = 0;
   for (int li = 0; li < nl; ++li) {
     const int d = sc.disks[li];
-    xoff[li] = acc;
+    lay.xoff[li] = acc;
     acc += (long long)N * P->d_n[d] * m;
     for (int j = 0; j < N; ++j) nodes[(size_t)li * N + j] = P->h_z[(size_t)d * N + j];
   }
   if (acc * (long long)sizeof(double2) > (long long)P->X.bytes)
     return fail(P, NEP_ERR_CAPACITY, "solution buffer too small for this sweep");
-  HIPCHK(P, hipMemsetAsync(P->sing.p, 0, sizeof(int) * (size_t)nl * N, P->st));
-  HIPCHK(P, hipMemcpyAsync(P->xoff.p, xoff.data(), sizeof(long long) * nl, hipMemcpyHostToDevice, P->st));
+  lay.groups.clear();
+  for (int li = 0; li < nl;) {
+    const int prob = P->d_prob[sc.disks[li]];
+    int lj = li;
+    while (lj < nl && P->d_prob[sc.disks[lj]] == prob) ++lj;
+    lay.groups.push_back({li, lj, P->pd[prob].n});
+    li = lj;
+  }
+  // largest systems first: the long factorisations start early and the small ones
+  // fill the tail
+  std::stable_sort(lay.groups.begin(), lay.groups.end(),
+                   [](const SweepLayout::Group& x, const SweepLayout::Group& y) { return x.n > y.n; });
+  HIPCHK(P, hipMemcpyAsync(P->xoff.p, lay.xoff.data(), sizeof(long long) * nl, hipMemcpyHostToDevice, P->st));
   HIPCHK(P, hipMemcpyAsync(P->tnode.p, nodes.data(), sizeof(double2) * nodes.size(), hipMemcpyHostToDevice, P->st));
   HIPCHK(P, hipMemcpyAsync(P->dlist.p, sc.disks.data(), sizeof(int) * nl, hipMemcpyHostToDevice, P->st));
-  // fork: both worker streams start after the uploads above
+  HIPCHK(P, hipStreamSynchronize(P->st));   // the host arrays go out of scope
+  return NEP_OK;
+}
+
+// quadrature sums and profiles of every listed disk, on the plan stream
+static nep_status run_sums(nep_plan_t* P, const SweepCall& sc, const SweepLayout& lay) {
+  const int N = P->opt.N, s = sc.s, L = sc.L, m = s + L;
+  double2* X = P->X.as<double2>();
+  tmark(P, PH_SUMS, true, P->st);
+  for (const auto& g : lay.groups) {
+    const int n = g.n;
+    HIPCHK(P, launch_sums(X + lay.xoff[g.li], (long long)n * m, P->dev_w.as<double2>(), P->dev_z.as<double2>(), N,
+                          n, s, L, P->PfN.as<double2>(), P->PfN2.as<double2>(), P->C0.as<double2>(),
+                          P->C1.as<double2>(), P->dlist.as<int>() + g.li, g.lj - g.li, P->dev_soff.as<long long>(),
+                          P->st));
+    if (s > 0 && sc.s == P->opt.s)
+      HIPCHK(P, launch_profile(X + lay.xoff[g.li], (long long)n * m, N, n, s, m, P->prof.as<double>(),
+                               P->dlist.as<int>() + g.li, g.lj - g.li, P->st));
+  }
+  tmark(P, PH_SUMS, false, P->st);
+  return NEP_OK;
+}
+
+// The device work of a sweep (stream-ordered, no host synchronisation unless the
+// mixed-precision refinement runs eagerly): batches of node systems alternate
+// between the worker streams, then the sums.
+static nep_status run_sweep_device(nep_plan_t* P, const SweepCall& sc, const SweepLayout& lay, bool* fallback) {
+  const int N = P->opt.N, m = sc.s + sc.L;
+  const int nl = (int)sc.disks.size();
+  HIPCHK(P, launch_fill_int(P->sing.as<int>(), 0, nl * N, P->st));
+  HIPCHK(P, launch_fill_int(P->fbflag.as<int>(), 0, nl * N, P->st));
+  // fork: both worker streams start after the work above
   HIPCHK(P, hipEventRecord(P->ev_fork, P->st));
   for (int q = 0; q < P->nstreams; ++q) HIPCHK(P, hipStreamWaitEvent(P->ws[q].st, P->ev_fork, 0));
   double2* X = P->X.as<double2>();
   const double2* tn = P->tnode.as<double2>();
   int k = 0;   // batch counter: batches alternate between the two workspaces
-  int li = 0;
-  while (li < nl) {
-    const int prob = P->d_prob[sc.disks[li]];
-    int lj = li;
-    while (lj < nl && P->d_prob[sc.disks[lj]] == prob) ++lj;
-    const int n = P->pd[prob].n;
-    const long long ntask = (long long)(lj - li) * N;
+  for (const auto& g : lay.groups) {
+    const int prob = P->d_prob[sc.disks[g.li]];
+    const int n = g.n;
+    const long long ntask = (long long)(g.lj - g.li) * N;
     for (long long t0 = 0; t0 < ntask; t0 += P->batch, ++k) {
       const int nb = (int)std::min<long long>(P->batch, ntask - t0);
       Workspace& w = P->ws[P->nstreams == 2 ? (k & 1) : 0];
-      nep_status r = sweep_batch(P, w, prob, tn + (long long)li * N + t0, X + xoff[li] + t0 * (long long)n * m, nb,
-                                 sc, P->sing.as<int>() + (long long)li * N + t0, fallback);
+      const long long task0 = (long long)g.li * N + t0;
+      nep_status r = sweep_batch(P, w, prob, tn + task0, X + lay.xoff[g.li] + t0 * (long long)n * m, nb, sc,
+                                 P->sing.as<int>() + task0, P->fbflag.as<int>() + task0, fallback);
       if (r != NEP_OK) return r;
     }
-    li = lj;
   }
   // join
   for (int q = 0; q < P->nstreams; ++q) {
@@ -553,25 +631,93 @@ static nep_status run_sweep(nep_plan_t* P, const SweepCall& sc, bool* singular, 
     HIPCHK(P, hipStreamWaitEvent(P->st, P->ev_join[q], 0));
   }
   P->stats.node_solves += (long long)nl * N;
-  // quadrature sums and profiles on the plan stream
-  tmark(P, PH_SUMS, true, P->st);
-  li = 0;
-  while (li < nl) {
-    const int prob = P->d_prob[sc.disks[li]];
-    int lj = li;
-    while (lj < nl && P->d_prob[sc.disks[lj]] == prob) ++lj;
-    const int n = P->pd[prob].n;
-    HIPCHK(P, launch_sums(X + xoff[li], (long long)n * m, P->dev_w.as<double2>(), P->dev_z.as<double2>(), N, n,
-                          s, L, P->PfN.as<double2>(), P->PfN2.as<double2>(), P->C0.as<double2>(),
-                          P->C1.as<double2>(), P->dlist.as<int>() + li, lj - li, P->dev_soff.as<long long>(),
-                          P->st));
-    if (s > 0 && sc.s == P->opt.s)
-      HIPCHK(P, launch_profile(X + xoff[li], (long long)n * m, N, n, s, m, P->prof.as<double>(),
-                               P->dlist.as<int>() + li, lj - li, P->st));
-    li = lj;
+  return run_sums(P, sc, lay);
+}
+
+static nep_status run_sweep(nep_plan_t* P, const SweepCall& sc, bool* fallback) {
+  SweepLayout lay;
+  nep_status r = upload_layout(P, sc, lay);
+  if (r != NEP_OK) return r;
+  return run_sweep_device(P, sc, lay, fallback);
+}
+
+// complex128 re-solves of the tasks a captured mixed-precision sweep listed, then the
+// sums again; returns the number of re-solved tasks
+static nep_status graph_fallbacks(nep_plan_t* P, const SweepCall& sc, const SweepLayout& lay, int* count) {
+  const int N = P->opt.N, s = sc.s, L = sc.L, m = s + L;
+  const int nl = (int)sc.disks.size();
+  *count = 0;
+  std::vector<int> fb((size_t)nl * N);
+  HIPCHK(P, hipMemcpyAsync(fb.data(), P->fbflag.p, sizeof(int) * fb.size(), hipMemcpyDeviceToHost, P->st));
+  HIPCHK(P, hipStreamSynchronize(P->st));
+  double2* X = P->X.as<double2>();
+  const double2* tn = P->tnode.as<double2>();
+  for (int li = 0; li < nl; ++li) {
+    for (int j = 0; j < N; ++j) {
+      if (!fb[(size_t)li * N + j]) continue;
+      const int d = sc.disks[li], prob = P->d_prob[d], n = P->d_n[d];
+      nep_status e = ensure_fp64_ws(P, n, 1);
+      if (e != NEP_OK) return e;
+      double2* xb = X + lay.xoff[li] + (long long)j * n * m;
+      const double2* F = static_cast<const double2*>(sc.F[prob]);
+      const double2* V = (L > 0) ? static_cast<const double2*>(sc.V[prob]) : nullptr;
+      HIPCHK(P, launch_rhs(F, s, V, L, n, xb, (long long)n * m, 1, P->w64.st));
+      e = factor_chunk<double>(P, P->w64, P->pd[prob], tn + (size_t)li * N + j, 1);
+      if (e != NEP_OK) return e;
+      e = solve_chunk<double>(P, P->w64, n, 1, xb, m, false, nullptr);
+      if (e != NEP_OK) return e;
+      ++*count;
+      P->stats.refine_fallbacks++;
+    }
   }
-  tmark(P, PH_SUMS, false, P->st);
+  if (*count > 0) return run_sums(P, sc, lay);
   return NEP_OK;
+}
+
+// Graph mode: capture the device work of the full sweep (every disk) and the
+// indicator kernel once, replay it on later calls with the same probe blocks.
+static nep_status capture_sweep(nep_plan_t* P, const SweepCall& sc, const SweepLayout& lay) {
+  if (P->gexec) { hipGraphExecDestroy(P->gexec); P->gexec = nullptr; }
+  if (P->graph) { hipGraphDestroy(P->graph); P->graph = nullptr; }
+  if (!P->cap_st) HIPCHK(P, hipStreamCreateWithFlags(&P->cap_st, hipStreamNonBlocking));
+  HIPCHK(P, hipStreamSynchronize(P->st));
+  const bool ev = P->lut.ev_enabled;
+  P->lut.ev_enabled = false;           // no timing events inside the graph
+  P->capturing = true;
+  // the null stream cannot be captured: record from a plan-owned stream, which stands
+  // in for the plan stream until the capture ends; the graph is launched on the plan
+  // stream
+  hipStream_t orig = P->st;
+  P->st = P->cap_st;
+  bool fb = false;
+  nep_status r = NEP_OK;
+  hipError_t e = hipStreamBeginCapture(P->st, hipStreamCaptureModeGlobal);
+  if (e == hipSuccess) {
+    r = run_sweep_device(P, sc, lay, &fb);
+    if (r == NEP_OK)
+      r = (launch_indicator(P->PfN.as<double2>(), P->PfN2.as<double2>(), P->dev_dn.as<int>(),
+                            P->dev_soff.as<long long>(), P->opt.s, P->opt.tol_ind, P->ind.as<double>(),
+                            P->flags.as<unsigned char>(), P->sing.as<int>(), P->opt.N, P->prof.as<double>(),
+                            P->dev_r.as<double>(), INDICATOR_NOISE_FLOOR, P->nd, P->st) == hipSuccess)
+              ? NEP_OK : NEP_ERR_HIP;
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(P->st, &g);
+    if (r == NEP_OK && e2 != hipSuccess) r = fail(P, NEP_ERR_HIP, "graph capture: %s", hipGetErrorString(e2));
+    if (r == NEP_OK) {
+      P->graph = g;
+      e = hipGraphInstantiate(&P->gexec, g, nullptr, nullptr, 0);
+      if (e != hipSuccess) r = fail(P, NEP_ERR_HIP, "graph instantiate: %s", hipGetErrorString(e));
+    } else if (g) {
+      hipGraphDestroy(g);
+    }
+  } else {
+    r = fail(P, NEP_ERR_HIP, "graph capture: %s", hipGetErrorString(e));
+  }
+  P->st = orig;
+  P->capturing = false;
+  P->lut.ev_enabled = ev;
+  P->graph_stats = P->stats;
+  return r;
 }
 
 extern "C" nep_status nep_indicator(nep_plan_t* P, const void* const* F_dev, const void* const* V_dev, double* ind,
@@ -581,7 +727,6 @@ extern "C" nep_status nep_indicator(nep_plan_t* P, const void* const* F_dev, con
   for (int p = 0; p < P->nprob; ++p)
     if (!F_dev[p] || (V_dev && P->opt.L > 0 && !V_dev[p])) return fail(P, NEP_ERR_ARG, "null probe block");
   reset_stats(P);
-  tmark(P, PH_TOTAL, true, P->st);
   SweepCall sc;
   sc.disks.resize(P->nd);
   for (int d = 0; d < P->nd; ++d) sc.disks[d] = d;
@@ -590,12 +735,42 @@ extern "C" nep_status nep_indicator(nep_plan_t* P, const void* const* F_dev, con
   sc.F = F_dev;
   sc.V = V_dev;
   bool sing = false, fb = false;
-  nep_status r = run_sweep(P, sc, &sing, &fb);
-  if (r != NEP_OK) return r;
-  HIPCHK(P, launch_indicator(P->PfN.as<double2>(), P->PfN2.as<double2>(), P->dev_dn.as<int>(),
-                             P->dev_soff.as<long long>(), P->opt.s, P->opt.tol_ind, P->ind.as<double>(),
-                             P->flags.as<unsigned char>(), P->sing.as<int>(), P->opt.N, P->prof.as<double>(),
-                             P->dev_r.as<double>(), INDICATOR_NOISE_FLOOR, P->nd, P->st));
+  if (P->opt.graph) {
+    SweepLayout lay;
+    nep_status r = upload_layout(P, sc, lay);
+    if (r != NEP_OK) return r;
+    std::vector<const void*> Fv(F_dev, F_dev + P->nprob), Vv;
+    if (sc.L > 0) Vv.assign(V_dev, V_dev + P->nprob);
+    if (!P->gexec || Fv != P->graph_F || Vv != P->graph_V) {
+      r = capture_sweep(P, sc, lay);
+      if (r != NEP_OK) return r;
+      P->graph_F = Fv;
+      P->graph_V = Vv;
+    }
+    P->stats = P->graph_stats;
+    tmark(P, PH_TOTAL, true, P->st);
+    HIPCHK(P, hipGraphLaunch(P->gexec, P->st));
+    if (P->opt.precision == NEP_FP32_REFINE) {
+      int cnt = 0;
+      r = graph_fallbacks(P, sc, lay, &cnt);
+      if (r != NEP_OK) return r;
+      if (cnt > 0) {
+        fb = true;
+        HIPCHK(P, launch_indicator(P->PfN.as<double2>(), P->PfN2.as<double2>(), P->dev_dn.as<int>(),
+                                   P->dev_soff.as<long long>(), P->opt.s, P->opt.tol_ind, P->ind.as<double>(),
+                                   P->flags.as<unsigned char>(), P->sing.as<int>(), P->opt.N, P->prof.as<double>(),
+                                   P->dev_r.as<double>(), INDICATOR_NOISE_FLOOR, P->nd, P->st));
+      }
+    }
+  } else {
+    tmark(P, PH_TOTAL, true, P->st);
+    nep_status r = run_sweep(P, sc, &fb);
+    if (r != NEP_OK) return r;
+    HIPCHK(P, launch_indicator(P->PfN.as<double2>(), P->PfN2.as<double2>(), P->dev_dn.as<int>(),
+                               P->dev_soff.as<long long>(), P->opt.s, P->opt.tol_ind, P->ind.as<double>(),
+                               P->flags.as<unsigned char>(), P->sing.as<int>(), P->opt.N, P->prof.as<double>(),
+                               P->dev_r.as<double>(), INDICATOR_NOISE_FLOOR, P->nd, P->st));
+  }
   tmark(P, PH_TOTAL, false, P->st);
   HIPCHK(P, hipMemcpyAsync(ind, P->ind.p, sizeof(double) * P->nd * P->opt.s, hipMemcpyDeviceToHost, P->st));
   HIPCHK(P, hipMemcpyAsync(flags, P->flags.p, P->nd, hipMemcpyDeviceToHost, P->st));
@@ -641,8 +816,8 @@ extern "C" nep_status nep_beyn(nep_plan_t* P, const int32_t* disk_ids, int ndisk
     sc.F = P->last_F.empty() ? nullptr : P->last_F.data();
     sc.V = V_dev;
     if (!sc.F) return fail(P, NEP_ERR_STATE, "no probe block F from the previous sweep");
-    bool sing = false, fb = false;
-    nep_status r = run_sweep(P, sc, &sing, &fb);
+    bool fb = false;
+    nep_status r = run_sweep(P, sc, &fb);
     if (r != NEP_OK) return r;
   } else if (!P->swept_with_V) {
     return fail(P, NEP_ERR_STATE, "no moments: call nep_indicator with V first, or pass V_dev");
@@ -656,15 +831,15 @@ extern "C" nep_status nep_beyn(nep_plan_t* P, const int32_t* disk_ids, int ndisk
   HIPCHK(P, hipMemsetAsync(P->bstat.p, 0, sizeof(int) * ndisks, P->st));
   // one launch per problem (region parameters differ)
   std::vector<int> ids(disk_ids, disk_ids + ndisks);
-  HIPCHK(P, P->dlist.alloc(sizeof(int) * std::max(P->nd, ndisks)));
-  HIPCHK(P, hipMemcpyAsync(P->dlist.p, ids.data(), sizeof(int) * ndisks, hipMemcpyHostToDevice, P->st));
+  HIPCHK(P, P->bids.alloc(sizeof(int) * ndisks));
+  HIPCHK(P, hipMemcpyAsync(P->bids.p, ids.data(), sizeof(int) * ndisks, hipMemcpyHostToDevice, P->st));
   int i = 0;
   while (i < ndisks) {
     const int prob = P->d_prob[ids[i]];
     int j = i;
     while (j < ndisks && P->d_prob[ids[j]] == prob) ++j;
     BeynArgs a{};
-    a.disk_ids = P->dlist.as<int>() + i;
+    a.disk_ids = P->bids.as<int>() + i;
     a.dn = P->dev_dn.as<int>();
     a.soff = P->dev_soff.as<long long>();
     a.ix = P->dev_ix.as<int>();

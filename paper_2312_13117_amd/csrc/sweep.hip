@@ -404,6 +404,17 @@ hipError_t launch_mark_singular(const int* info, int nb, int* sing, hipStream_t 
   return hipGetLastError();
 }
 
+// out[b] = a[b] | c[b]: the tasks still unconverged or diverged after refinement
+__global__ void or_flags_kernel(const int* __restrict__ a, const int* __restrict__ c, int nb, int* __restrict__ out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < nb) out[b] = (a[b] | c[b]) != 0 ? 1 : 0;
+}
+
+hipError_t launch_or_flags(const int* a, const int* c, int nb, int* out, hipStream_t st) {
+  or_flags_kernel<<<(nb + 255) / 256, 256, 0, st>>>(a, c, nb, out);
+  return hipGetLastError();
+}
+
 // a[i] = v for i < n (a fill kernel instead of a memset node, so graph captures replay it)
 __global__ void fill_int_kernel(int* a, int v, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;

@@ -33,7 +33,7 @@ class nep_options(C.Structure):
     _fields_ = [("N", C.c_int), ("s", C.c_int), ("L", C.c_int), ("tol_ind", C.c_double),
                 ("tol_svd", C.c_double), ("tol_ver", C.c_double), ("precision", C.c_int),
                 ("max_refine", C.c_int), ("batch", C.c_int), ("streams", C.c_int),
-                ("pivot", C.c_int)]
+                ("pivot", C.c_int), ("graph", C.c_int)]
 
 
 class nep_stats(C.Structure):
@@ -164,7 +164,7 @@ def nep_plan(problems, regions, opts, stream=None) -> Plan:
         cr[i] = nep_region(r.x0, r.x1, r.y0, r.y1, r.nx, r.ny)
     co = nep_options(opts.N, opts.s, opts.L, opts.tol_ind, opts.tol_svd, opts.tol_ver, opts.precision,
                      opts.max_refine, int(getattr(opts, "batch", 0) or 0), int(getattr(opts, "streams", 0) or 0),
-                     int(getattr(opts, "pivot", 0) or 0))
+                     int(getattr(opts, "pivot", 0) or 0), int(getattr(opts, "graph", 0) or 0))
     if stream is None:
         stream = torch.cuda.current_stream().cuda_stream
     h = C.c_void_p()
@@ -232,11 +232,8 @@ def nep_verify(plan: Plan, prob_ids: Sequence[int], lam: Sequence[complex]):
     return sig, acc.astype(bool)
 
 
-def nep_copy_sums(plan: Plan, first: int, count: int):
+def _copy_sums_uniform(plan: Plan, first: int, count: int, n: int):
     L = lib()
-    n = plan.n[0] if plan.nprob == 1 else None
-    if n is None:
-        raise ValueError("nep_copy_sums binding expects a single-problem plan")
     PfN = np.zeros((count, n, plan.s), np.complex128)
     PfN2 = np.zeros((count, n, plan.s), np.complex128)
     C0 = np.zeros((count, n, plan.L), np.complex128) if plan.L else None
@@ -245,6 +242,27 @@ def nep_copy_sums(plan: Plan, first: int, count: int):
                            _ptr(C0) if C0 is not None else None, _ptr(C1) if C1 is not None else None),
            plan.handle)
     return PfN, PfN2, C0, C1
+
+
+def nep_copy_sums(plan: Plan, first: int, count: int):
+    """Sums of disks [first, first + count): arrays [count, n, cols] when the disks share
+    n (always for a single-problem plan), else per-disk lists of [n, cols] arrays."""
+    L = lib()
+    if plan.nprob == 1:
+        return _copy_sums_uniform(plan, first, count, plan.n[0])
+    offs = [L.nep_disk_offset(plan.handle, p) for p in range(plan.nprob)] + [plan.total_disks]
+    parts = []
+    for p in range(plan.nprob):
+        a, b = max(first, offs[p]), min(first + count, offs[p + 1])
+        if a < b:
+            parts.append(_copy_sums_uniform(plan, a, b - a, plan.n[p]))
+    out = []
+    for k in range(4):
+        if parts and parts[0][k] is None:
+            out.append(None)
+        else:
+            out.append([x for part in parts for x in part[k]])
+    return tuple(out)
 
 
 def nep_dedup(lam, sigma, rel: float = 1e-8):

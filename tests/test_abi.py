@@ -36,14 +36,14 @@ def test_plan_rejects_bad_options():
     h = C.c_void_p()
     for o in (gen.Options(N=7), gen.Options(N=2), gen.Options(s=0), gen.Options(L=40), gen.Options(precision=5),
               gen.Options(max_refine=-1), gen.Options(tol_ind=float("nan")), gen.Options(streams=3),
-              gen.Options(pivot=2)):
+              gen.Options(pivot=2), gen.Options(graph=2)):
         co = N.nep_options(o.N, o.s, o.L, o.tol_ind, o.tol_svd, o.tol_ver, o.precision, o.max_refine, o.batch,
-                           o.streams, o.pivot)
+                           o.streams, o.pivot, o.graph)
         st = L.nep_plan(C.byref(prob), 1, C.byref(reg), C.byref(co), None, C.byref(h))
         assert st == -1 and not h.value
         assert L.nep_last_error(None).decode()
     # null arguments and a bad region
-    co = N.nep_options(32, 1, 8, 0.1, 1e-6, 1e-6, 0, 3, 0, 0, 0)
+    co = N.nep_options(32, 1, 8, 0.1, 1e-6, 1e-6, 0, 3, 0, 0, 0, 0)
     assert L.nep_plan(None, 1, C.byref(reg), C.byref(co), None, C.byref(h)) == -1
     kinds = (C.c_int * 1)(0)
     ptrs = (C.c_void_p * 1)(None)
