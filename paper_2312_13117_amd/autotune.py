@@ -1,0 +1,138 @@
+"""Launch-configuration autotuner for the node sweep.
+
+For each matrix order n and precision it times full indicator sweeps of a seeded
+synthetic QEP (the dense workload's generator at that order, s = 4 and L = 16 probe
+columns, 32 nodes per disk, enough disks for several batches) over the candidate
+configurations
+
+    batch    node matrices factored together (library default, or fixed sizes)
+    streams  1 or 2 worker streams
+    graph    eager launches, or the sweep captured in a HIP graph and replayed
+    pivot    partial or tournament pivoting (recorded, not applied: it changes the
+             rounding of the results)
+
+and writes the fastest per (n, precision) to a JSON table.  Batch, streams and graph
+never change a result bit (each node system is independent and the sums run in a
+fixed order), so the binding applies them from the table whenever a caller leaves
+batch and streams at 0 (library default).
+
+    python -m paper_2312_13117_amd.autotune --sizes 64 128 256 512 1024 2048
+"""
+from __future__ import annotations
+
+import argparse
+import itertools
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+from . import nep as N
+
+TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
+
+
+def _workload(n: int, precision: int, tasks: int):
+    import gen
+    w = gen.workload_dense_qep(n, precision=precision)
+    disks = max(1, math.ceil(tasks / 32))
+    nx = max(1, int(round(math.sqrt(disks))))
+    ny = max(1, math.ceil(disks / nx))
+    w.regions = [gen.Region(-4.0, 4.0, -4.0, 4.0, nx, ny)]
+    return w
+
+
+def _time_config(w, opts, reps: int) -> float:
+    import torch
+    plan = N.nep_plan(w.problems, w.regions, opts)
+    try:
+        N.nep_indicator(plan, w.F, w.V)            # warm-up (and graph capture)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            N.nep_indicator(plan, w.F, w.V)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return plan.total_disks * opts.N / float(np.median(ts))
+    finally:
+        N.nep_destroy(plan)
+
+
+def tune(sizes, precisions=(0, 1), reps: int = 3, log=print) -> dict:
+    import gen
+    import torch
+    entries = []
+    for n, prec in itertools.product(sizes, precisions):
+        eb = 16 if prec == 0 else 8
+        # batches that keep two workspaces under 16 GB
+        cands = [0] + [b for b in (32, 64, 128, 256, 512) if 2 * b * n * n * eb <= 16e9]
+        big = max(b for b in cands if b) if len(cands) > 1 else 32
+        w = _workload(n, prec, tasks=max(256, 3 * big))
+        best, results = None, []
+        for batch, streams, graph in itertools.product(cands, (1, 2), (0, 1)):
+            o = gen.Options(N=32, s=4, L=16, precision=prec, batch=batch, streams=streams, graph=graph)
+            rate = _time_config(w, o, reps)
+            results.append({"batch": batch, "streams": streams, "graph": graph, "solves_per_s": rate})
+            if best is None or rate > best["solves_per_s"]:
+                best = results[-1]
+        piv = {}
+        for pivot in (0, 1):
+            o = gen.Options(N=32, s=4, L=16, precision=prec, batch=best["batch"], streams=best["streams"],
+                            graph=best["graph"], pivot=pivot)
+            piv[pivot] = _time_config(w, o, reps)
+        e = {"n": n, "precision": prec, "batch": best["batch"], "streams": best["streams"], "graph": best["graph"],
+             "solves_per_s": best["solves_per_s"], "pivot_best": int(max(piv, key=piv.get)),
+             "pivot_rates": {str(k): v for k, v in piv.items()}, "tasks": w.regions[0].nx * w.regions[0].ny * 32,
+             "candidates": results}
+        log(f"n={n} precision={prec}: batch={e['batch']} streams={e['streams']} graph={e['graph']} "
+            f"{e['solves_per_s']:.0f} solves/s; pivot rates {piv}")
+        entries.append(e)
+        torch.cuda.empty_cache()
+    return {"device": torch.cuda.get_device_name(0), "entries": entries}
+
+
+_cache = {}
+
+
+def load_table(path: str = TABLE):
+    if path not in _cache:
+        try:
+            with open(path) as f:
+                _cache[path] = json.load(f)
+        except (OSError, ValueError):
+            _cache[path] = None
+    return _cache[path]
+
+
+def lookup(n: int, precision: int, path: str = TABLE):
+    """Entry for the smallest tuned order >= n (else the largest) of this precision."""
+    t = load_table(path)
+    if not t:
+        return None
+    es = sorted((e for e in t["entries"] if e["precision"] == precision), key=lambda e: e["n"])
+    if not es:
+        return None
+    for e in es:
+        if e["n"] >= n:
+            return e
+    return es[-1]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--sizes", type=int, nargs="+", default=[64, 128, 256, 512, 1024, 2048])
+    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--out", default=TABLE)
+    a = ap.parse_args()
+    t = tune(a.sizes, reps=a.reps, log=lambda *x: print(*x, file=sys.stderr, flush=True))
+    with open(a.out, "w") as f:
+        json.dump(t, f, indent=1)
+    print(json.dumps({"written": a.out, "entries": len(t["entries"])}))
+
+
+if __name__ == "__main__":
+    main()

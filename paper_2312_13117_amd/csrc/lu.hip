@@ -461,25 +461,27 @@ __global__ __launch_bounds__(NT) void lu_panel_kernel(c2<T>* __restrict__ W, lon
 // The pivot rows differ from plain partial pivoting; the result is still P A = L U
 // with |multipliers| bounded in practice, and every pass over the panel is parallel.
 //
-// gepp_chunk: partial pivoting on up to 128 candidate rows x nbk <= 64 panel columns
-// held in registers: 512 threads, thread t owns chunk row i = t/4 and the 16 columns
+// gepp_chunk: partial pivoting on up to R (128 or 256) rows x nbk <= 64 panel columns
+// held in registers: 4R threads, thread t owns chunk row i = t/4 and the 16 columns
 // 16*(t&3) .. +15, so the four threads of a row form a quad of lanes.  Rows are never
-// moved; a row is marked when chosen.  Produces the pivot rows in order (win) and,
-// for the chosen rows, the factored values in place (multipliers left of the row's
-// pivot column, U from it on).  Every value read is an original panel value.
+// moved; a row is marked when chosen.  Produces the pivot rows in order (win) and
+// leaves every row factored in place: a chosen row holds its multipliers left of its
+// pivot column and its U row from there on, a row never chosen holds its multipliers
+// (its row of L21).  Every value read is an original panel value.
 //
 // One workgroup barrier per column: each wave reduces its best row for column j to a
-// packed key (magnitude bits | row), and the lanes holding that row publish it to LDS;
-// after the barrier every thread picks the best of the 8 keys and reads the pivot row
-// from that wave's slot.  Slots are double-buffered by column parity.
+// packed key (magnitude bits | row), and the lanes holding that row publish it (and
+// the reciprocal of its column-j entry) to LDS; after the barrier every thread picks
+// the best of the wave keys and reads the pivot row from that wave's slot.  Slots are
+// double-buffered by column parity.
 //
-// Key: the upper bits of |Re| + |Im| (IEEE bits of a non-negative value order like
-// unsigned integers), 12 (double) / 15 (float) mantissa bits kept, and 255 - i in the
-// low byte so that equal magnitudes go to the lowest row; 0 = no candidate.  The pivot
-// is therefore the row of largest magnitude up to a relative 2^-12 (threshold
-// pivoting), the first such row on ties.
-constexpr int GEPP_ROWS = 128, GEPP_Q = 4, GEPP_NT = GEPP_ROWS * GEPP_Q, GEPP_H = 64 / GEPP_Q,
-              GEPP_NW = GEPP_NT / 64;
+// Key: the IEEE bits of |Re| + |Im| (bits of a non-negative value order like unsigned
+// integers) with the low bits replaced by (2R - 1 - i), so that equal keys go to the
+// lowest row and 0 means no candidate.  32-bit keys keep 12 (double) / 15 (float)
+// mantissa bits: the pivot is the largest row up to a relative 2^-12 (the tournament's
+// selection passes).  64-bit keys keep 43 (double) / all 23 (float) mantissa bits: the
+// choice of partial pivoting, up to ties within 2^-43 relative.
+constexpr int GEPP_Q = 4, GEPP_H = 64 / GEPP_Q;
 
 template <typename T>
 struct Gepp {
@@ -488,44 +490,66 @@ struct Gepp {
   bool chosen;
 };
 
-template <typename T>
+template <typename T, int R, typename K>
 struct GeppShared {
-  c2<T> rowbuf[2][GEPP_NW][64];
-  c2<T> rinv[2][GEPP_NW];          // 1 / (the wave candidate's column-j entry)
-  unsigned keys[2][GEPP_NW];
+  static constexpr int NW = 4 * R / 64;
+  c2<T> rowbuf[2][NW][64];
+  c2<T> rinv[2][NW];               // 1 / (the wave candidate's column-j entry)
+  K keys[2][NW];
   int win[64];
   int singular;
 };
 
-__device__ inline unsigned gepp_key(double m, int i) {
+template <int R> __device__ inline unsigned gepp_key32(double m, int i) {
   const unsigned hi = (unsigned)((unsigned long long)__double_as_longlong(m) >> 32);
-  return (hi & ~255u) | (unsigned)(255 - i);
+  return (hi & ~(unsigned)(2 * R - 1)) | (unsigned)(2 * R - 1 - i);
 }
-__device__ inline unsigned gepp_key(float m, int i) {
-  return ((unsigned)__float_as_uint(m) & ~255u) | (unsigned)(255 - i);
+template <int R> __device__ inline unsigned gepp_key32(float m, int i) {
+  return ((unsigned)__float_as_uint(m) & ~(unsigned)(2 * R - 1)) | (unsigned)(2 * R - 1 - i);
+}
+template <int R> __device__ inline unsigned long long gepp_key64(double m, int i) {
+  return ((unsigned long long)__double_as_longlong(m) & ~(unsigned long long)(2 * R - 1)) |
+         (unsigned long long)(2 * R - 1 - i);
+}
+template <int R> __device__ inline unsigned long long gepp_key64(float m, int i) {
+  return ((unsigned long long)__float_as_uint(m) << 16) | (unsigned long long)(2 * R - 1 - i);
+}
+template <int R, typename K, typename T> __device__ inline K gepp_key(T m, int i) {
+  if constexpr (sizeof(K) == 4) return gepp_key32<R>(m, i);
+  else return gepp_key64<R>(m, i);
 }
 
-__device__ inline unsigned dpp_max(unsigned v, int ctrl_sel) {
-  // ctrl_sel picks a constant DPP control: quad xor 1, quad xor 2, half-row mirror, row mirror
-  unsigned o;
+// DPP move of lane data; ctrl_sel picks a constant control: quad xor 1, quad xor 2,
+// half-row mirror, row mirror
+__device__ inline unsigned dpp_mov(unsigned v, int ctrl_sel) {
   switch (ctrl_sel) {
-    case 0: o = (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xf, 0xf, false); break;
-    case 1: o = (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xf, 0xf, false); break;
-    case 2: o = (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xf, 0xf, false); break;
-    default: o = (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xf, 0xf, false); break;
+    case 0: return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xf, 0xf, false);
+    case 1: return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xf, 0xf, false);
+    case 2: return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xf, 0xf, false);
+    default: return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xf, 0xf, false);
   }
-  return v > o ? v : o;
+}
+__device__ inline unsigned long long dpp_mov(unsigned long long v, int ctrl_sel) {
+  const unsigned lo = dpp_mov((unsigned)v, ctrl_sel), hi = dpp_mov((unsigned)(v >> 32), ctrl_sel);
+  return ((unsigned long long)hi << 32) | lo;
+}
+__device__ inline unsigned readlane_k(unsigned v, int l) { return (unsigned)__builtin_amdgcn_readlane((int)v, l); }
+__device__ inline unsigned long long readlane_k(unsigned long long v, int l) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), l);
+  return ((unsigned long long)hi << 32) | lo;
 }
 
 // maximum over the 64 lanes, returned to every lane (all lanes must be active)
-__device__ inline unsigned wave_max_u32(unsigned v) {
-  v = dpp_max(v, 0);
-  v = dpp_max(v, 1);
-  v = dpp_max(v, 2);
-  v = dpp_max(v, 3);
-  const unsigned a = (unsigned)__builtin_amdgcn_readlane((int)v, 0), b = (unsigned)__builtin_amdgcn_readlane((int)v, 16);
-  const unsigned c = (unsigned)__builtin_amdgcn_readlane((int)v, 32), d = (unsigned)__builtin_amdgcn_readlane((int)v, 48);
-  const unsigned x = a > b ? a : b, y = c > d ? c : d;
+template <typename K>
+__device__ inline K wave_max_key(K v) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const K o = dpp_mov(v, c);
+    v = v > o ? v : o;
+  }
+  const K a = readlane_k(v, 0), b = readlane_k(v, 16), c = readlane_k(v, 32), d = readlane_k(v, 48);
+  const K x = a > b ? a : b, y = c > d ? c : d;
   return x > y ? x : y;
 }
 
@@ -545,9 +569,10 @@ __device__ inline double quad_bcast(double v, int src) {
 }
 __device__ inline float quad_bcast(float v, int src) { return __int_as_float(quad_bcast(__float_as_int(v), src)); }
 
-template <typename T>
-__device__ __forceinline__ void gepp_chunk(Gepp<T>& g, int nbk, GeppShared<T>& sh) {
-  constexpr int H = GEPP_H;
+template <typename T, int R, typename K>
+__device__ __forceinline__ void gepp_chunk(Gepp<T>& g, int nbk, GeppShared<T, R, K>& sh) {
+  constexpr int H = GEPP_H, NW = GeppShared<T, R, K>::NW;
+  constexpr K MASK = (K)(2 * R - 1);
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int h = t & (GEPP_Q - 1), i = t / GEPP_Q;
   g.chosen = false;
@@ -560,30 +585,30 @@ __device__ __forceinline__ void gepp_chunk(Gepp<T>& g, int nbk, GeppShared<T>& s
       const int buf = j & 1;
       const bool live = g.row >= 0 && !g.chosen;
       const c2<T> ajj = g.a[ju];
-      unsigned key = 0;
-      if (h == jb && live) key = gepp_key(cabs1<T>(ajj), i);
+      K key = 0;
+      if (h == jb && live) key = gepp_key<R, K>(cabs1<T>(ajj), i);
       // the reciprocal is formed by every owner lane while the reduction runs, so
       // that no division sits between the barrier and the update
       const bool nzj = ajj.x != T(0) || ajj.y != T(0);
       const c2<T> r = nzj ? crcp<T>(ajj) : czero<T>();
-      const unsigned wk = wave_max_u32(key);
-      if (wk != 0 && i == 255 - (int)(wk & 255u)) {
+      const K wk = wave_max_key<K>(key);
+      if (wk != 0 && i == (int)(MASK - (wk & MASK))) {
 #pragma unroll
         for (int u = 0; u < H; ++u) sh.rowbuf[buf][wave][h * H + u] = g.a[u];
         if (h == jb) sh.rinv[buf][wave] = r;
       }
       if (lane == 0) sh.keys[buf][wave] = wk;
       __syncthreads();
-      unsigned best = 0;
+      K best = 0;
       int bw = 0;
 #pragma unroll
-      for (int w = 0; w < GEPP_NW; ++w) {
-        const unsigned k = sh.keys[buf][w];
+      for (int w = 0; w < NW; ++w) {
+        const K k = sh.keys[buf][w];
         if (k > best) { best = k; bw = w; }
       }
       if (best == 0) { done = true; continue; }         // no candidate rows left (uniform)
-      const int pi = 255 - (int)(best & 255u);
-      if ((best & ~255u) == 0u && t == 0) sh.singular = 1;
+      const int pi = (int)(MASK - (best & MASK));
+      if ((best & ~MASK) == 0 && t == 0) sh.singular = 1;
       if (i == pi) {
         g.chosen = true;
         if (h == 0) sh.win[j] = g.row;
@@ -625,85 +650,95 @@ __device__ __forceinline__ void gepp_load(Gepp<T>& g, const c2<T>* A, int n, int
   }
 }
 
-template <typename T>
-__device__ void gepp_init(GeppShared<T>& sh) {
+template <typename T, int R, typename K>
+__device__ void gepp_init(GeppShared<T, R, K>& sh) {
   const int t = threadIdx.x;
   if (t < 64) sh.win[t] = -1;
   if (t == 0) sh.singular = 0;
 }
 
+// Tournament selection passes use 128-row chunks and 32-bit keys.
+constexpr int TSLU_ROWS = 128, TSLU_NT = 4 * TSLU_ROWS;
+
 // T1: grid nbatch x nch, chunk c of matrix b: rows k0 + 128c .. +127 -> 64 nominations
 template <typename T>
-__global__ __launch_bounds__(GEPP_NT) void tslu_local_kernel(const c2<T>* __restrict__ W, long long mstride,
+__global__ __launch_bounds__(TSLU_NT) void tslu_local_kernel(const c2<T>* __restrict__ W, long long mstride,
                                                              int n, int k0, int nbk, int nch,
                                                              int* __restrict__ cand) {
   const int b = blockIdx.x / nch, c = blockIdx.x % nch;
   const c2<T>* A = W + (long long)b * mstride;
-  __shared__ GeppShared<T> sh;
+  __shared__ GeppShared<T, TSLU_ROWS, unsigned> sh;
   const int t = threadIdx.x;
-  gepp_init<T>(sh);
+  gepp_init(sh);
   Gepp<T> g;
-  const int r = k0 + c * GEPP_ROWS + t / GEPP_Q;
+  const int r = k0 + c * TSLU_ROWS + t / GEPP_Q;
   gepp_load<T>(g, A, n, k0, nbk, r < n ? r : -1);
   __syncthreads();
-  gepp_chunk<T>(g, nbk, sh);
+  gepp_chunk(g, nbk, sh);
   if (t < 64) cand[((long long)b * 64 + c) * 64 + t] = sh.win[t];
 }
 
 // T2: grid nbatch x npair, merge candidate sets 2p and 2p+1 (of nin) -> set p
 template <typename T>
-__global__ __launch_bounds__(GEPP_NT) void tslu_merge_kernel(const c2<T>* __restrict__ W, long long mstride,
+__global__ __launch_bounds__(TSLU_NT) void tslu_merge_kernel(const c2<T>* __restrict__ W, long long mstride,
                                                              int n, int k0, int nbk, int nin,
                                                              const int* __restrict__ cin, int* __restrict__ cout) {
   const int npair = (nin + 1) / 2;
   const int b = blockIdx.x / npair, p = blockIdx.x % npair;
   const c2<T>* A = W + (long long)b * mstride;
-  __shared__ GeppShared<T> sh;
+  __shared__ GeppShared<T, TSLU_ROWS, unsigned> sh;
   const int t = threadIdx.x;
-  gepp_init<T>(sh);
+  gepp_init(sh);
   const int i = t / GEPP_Q;
   const int set = 2 * p + (i >> 6);
   const int row = (set < nin) ? cin[((long long)b * 64 + set) * 64 + (i & 63)] : -1;
   Gepp<T> g;
   gepp_load<T>(g, A, n, k0, nbk, row);
   __syncthreads();
-  gepp_chunk<T>(g, nbk, sh);
+  gepp_chunk(g, nbk, sh);
   if (t < 64) cout[((long long)b * 64 + p) * 64 + t] = sh.win[t];
 }
 
-// T3: one workgroup per matrix: partial pivoting on the final <= 128 candidates (the
-// union of <= 2 sets, or all rows when m <= 128), then
+// Final panel pass, one workgroup of 4R threads per matrix, partial pivoting with
+// 64-bit keys on
+//   DIRECT:  every row of the panel (n - k0 <= R), or
+//   !DIRECT: the union of <= 2 tournament candidate sets (R = 128),
+// then
 //   - the step's row exchange as a compact permutation (top rows k0+k <- winner k;
 //     the displaced top rows fill the positions the winners vacate below kend),
-//   - the displaced top rows' panel values saved (the L21 pass reads them there),
 //   - the winners' factored rows (L11 \ U11) written to the top rows,
+//   - DIRECT: every other row's multipliers (its row of L21) written at its new
+//     position; !DIRECT: the displaced top rows' panel values saved for the L21 pass,
 //   - inv(L11) and inv(U11).
-template <typename T, int NB>
-__global__ __launch_bounds__(GEPP_NT) void tslu_root_kernel(c2<T>* __restrict__ W, long long mstride, int n, int k0,
-                                                        int nbk, int step, int nin, const int* __restrict__ cin,
-                                                        int* __restrict__ perm, long long perm_stride,
-                                                        c2<T>* __restrict__ saved, c2<T>* __restrict__ Linv,
-                                                        c2<T>* __restrict__ Uinv, long long inv_stride,
-                                                        int* __restrict__ info) {
+template <typename T, int NB, int R, bool DIRECT>
+__global__ __launch_bounds__(4 * R) void tslu_root_kernel(c2<T>* __restrict__ W, long long mstride, int n, int k0,
+                                                          int nbk, int step, int nin, const int* __restrict__ cin,
+                                                          int* __restrict__ perm, long long perm_stride,
+                                                          c2<T>* __restrict__ saved, c2<T>* __restrict__ Linv,
+                                                          c2<T>* __restrict__ Uinv, long long inv_stride,
+                                                          int* __restrict__ info) {
+  constexpr int NT = 4 * R;
+  using K = unsigned long long;
   const int b = blockIdx.x;
   c2<T>* A = W + (long long)b * mstride;
   // the GEPP state and the triangle workspace are used one after the other
   union RootShared {
-    GeppShared<T> g;
+    GeppShared<T, R, K> g;
     struct { c2<T> M[NB][NB + 1]; c2<T> S[TB][NB]; } tri;
   };
   __shared__ RootShared shu;
   __shared__ int win[64];
   __shared__ int s_pos[2 * NB], s_src[2 * NB], s_cnt, s_sing;
+  __shared__ int s_dest[NB];         // DIRECT: new position of each top row not chosen
   __shared__ unsigned char s_top[NB];
   auto Mtri = shu.tri.M;
   auto Stmp = shu.tri.S;
   const int t = threadIdx.x;
-  gepp_init<T>(shu.g);
+  gepp_init(shu.g);
   const int i = t / GEPP_Q;
   int row;
-  if (nin == 0) {
-    row = (k0 + i < n) ? k0 + i : -1;    // m <= 128: all rows are candidates
+  if (DIRECT) {
+    row = (k0 + i < n) ? k0 + i : -1;
   } else {
     const int set = i >> 6;
     row = (set < nin) ? cin[((long long)b * 64 + set) * 64 + (i & 63)] : -1;
@@ -711,14 +746,14 @@ __global__ __launch_bounds__(GEPP_NT) void tslu_root_kernel(c2<T>* __restrict__ 
   Gepp<T> g;
   gepp_load<T>(g, A, n, k0, nbk, row);
   __syncthreads();
-  gepp_chunk<T>(g, nbk, shu.g);
+  gepp_chunk(g, nbk, shu.g);
   if (t < 64) win[t] = shu.g.win[t];
   if (t == 0) s_sing = shu.g.singular;
   __syncthreads();
   // ---- compact permutation
+  const int kend = k0 + nbk;
   if (t == 0) {
-    const int kend = k0 + nbk;
-    for (int k = 0; k < nbk; ++k) s_top[k] = 0;
+    for (int k = 0; k < nbk; ++k) { s_top[k] = 0; s_dest[k] = -1; }
     for (int k = 0; k < nbk; ++k)
       if (win[k] >= k0 && win[k] < kend) s_top[win[k] - k0] = 1;
     int cnt = nbk, d = 0;
@@ -728,6 +763,7 @@ __global__ __launch_bounds__(GEPP_NT) void tslu_root_kernel(c2<T>* __restrict__ 
         while (d < nbk - 1 && s_top[d]) ++d;   // next top row that was not chosen
         s_pos[cnt] = win[k];
         s_src[cnt] = k0 + d;
+        s_dest[d] = win[k];
         ++d;
         ++cnt;
       }
@@ -738,26 +774,37 @@ __global__ __launch_bounds__(GEPP_NT) void tslu_root_kernel(c2<T>* __restrict__ 
   __syncthreads();
   {
     int* P = perm + (long long)b * perm_stride + (long long)step * (1 + 4 * NB);
-    for (int e = t; e < 2 * NB; e += GEPP_NT) {
+    for (int e = t; e < 2 * NB; e += NT) {
       P[1 + e] = (e < s_cnt) ? s_pos[e] : -1;
       P[1 + 2 * NB + e] = (e < s_cnt) ? s_src[e] : -1;
     }
     if (t == 0) P[0] = s_cnt;
   }
-  // ---- save the displaced top rows (original panel values), slot e - nbk
-  c2<T>* sv = saved + (long long)b * NB * NB;
-  for (int e = t; e < (s_cnt - nbk) * nbk; e += GEPP_NT) {
-    const int q = e / nbk, c = e % nbk;
-    sv[q * NB + c] = A[(long long)s_src[nbk + q] * n + k0 + c];
+  if (!DIRECT) {
+    // ---- save the displaced top rows (original panel values), slot e - nbk
+    c2<T>* sv = saved + (long long)b * NB * NB;
+    for (int e = t; e < (s_cnt - nbk) * nbk; e += NT) {
+      const int q = e / nbk, c = e % nbk;
+      sv[q * NB + c] = A[(long long)s_src[nbk + q] * n + k0 + c];
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  // ---- winners' factored rows -> top rows; the inverses of L11 and U11 are taken
-  // from the registers (the written rows are not read back)
+  // ---- factored rows to their positions; every value comes from the registers
   int k = -1;
   if (g.chosen)
     for (int q = 0; q < nbk; ++q)
       if (win[q] == g.row) k = q;
   const int h = t % GEPP_Q;
+  int dest = -1;
+  if (k >= 0) dest = k0 + k;
+  else if (DIRECT && g.row >= 0) dest = (g.row < kend) ? s_dest[g.row - k0] : g.row;
+  if (dest >= 0) {
+#pragma unroll
+    for (int u = 0; u < GEPP_H; ++u) {
+      const int c = h * GEPP_H + u;
+      if (c < nbk) A[(long long)dest * n + k0 + c] = g.a[u];
+    }
+  }
   auto fill = [&]() {
     if (k >= 0) {
 #pragma unroll
@@ -767,19 +814,12 @@ __global__ __launch_bounds__(GEPP_NT) void tslu_root_kernel(c2<T>* __restrict__ 
       }
     }
   };
-  if (k >= 0) {
-#pragma unroll
-    for (int u = 0; u < GEPP_H; ++u) {
-      const int c = h * GEPP_H + u;
-      if (c < nbk) A[(long long)(k0 + k) * n + k0 + c] = g.a[u];
-    }
-  }
   fill();
   __syncthreads();
   c2<T>* Li = Linv + (long long)b * inv_stride + (long long)step * NB * NB;
   c2<T>* Ui = Uinv + (long long)b * inv_stride + (long long)step * NB * NB;
-  inv_unit_lower<T, NB, GEPP_NT>(Mtri, Stmp, nbk);
-  for (int e = t; e < NB * NB; e += GEPP_NT) {
+  inv_unit_lower<T, NB, NT>(Mtri, Stmp, nbk);
+  for (int e = t; e < NB * NB; e += NT) {
     const int r = e / NB, c = e % NB;
     c2<T> v = czero<T>();
     if (r < nbk && c < nbk) v = (r == c) ? cmk<T>(T(1), T(0)) : (c < r ? Mtri[r][c] : czero<T>());
@@ -788,8 +828,8 @@ __global__ __launch_bounds__(GEPP_NT) void tslu_root_kernel(c2<T>* __restrict__ 
   __syncthreads();
   fill();
   __syncthreads();
-  inv_upper<T, NB, GEPP_NT>(Mtri, Stmp, nbk);
-  for (int e = t; e < NB * NB; e += GEPP_NT) {
+  inv_upper<T, NB, NT>(Mtri, Stmp, nbk);
+  for (int e = t; e < NB * NB; e += NT) {
     const int r = e / NB, c = e % NB;
     Ui[e] = (r < nbk && c < nbk && c >= r) ? Mtri[r][c] : czero<T>();
   }
@@ -1335,11 +1375,24 @@ hipError_t lu_factor_batch(c2<T>* W, long long mstride, int n, int nbatch, void*
                            int pivot, hipStream_t st, LuTimers* tm) {
   constexpr int NB = LU_NB, IB = 8;
   if (n > 4096 || n < 1) return hipErrorInvalidValue;
+  if (pivot != LU_PIVOT_PARTIAL && pivot != LU_PIVOT_TOURNAMENT) return hipErrorInvalidValue;
   const int nsteps = (n + NB - 1) / NB;
-  if (pivot == LU_PIVOT_PARTIAL) {
-    int* ipiv = static_cast<int*>(scratch);
-    for (int s = 0; s < nsteps; ++s) {
-      const int k0 = s * NB, nbk = min(NB, n - k0);
+  // per-matrix scratch: ipiv (partial pivoting), or two candidate-set buffers
+  // (64 sets x 64 rows) and the saved displaced rows (NB x NB), each [nbatch][...]
+  int* ipiv = static_cast<int*>(scratch);
+  int* cand0 = static_cast<int*>(scratch);
+  int* cand1 = cand0 + (size_t)nbatch * 64 * 64;
+  c2<T>* saved = reinterpret_cast<c2<T>*>(cand1 + (size_t)nbatch * 64 * 64);
+  for (int s = 0; s < nsteps; ++s) {
+    const int k0 = s * NB, nbk = min(NB, n - k0), rows = n - k0;
+    if (rows <= 128) {
+      // the whole panel in registers (either pivot choice: this is partial pivoting)
+      tslu_root_kernel<T, NB, 128, true><<<nbatch, 512, 0, st>>>(W, mstride, n, k0, nbk, s, 0, nullptr, perm,
+                                                                  perm_stride, nullptr, Linv, Uinv, inv_stride, info);
+    } else if (rows <= 256) {
+      tslu_root_kernel<T, NB, 256, true><<<nbatch, 1024, 0, st>>>(W, mstride, n, k0, nbk, s, 0, nullptr, perm,
+                                                                   perm_stride, nullptr, Linv, Uinv, inv_stride, info);
+    } else if (pivot == LU_PIVOT_PARTIAL) {
       // panel rows n - k0 <= threads * rows-per-thread
       if (n <= 1024)
         lu_panel_kernel<T, NB, IB, 512, 2><<<nbatch, 512, 0, st>>>(W, mstride, n, k0, s, ipiv, perm, perm_stride, Linv, Uinv, inv_stride, info);
@@ -1347,38 +1400,21 @@ hipError_t lu_factor_batch(c2<T>* W, long long mstride, int n, int nbatch, void*
         lu_panel_kernel<T, NB, IB, 1024, 2><<<nbatch, 1024, 0, st>>>(W, mstride, n, k0, s, ipiv, perm, perm_stride, Linv, Uinv, inv_stride, info);
       else
         lu_panel_kernel<T, NB, IB, 1024, 4><<<nbatch, 1024, 0, st>>>(W, mstride, n, k0, s, ipiv, perm, perm_stride, Linv, Uinv, inv_stride, info);
-      launch_trailing<T>(W, mstride, n, nbatch, k0, nbk, s, perm, perm_stride, Linv, inv_stride, st, tm);
-    }
-    return hipGetLastError();
-  }
-  if (pivot != LU_PIVOT_TOURNAMENT) return hipErrorInvalidValue;
-  // per-matrix scratch: two candidate-set buffers (64 sets x 64 rows) and the saved
-  // displaced rows (NB x NB), laid out as [nbatch][...] each
-  int* cand0 = static_cast<int*>(scratch);
-  int* cand1 = cand0 + (size_t)nbatch * 64 * 64;
-  c2<T>* saved = reinterpret_cast<c2<T>*>(cand1 + (size_t)nbatch * 64 * 64);
-  for (int s = 0; s < nsteps; ++s) {
-    const int k0 = s * NB, nbk = min(NB, n - k0), rows = n - k0;
-    int nin = 0;
-    const int* cin = cand0;
-    if (rows > 128) {
-      const int nch = (rows + 127) / 128;     // <= 32 for n <= 4096
-      tslu_local_kernel<T><<<dim3((unsigned)(nbatch * nch)), GEPP_NT, 0, st>>>(W, mstride, n, k0, nbk, nch, cand0);
-      nin = nch;
+    } else {
+      const int nch = (rows + TSLU_ROWS - 1) / TSLU_ROWS;     // <= 32 for n <= 4096
+      tslu_local_kernel<T><<<dim3((unsigned)(nbatch * nch)), TSLU_NT, 0, st>>>(W, mstride, n, k0, nbk, nch, cand0);
+      int nin = nch;
       int* a = cand0;
-      int* b = cand1;
+      int* bb = cand1;
       while (nin > 2) {
         const int npair = (nin + 1) / 2;
-        tslu_merge_kernel<T><<<dim3((unsigned)(nbatch * npair)), GEPP_NT, 0, st>>>(W, mstride, n, k0, nbk, nin, a, b);
+        tslu_merge_kernel<T><<<dim3((unsigned)(nbatch * npair)), TSLU_NT, 0, st>>>(W, mstride, n, k0, nbk, nin, a, bb);
         nin = npair;
-        int* x = a; a = b; b = x;
+        int* x = a; a = bb; bb = x;
       }
-      cin = a;
-    }
-    tslu_root_kernel<T, NB><<<nbatch, GEPP_NT, 0, st>>>(W, mstride, n, k0, nbk, s, nin, cin, perm, perm_stride, saved,
-                                                    Linv, Uinv, inv_stride, info);
-    const int m = n - k0 - nbk;
-    if (m > 0) {
+      tslu_root_kernel<T, NB, 128, false><<<nbatch, 512, 0, st>>>(W, mstride, n, k0, nbk, s, nin, a, perm,
+                                                                   perm_stride, saved, Linv, Uinv, inv_stride, info);
+      const int m = n - k0 - nbk;   // > 0 here
       const int tr = (m + 63) / 64;
       const long long groups = (nbatch + 7) / 8;
       lu_gemm_kernel<T, GEMM_PANEL><<<dim3((unsigned)(groups * 8 * tr)), 256, 0, st>>>(

@@ -162,8 +162,15 @@ def nep_plan(problems, regions, opts, stream=None) -> Plan:
     cr = (nep_region * len(regions))()
     for i, r in enumerate(regions):
         cr[i] = nep_region(r.x0, r.x1, r.y0, r.y1, r.nx, r.ny)
+    batch, streams = int(getattr(opts, "batch", 0) or 0), int(getattr(opts, "streams", 0) or 0)
+    if batch == 0 and streams == 0 and not os.environ.get("NEP_NO_TUNING"):
+        # launch configuration from the autotuner's table (never changes a result bit)
+        from . import autotune
+        e = autotune.lookup(max(p.n for p in problems), opts.precision)
+        if e is not None:
+            batch, streams = int(e["batch"]), int(e["streams"])
     co = nep_options(opts.N, opts.s, opts.L, opts.tol_ind, opts.tol_svd, opts.tol_ver, opts.precision,
-                     opts.max_refine, int(getattr(opts, "batch", 0) or 0), int(getattr(opts, "streams", 0) or 0),
+                     opts.max_refine, batch, streams,
                      int(getattr(opts, "pivot", 0) or 0), int(getattr(opts, "graph", 0) or 0))
     if stream is None:
         stream = torch.cuda.current_stream().cuda_stream
