@@ -20,6 +20,9 @@ SOURCES = ["lu.hip", "sweep.hip", "beyn.hip", "mlp.hip", "nep_abi.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wno-unused-result",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # private arrays stay in registers/scratch: promoting them to LDS fills the
+         # CU's LDS (the panel kernel took 159 KB) and keeps other kernels off the CU
+         "-mllvm", "-disable-promote-alloca-to-lds",
          "-I" + os.path.join(os.path.dirname(HERE), "include")]
 
 
