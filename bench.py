@@ -152,6 +152,21 @@ def cpu_baseline(w, max_disks: int):
                       f"complex128 LAPACK gesv per node), {dt:.1f} s"}
 
 
+def copy_calibration(nbytes: int = 1 << 30, reps: int = 3):
+    """A plain device-to-device copy of `nbytes` (torch's copy kernel), for scaling
+    the FETCH_SIZE / WRITE_SIZE counters of a profiled run to bytes."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    return {"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps, "GBps": 2 * nbytes / dt / 1e9}
+
+
 def phase_dict(st):
     return {k: st[k] for k in ("ms_assemble", "ms_lu", "ms_solve", "ms_refine", "ms_sums", "ms_total")}
 
@@ -178,8 +193,13 @@ def main():
     ap.add_argument("--no-eigen", action="store_true")
     ap.add_argument("--pivot", choices=("partial", "tournament"), default="partial",
                     help="pivot choice of the node LU panels")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (counter calibration) and print its sizes")
     args = ap.parse_args()
     pivot = 0 if args.pivot == "partial" else 1
+    if args.copy_calibration:
+        print(json.dumps(copy_calibration()))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)

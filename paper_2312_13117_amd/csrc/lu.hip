@@ -897,13 +897,21 @@ __global__ __launch_bounds__(256) void lu_gemm_kernel(c2<T>* __restrict__ W, lon
 
   // accumulators start from C (update: C - A B) or zero (TRSM: A B); the C loads are in
   // flight together with the first operand chunks
-  acc4<T> cre[2][2], cim[2][2];
+  // UPDATE forms its complex products by three real products per block (Gauss / 3M):
+  // with the negated operand a' = -a and b,
+  //   A1 += a'.x b.x,  A2 += (-a'.y) b.y,  A3 += (a'.x + a'.y)(b.x + b.y),
+  // starting from A1 = Re C, A2 = 0, A3 = Im C + Re C; at the end re = A1 + A2 and
+  // im = A3 - A1 + A2.  The other modes use four real products into (c1, c3) = (re, im)
+  // (three accumulators would cost them occupancy).
+  constexpr bool G3 = MODE == GEMM_UPDATE;
+  acc4<T> c1[2][2], c2a[2][2], c3[2][2];
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) {
-      cre[bi][bj] = acc_zero<T>();
-      cim[bi][bj] = acc_zero<T>();
+      c1[bi][bj] = acc_zero<T>();
+      c2a[bi][bj] = acc_zero<T>();
+      c3[bi][bj] = acc_zero<T>();
       if (MODE == GEMM_UPDATE) {
         const int col = cb + bj * 16 + l16;
 #pragma unroll
@@ -911,8 +919,8 @@ __global__ __launch_bounds__(256) void lu_gemm_kernel(c2<T>* __restrict__ W, lon
           const int row = rb + bi * 16 + acc_row<T>(lane, r);
           if (row < n && col < n) {
             const c2<T> v = A[(long long)row * n + col];
-            cre[bi][bj][r] = v.x;
-            cim[bi][bj][r] = v.y;
+            c1[bi][bj][r] = v.x;
+            c3[bi][bj][r] = v.y + v.x;
           }
         }
       }
@@ -994,21 +1002,43 @@ __global__ __launch_bounds__(256) void lu_gemm_kernel(c2<T>* __restrict__ W, lon
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi) af[bi] = cmk<T>(-af[bi].x, -af[bi].y);   // C - A B
       }
-      // real parts of A first, then imaginary parts: dependent products 8 apart
+      if (G3) {
+        T as[2], bs[2];
 #pragma unroll
-      for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj) {
-          cre[bi][bj] = mfma16(af[bi].x, bf[bj].x, cre[bi][bj]);
-          cim[bi][bj] = mfma16(af[bi].x, bf[bj].y, cim[bi][bj]);
+        for (int q = 0; q < 2; ++q) {
+          as[q] = af[q].x + af[q].y;
+          bs[q] = bf[q].x + bf[q].y;
         }
+        // the three products of a block are 4 apart in issue order
 #pragma unroll
-      for (int bi = 0; bi < 2; ++bi)
+        for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj) {
-          cre[bi][bj] = mfma16(-af[bi].y, bf[bj].y, cre[bi][bj]);
-          cim[bi][bj] = mfma16(af[bi].y, bf[bj].x, cim[bi][bj]);
-        }
+          for (int bj = 0; bj < 2; ++bj) c1[bi][bj] = mfma16(af[bi].x, bf[bj].x, c1[bi][bj]);
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj) c2a[bi][bj] = mfma16(-af[bi].y, bf[bj].y, c2a[bi][bj]);
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj) c3[bi][bj] = mfma16(as[bi], bs[bj], c3[bi][bj]);
+      } else {
+        // real parts of A first, then imaginary parts: dependent products 8 apart
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj) {
+            c1[bi][bj] = mfma16(af[bi].x, bf[bj].x, c1[bi][bj]);
+            c3[bi][bj] = mfma16(af[bi].x, bf[bj].y, c3[bi][bj]);
+          }
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj) {
+            c1[bi][bj] = mfma16(-af[bi].y, bf[bj].y, c1[bi][bj]);
+            c3[bi][bj] = mfma16(af[bi].y, bf[bj].x, c3[bi][bj]);
+          }
+      }
     }
     if (c + 1 < nch) {
       store_chunk(buf ^ 1);                  // chunk c+1 (its readers finished at the last barrier)
@@ -1026,7 +1056,15 @@ __global__ __launch_bounds__(256) void lu_gemm_kernel(c2<T>* __restrict__ W, lon
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = rb + bi * 16 + acc_row<T>(lane, r);
-        if (row < rlim && col < clim) A[(long long)row * n + col] = cmk<T>(cre[bi][bj][r], cim[bi][bj][r]);
+        if (row < rlim && col < clim) {
+          const T a1 = c1[bi][bj][r], a3 = c3[bi][bj][r];
+          if (G3) {
+            const T a2 = c2a[bi][bj][r];
+            A[(long long)row * n + col] = cmk<T>(a1 + a2, a3 - a1 + a2);
+          } else {
+            A[(long long)row * n + col] = cmk<T>(a1, a3);
+          }
+        }
       }
     }
   if (MODE == GEMM_TRSM) {
