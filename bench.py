@@ -171,11 +171,33 @@ def phase_dict(st):
     return {k: st[k] for k in ("ms_assemble", "ms_lu", "ms_solve", "ms_refine", "ms_sums", "ms_total")}
 
 
-def roofline(st, prec):
+def measured_traffic(workload: str, prec: str):
+    """HBM bytes per launch of the update kernel from the committed counter summary,
+    or None when there is none for this workload or the LU source has changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "lu_update_traffic_dense_n1024.md")
+    try:
+        kv = {}
+        for line in open(path):
+            if ":" in line and not line.startswith(("#", "`", " ")):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        src = os.path.join(ROOT, kv["kernel_source"])
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if h != kv["kernel_source_sha256"] or kv["workload"] != workload or kv["precision"] != prec:
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def roofline(st, prec, workload=None):
     achieved = st["gemm_flops"] / (st["ms_gemm"] * 1e-3) if st["ms_gemm"] > 0 else 0.0
+    traffic = measured_traffic(workload, prec) if workload else None
     return {"kernel": "lu_gemm_kernel<update> (trailing update of the batched LU)", "bound": "mfma",
             "achieved": achieved / 1e12, "peak": PEAK[prec] / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / PEAK[prec], "traffic": None, "launches": st["gemm_launches"],
+            "frac": achieved / PEAK[prec], "traffic": traffic, "traffic_unit": "bytes per launch (HBM, counters)",
+            "launches": st["gemm_launches"],
             "avg_launch_ms": st["ms_gemm"] / max(1, st["gemm_launches"]),
             "flops_per_launch": st["gemm_flops"] / max(1, st["gemm_launches"])}
 
@@ -235,7 +257,7 @@ def main():
         "phase_ms": phase_dict(st),
         "lu_tflops": lu_rate / 1e12,
         "lu_frac_of_peak": lu_rate / PEAK[prec],
-        "roofline": roofline(st, prec),
+        "roofline": roofline(st, prec, w.name),
     }
     if args.workload == "dense" and not args.no_mixed:
         wm = build_workload("dense_mixed", pivot=pivot)
