@@ -116,19 +116,31 @@ class Runner:
         self.N.nep_destroy(self.plan)
 
 
+VERBOSE = False
+
+
+def _log(msg):
+    if VERBOSE:
+        print(msg, file=sys.stderr, flush=True)
+
+
 def timed(runner, steps: int, warmup: int):
     import torch
-    for _ in range(warmup):
+    for i in range(warmup):
+        t0 = time.perf_counter()
         runner.step()
+        torch.cuda.synchronize()
+        _log(f"{runner.w.name}: warm-up step {i + 1}/{warmup} {time.perf_counter() - t0:.2f} s")
     torch.cuda.synchronize()
     times, outs = [], []
-    for _ in range(steps):
+    for i in range(steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         o = runner.step()
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
         outs.append(o)
+        _log(f"{runner.w.name}: step {i + 1}/{steps} {times[-1]:.2f} s")
     k = int(np.argsort(times)[len(times) // 2])
     return float(np.median(times)), outs[k]
 
@@ -215,9 +227,12 @@ def main():
     ap.add_argument("--no-eigen", action="store_true")
     ap.add_argument("--pivot", choices=("partial", "tournament"), default="partial",
                     help="pivot choice of the node LU panels")
+    ap.add_argument("--verbose", action="store_true", help="one stderr line per step")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration) and print its sizes")
     args = ap.parse_args()
+    global VERBOSE
+    VERBOSE = args.verbose
     pivot = 0 if args.pivot == "partial" else 1
     if args.copy_calibration:
         print(json.dumps(copy_calibration()))
@@ -255,6 +270,8 @@ def main():
         "flagged_disks": int(np.sum(o["flags"])),
         "candidates": o["ncand"],
         "phase_ms": phase_dict(st),
+        "refine_sweeps": st["refine_sweeps"],
+        "refine_fallbacks": st["refine_fallbacks"],
         "lu_tflops": lu_rate / 1e12,
         "lu_frac_of_peak": lu_rate / PEAK[prec],
         "roofline": roofline(st, prec, w.name),

@@ -123,6 +123,7 @@ struct nep_plan {
   std::vector<const void*> graph_F, graph_V;
   nep_stats graph_stats{};
   DevBuf fbflag;                      // per task: complex128 re-solve needed (mixed precision)
+  DevBuf fbx, fbz;                    // gathered right-hand sides and nodes of complex128 re-solves
 };
 
 static nep_status fail(nep_plan_t* p, nep_status s, const char* fmt, ...) {
@@ -387,6 +388,8 @@ extern "C" void nep_destroy(nep_plan_t* P) {
   if (P->graph) hipGraphDestroy(P->graph);
   if (P->cap_st) hipStreamDestroy(P->cap_st);
   P->fbflag.release();
+  P->fbx.release();
+  P->fbz.release();
   if (P->ev_fork) hipEventDestroy(P->ev_fork);
   for (auto& e : P->ev_join) if (e) hipEventDestroy(e);
   for (auto& e : P->gemm_ev) if (e) hipEventDestroy(e);
@@ -442,6 +445,47 @@ static nep_status ensure_fp64_ws(nep_plan_t* P, int n, int B) {
   HIPCHK(P, w.Linv.alloc(16ull * B * steps * LU_NB * LU_NB));
   HIPCHK(P, w.Uinv.alloc(16ull * B * steps * LU_NB * LU_NB));
   HIPCHK(P, w.info.alloc(sizeof(int) * B));
+  return NEP_OK;
+}
+
+// complex128 re-solves of mixed-precision nodes that did not converge: the listed
+// nodes of one problem are gathered (node value, right-hand sides) into batches of up
+// to 32, factored and solved together on the plan stream, and the solutions copied
+// back to their slots.
+struct FbTask {
+  const double2* z;   // device: the node
+  double2* x;         // device: the node's n x m solution slot
+};
+
+static nep_status fallback_solves(nep_plan_t* P, int prob, const SweepCall& sc, const std::vector<FbTask>& tasks) {
+  constexpr int FB = 32;
+  const int n = P->pd[prob].n, s = sc.s, L = sc.L, m = s + L;
+  if (tasks.empty()) return NEP_OK;
+  const int cap = std::min<int>(FB, (int)tasks.size());
+  nep_status e = ensure_fp64_ws(P, n, cap);
+  if (e != NEP_OK) return e;
+  HIPCHK(P, P->fbx.alloc(sizeof(double2) * (size_t)cap * n * m));
+  HIPCHK(P, P->fbz.alloc(sizeof(double2) * cap));
+  const double2* F = static_cast<const double2*>(sc.F[prob]);
+  const double2* V = (L > 0) ? static_cast<const double2*>(sc.V[prob]) : nullptr;
+  hipStream_t st = P->w64.st;
+  double2* xb = P->fbx.as<double2>();
+  double2* zb = P->fbz.as<double2>();
+  for (size_t c0 = 0; c0 < tasks.size(); c0 += cap) {
+    const int c = (int)std::min<size_t>(cap, tasks.size() - c0);
+    for (int i = 0; i < c; ++i)
+      HIPCHK(P, hipMemcpyAsync(zb + i, tasks[c0 + i].z, sizeof(double2), hipMemcpyDeviceToDevice, st));
+    HIPCHK(P, launch_rhs(F, s, V, L, n, xb, (long long)n * m, c, st));
+    e = factor_chunk<double>(P, P->w64, P->pd[prob], zb, c);
+    if (e != NEP_OK) return e;
+    e = solve_chunk<double>(P, P->w64, n, c, xb, m, false, nullptr);
+    if (e != NEP_OK) return e;
+    for (int i = 0; i < c; ++i)
+      HIPCHK(P, hipMemcpyAsync(tasks[c0 + i].x, xb + (size_t)i * n * m, sizeof(double2) * (size_t)n * m,
+                               hipMemcpyDeviceToDevice, st));
+    P->stats.refine_fallbacks += c;
+  }
+  HIPCHK(P, hipStreamSynchronize(st));
   return NEP_OK;
 }
 
@@ -518,20 +562,12 @@ static nep_status sweep_batch(nep_plan_t* P, Workspace& w, int prob, const doubl
     nact = 0;
     for (int b = 0; b < nb; ++b) nact += act[b];
     if (nact > 0) {
-      nep_status e = ensure_fp64_ws(P, n, 1);
+      std::vector<FbTask> tasks;
+      for (int b = 0; b < nb; ++b)
+        if (act[b]) tasks.push_back({zb + b, Xb + (long long)b * n * m});
+      *fallback = true;
+      nep_status e = fallback_solves(P, prob, sc, tasks);
       if (e != NEP_OK) return e;
-      for (int b = 0; b < nb; ++b) {
-        if (!act[b]) continue;
-        *fallback = true;
-        P->stats.refine_fallbacks++;
-        double2* xb = Xb + (long long)b * n * m;
-        HIPCHK(P, launch_rhs(F, s, V, L, n, xb, (long long)n * m, 1, P->w64.st));
-        e = factor_chunk<double>(P, P->w64, pd, zb + b, 1);
-        if (e != NEP_OK) return e;
-        e = solve_chunk<double>(P, P->w64, n, 1, xb, m, false, nullptr);
-        if (e != NEP_OK) return e;
-      }
-      HIPCHK(P, hipStreamSynchronize(P->w64.st));
     }
   }
   tmark(P, PH_REFINE, false, w.st);
@@ -652,23 +688,15 @@ static nep_status graph_fallbacks(nep_plan_t* P, const SweepCall& sc, const Swee
   HIPCHK(P, hipStreamSynchronize(P->st));
   double2* X = P->X.as<double2>();
   const double2* tn = P->tnode.as<double2>();
-  for (int li = 0; li < nl; ++li) {
-    for (int j = 0; j < N; ++j) {
-      if (!fb[(size_t)li * N + j]) continue;
-      const int d = sc.disks[li], prob = P->d_prob[d], n = P->d_n[d];
-      nep_status e = ensure_fp64_ws(P, n, 1);
-      if (e != NEP_OK) return e;
-      double2* xb = X + lay.xoff[li] + (long long)j * n * m;
-      const double2* F = static_cast<const double2*>(sc.F[prob]);
-      const double2* V = (L > 0) ? static_cast<const double2*>(sc.V[prob]) : nullptr;
-      HIPCHK(P, launch_rhs(F, s, V, L, n, xb, (long long)n * m, 1, P->w64.st));
-      e = factor_chunk<double>(P, P->w64, P->pd[prob], tn + (size_t)li * N + j, 1);
-      if (e != NEP_OK) return e;
-      e = solve_chunk<double>(P, P->w64, n, 1, xb, m, false, nullptr);
-      if (e != NEP_OK) return e;
-      ++*count;
-      P->stats.refine_fallbacks++;
-    }
+  for (const auto& g : lay.groups) {          // one problem per group
+    std::vector<FbTask> tasks;
+    for (int li = g.li; li < g.lj; ++li)
+      for (int j = 0; j < N; ++j)
+        if (fb[(size_t)li * N + j])
+          tasks.push_back({tn + (size_t)li * N + j, X + lay.xoff[li] + (long long)j * g.n * m});
+    nep_status e = fallback_solves(P, P->d_prob[sc.disks[g.li]], sc, tasks);
+    if (e != NEP_OK) return e;
+    *count += (int)tasks.size();
   }
   if (*count > 0) return run_sums(P, sc, lay);
   return NEP_OK;

@@ -71,9 +71,14 @@ def test_graph_replays_equal_eager(N, prec, max_refine):
     for r in reps:
         _same(eager, r)
     if prec == 1 and max_refine == 0:
-        # no refinement sweeps: every node takes the complex128 re-solve
+        # no refinement sweeps: every node takes the complex128 re-solve (gathered in
+        # batches of 32), which must give the complex128 sweep's bits
         assert eager[3] == N.NEP_WARN_REFINE_FALLBACK
         assert all(r[5]["refine_fallbacks"] == 16 * 32 for r in reps)
+        fp64 = _run(N, w.problems, w.regions, gen.Options(N=32, s=1, L=8, precision=0), w.F, w.V, 1)[0]
+        assert np.array_equal(fp64[1], eager[1])
+        for x, y in zip(fp64[4], eager[4]):
+            assert np.array_equal(x, y)
 
 
 def test_graph_uneven_plan_and_beyn_between(N):
