@@ -897,13 +897,15 @@ __global__ __launch_bounds__(256) void lu_gemm_kernel(c2<T>* __restrict__ W, lon
 
   // accumulators start from C (update: C - A B) or zero (TRSM: A B); the C loads are in
   // flight together with the first operand chunks
-  // UPDATE forms its complex products by three real products per block (Gauss / 3M):
-  // with the negated operand a' = -a and b,
+  // The complex128 UPDATE forms its complex products by three real products per
+  // block (Gauss / 3M): with the negated operand a' = -a and b,
   //   A1 += a'.x b.x,  A2 += (-a'.y) b.y,  A3 += (a'.x + a'.y)(b.x + b.y),
   // starting from A1 = Re C, A2 = 0, A3 = Im C + Re C; at the end re = A1 + A2 and
-  // im = A3 - A1 + A2.  The other modes use four real products into (c1, c3) = (re, im)
-  // (three accumulators would cost them occupancy).
-  constexpr bool G3 = MODE == GEMM_UPDATE;
+  // im = A3 - A1 + A2.  Everything else uses four real products into (c1, c3) =
+  // (re, im): in the other modes a third accumulator would cost occupancy, and in
+  // complex64 the larger rounding error of 3M more than doubled the nodes whose
+  // refinement fails (delay workload: 230 instead of 96 of 49152).
+  constexpr bool G3 = MODE == GEMM_UPDATE && sizeof(T) == 8;
   acc4<T> c1[2][2], c2a[2][2], c3[2][2];
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
@@ -920,7 +922,7 @@ __global__ __launch_bounds__(256) void lu_gemm_kernel(c2<T>* __restrict__ W, lon
           if (row < n && col < n) {
             const c2<T> v = A[(long long)row * n + col];
             c1[bi][bj][r] = v.x;
-            c3[bi][bj][r] = v.y + v.x;
+            c3[bi][bj][r] = G3 ? v.y + v.x : v.y;
           }
         }
       }
