@@ -599,15 +599,12 @@ __device__ __forceinline__ void gepp_chunk(Gepp<T>& g, int nbk, GeppShared<T, R,
       }
       if (lane == 0) sh.keys[buf][wave] = wk;
       __syncthreads();
-      K best = 0;
-      int bw = 0;
-#pragma unroll
-      for (int w = 0; w < NW; ++w) {
-        const K k = sh.keys[buf][w];
-        if (k > best) { best = k; bw = w; }
-      }
+      // the best of the wave keys, reduced once more across a wave; the winning row's
+      // index names its wave (16 rows per wave)
+      const K best = wave_max_key<K>(lane < NW ? sh.keys[buf][lane] : K(0));
       if (best == 0) { done = true; continue; }         // no candidate rows left (uniform)
       const int pi = (int)(MASK - (best & MASK));
+      const int bw = pi / (64 / GEPP_Q);
       if ((best & ~MASK) == 0 && t == 0) sh.singular = 1;
       if (i == pi) {
         g.chosen = true;
@@ -832,6 +829,282 @@ __global__ __launch_bounds__(4 * R) void tslu_root_kernel(c2<T>* __restrict__ W,
   for (int e = t; e < NB * NB; e += NT) {
     const int r = e / NB, c = e % NB;
     Ui[e] = (r < nbk && c < nbk && c >= r) ? Mtri[r][c] : czero<T>();
+  }
+}
+
+// ----------------------------------------------------------------------------- recursive panel
+// Panels of more than 256 rows under partial pivoting, as four 16-column leaves.  A
+// leaf holds rows r0 .. n-1 of its 16 columns in registers (RPT rows per thread, 1024
+// threads), runs partial pivoting on them (one barrier per column; 64-bit keys hold
+// the magnitude's top bits and the row), writes the factored columns at their
+// exchanged rows, applies its exchange to the panel's other 48 columns and forms the
+// 16 rows of U to its right inside the panel.  A rank-16 update of the rows below
+// follows as a launch of its own (many workgroups per matrix).  A finishing kernel
+// composes the four exchanges into the step's one and forms inv(L11) and inv(U11).
+constexpr int RP_W = 16, RP_NT = 1024, RP_NW = RP_NT / 64;
+constexpr int RP_EX = 1 + 4 * RP_W;   // leaf exchange record: cnt, pos[2W], src[2W]
+
+__device__ inline unsigned long long rp_key(double m, int i) {
+  return ((unsigned long long)__double_as_longlong(m) & ~4095ull) | (unsigned long long)(4095 - i);
+}
+__device__ inline unsigned long long rp_key(float m, int i) {
+  return ((unsigned long long)__float_as_uint(m) << 16) | (unsigned long long)(4095 - i);
+}
+
+template <typename T, int RPT>
+__global__ __launch_bounds__(RP_NT) void rpanel_leaf_kernel(c2<T>* __restrict__ W, long long mstride, int n,
+                                                            int k0, int q, int* __restrict__ sub,
+                                                            int* __restrict__ info) {
+  using K = unsigned long long;
+  constexpr K MASK = 4095;
+  const int b = blockIdx.x, t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  c2<T>* A = W + (long long)b * mstride;
+  const int c0 = k0 + RP_W * q, r0 = c0;           // the leaf's first column and first row
+  const int cr = c0 + RP_W, wr = k0 + 64 - cr;     // panel columns right of the leaf
+  __shared__ c2<T> rowbuf[2][RP_NW][RP_W];
+  __shared__ c2<T> rinv[2][RP_NW];
+  __shared__ K keys[2][RP_NW];
+  __shared__ int win[RP_W];
+  __shared__ int s_pos[2 * RP_W], s_src[2 * RP_W], s_cnt, s_sing;
+  __shared__ int s_dest[RP_W];
+  __shared__ unsigned char s_top[RP_W];
+  __shared__ c2<T> xbuf[2 * RP_W][48];             // exchanged rows of the other 48 panel columns
+  __shared__ c2<T> Lqq[RP_W][RP_W + 1];
+
+  c2<T> a[RPT][RP_W];
+  int row[RPT];
+  bool chosen[RPT];
+#pragma unroll
+  for (int p = 0; p < RPT; ++p) {
+    const int r = r0 + t + p * RP_NT;
+    row[p] = r < n ? r : -1;
+    chosen[p] = false;
+#pragma unroll
+    for (int u = 0; u < RP_W; ++u) a[p][u] = (r < n) ? A[(long long)r * n + c0 + u] : czero<T>();
+  }
+  if (t == 0) s_sing = 0;
+  if (t < RP_W) win[t] = -1;
+  __syncthreads();
+#pragma clang loop unroll(full)
+  for (int j = 0; j < RP_W; ++j) {
+    const int buf = j & 1;
+    K key = 0;
+    c2<T> ajj = czero<T>();
+    int bp = 0;
+#pragma unroll
+    for (int p = 0; p < RPT; ++p) {
+      if (row[p] >= 0 && !chosen[p]) {
+        const K kk = rp_key(cabs1<T>(a[p][j]), row[p] - r0);
+        if (kk > key) { key = kk; ajj = a[p][j]; bp = p; }
+      }
+    }
+    const bool nzj = ajj.x != T(0) || ajj.y != T(0);
+    const c2<T> r = nzj ? crcp<T>(ajj) : czero<T>();
+    const K wk = wave_max_key<K>(key);
+    if (wk != 0 && key == wk) {                     // this thread holds the wave's best row
+#pragma unroll
+      for (int p = 0; p < RPT; ++p)
+        if (p == bp) {
+#pragma unroll
+          for (int u = 0; u < RP_W; ++u) rowbuf[buf][wave][u] = a[p][u];
+        }
+      rinv[buf][wave] = r;
+    }
+    if (lane == 0) keys[buf][wave] = wk;
+    __syncthreads();
+    // the best of the wave keys, reduced once more across a wave; the winning row's
+    // index names the thread (row r0 + t + p * RP_NT) and so its wave
+    const K best = wave_max_key<K>(lane < RP_NW ? keys[buf][lane] : K(0));
+    const int bi = (int)(MASK - (best & MASK));          // rows > 16 remain, so best != 0
+    const int pi = r0 + bi;
+    const int bw = (bi % RP_NT) / 64;
+    if ((best & ~MASK) == 0 && t == 0) s_sing = 1;
+#pragma unroll
+    for (int p = 0; p < RPT; ++p)
+      if (row[p] == pi) { chosen[p] = true; win[j] = pi; }
+    const c2<T>* prow = rowbuf[buf][bw];
+    const c2<T> rp = rinv[buf][bw];
+#pragma unroll
+    for (int p = 0; p < RPT; ++p) {
+      if (row[p] >= 0 && !chosen[p]) {
+        const c2<T> l = cmul<T>(a[p][j], rp);
+        a[p][j] = l;
+#pragma unroll
+        for (int u = j + 1; u < RP_W; ++u) {
+          const c2<T> pv = prow[u];
+          a[p][u].x = fma(-l.x, pv.x, fma(l.y, pv.y, a[p][u].x));
+          a[p][u].y = fma(-l.x, pv.y, fma(-l.y, pv.x, a[p][u].y));
+          // keep at most four pivot-row entries in flight (the row itself fills half
+          // of the registers a 1024-thread workgroup may use)
+          if ((u - j) % 4 == 0) __asm__ volatile("" ::: "memory");
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // ---- the leaf's exchange: top rows r0 + k <- winner k; the top rows not chosen fill
+  // the positions the winners below vacate
+  if (t == 0) {
+    const int tend = r0 + RP_W;
+    for (int k = 0; k < RP_W; ++k) { s_top[k] = 0; s_dest[k] = -1; }
+    for (int k = 0; k < RP_W; ++k)
+      if (win[k] >= r0 && win[k] < tend) s_top[win[k] - r0] = 1;
+    int cnt = RP_W, d = 0;
+    for (int k = 0; k < RP_W; ++k) { s_pos[k] = r0 + k; s_src[k] = win[k]; }
+    for (int k = 0; k < RP_W; ++k) {
+      if (win[k] >= tend) {
+        while (d < RP_W - 1 && s_top[d]) ++d;
+        s_pos[cnt] = win[k];
+        s_src[cnt] = r0 + d;
+        s_dest[d] = win[k];
+        ++d;
+        ++cnt;
+      }
+    }
+    s_cnt = cnt;
+    if (s_sing && info[b] == 0) info[b] = c0 + 1;
+    int* R = sub + ((long long)b * 4 + q) * RP_EX;
+    R[0] = cnt;
+    for (int i = 0; i < 2 * RP_W; ++i) {
+      R[1 + i] = i < cnt ? s_pos[i] : -1;
+      R[1 + 2 * RP_W + i] = i < cnt ? s_src[i] : -1;
+    }
+  }
+  __syncthreads();
+  const int cnt = s_cnt;
+  // ---- factored leaf columns at their new rows; the chosen rows also into Lqq
+#pragma unroll
+  for (int p = 0; p < RPT; ++p) {
+    if (row[p] < 0) continue;
+    int dest = row[p];
+    if (chosen[p]) {
+      for (int k = 0; k < RP_W; ++k)
+        if (win[k] == row[p]) dest = r0 + k;
+#pragma unroll
+      for (int u = 0; u < RP_W; ++u) Lqq[dest - r0][u] = a[p][u];
+    } else if (row[p] < r0 + RP_W) {
+      dest = s_dest[row[p] - r0];
+    }
+    if (dest >= 0) {
+#pragma unroll
+      for (int u = 0; u < RP_W; ++u) A[(long long)dest * n + c0 + u] = a[p][u];
+    }
+  }
+  // ---- the exchange on the other 48 panel columns (gathered before any is written)
+  auto ocol = [&](int cc) { return cc < RP_W * q ? k0 + cc : k0 + RP_W + cc; };
+  for (int e = t; e < cnt * 48; e += RP_NT) {
+    const int i = e / 48, cc = e % 48;
+    xbuf[i][cc] = A[(long long)s_src[i] * n + ocol(cc)];
+  }
+  __syncthreads();
+  const int cright = RP_W * q;                      // xbuf columns >= cright lie right of the leaf
+  for (int e = t; e < cnt * 48; e += RP_NT) {
+    const int i = e / 48, cc = e % 48;
+    if (i < RP_W && cc >= cright) continue;         // the top rows' right part: U, written below
+    A[(long long)s_pos[i] * n + ocol(cc)] = xbuf[i][cc];
+  }
+  // ---- U rows right of the leaf: inv(L_qq) times the exchanged top rows (one column
+  // per thread, forward substitution out of LDS)
+  if (t < wr) {
+    const int cc = cright + t;                      // each thread owns one column of xbuf
+    for (int i = 0; i < RP_W; ++i) {
+      c2<T> v = xbuf[i][cc];
+      for (int l = 0; l < i; ++l) v = cfms<T>(v, Lqq[i][l], xbuf[l][cc]);
+      xbuf[i][cc] = v;
+      A[(long long)(r0 + i) * n + cr + t] = v;
+    }
+  }
+}
+
+// rank-16 update of the panel columns right of leaf q, rows below the leaf's top rows:
+// A[r, cr:k0+64] -= L[r, c0:c0+16] U[r0:r0+16, cr:k0+64]; 64 rows per workgroup
+template <typename T>
+__global__ __launch_bounds__(256) void rpanel_update_kernel(c2<T>* __restrict__ W, long long mstride, int n, int k0,
+                                                            int q, int tiles) {
+  const int b = blockIdx.x / tiles, tile = blockIdx.x % tiles, t = threadIdx.x;
+  c2<T>* A = W + (long long)b * mstride;
+  const int c0 = k0 + RP_W * q, r0 = c0, cr = c0 + RP_W, wr = k0 + 64 - cr;
+  const int R0 = r0 + RP_W + tile * 64;
+  __shared__ c2<T> U[RP_W][48];
+  __shared__ c2<T> Lt[64][RP_W + 1];
+  for (int e = t; e < RP_W * wr; e += 256) U[e / wr][e % wr] = A[(long long)(r0 + e / wr) * n + cr + e % wr];
+  for (int e = t; e < 64 * RP_W; e += 256) {
+    const int i = e / RP_W, u = e % RP_W, r = R0 + i;
+    Lt[i][u] = r < n ? A[(long long)r * n + c0 + u] : czero<T>();
+  }
+  __syncthreads();
+  for (int e = t; e < 64 * wr; e += 256) {
+    const int i = e / wr, c = e % wr, r = R0 + i;
+    if (r >= n) continue;
+    c2<T> v = A[(long long)r * n + cr + c];
+#pragma unroll
+    for (int u = 0; u < RP_W; ++u) v = cfms<T>(v, Lt[i][u], U[u][c]);
+    A[(long long)r * n + cr + c] = v;
+  }
+}
+
+// the step's exchange (the four leaf exchanges composed, top rows first) and the
+// inverses of the factored 64 x 64 diagonal block
+template <typename T, int NB>
+__global__ __launch_bounds__(256) void rpanel_finish_kernel(const c2<T>* __restrict__ W, long long mstride, int n,
+                                                            int k0, int step, const int* __restrict__ sub,
+                                                            int* __restrict__ perm, long long perm_stride,
+                                                            c2<T>* __restrict__ Linv, c2<T>* __restrict__ Uinv,
+                                                            long long inv_stride) {
+  const int b = blockIdx.x, t = threadIdx.x;
+  const c2<T>* A = W + (long long)b * mstride;
+  __shared__ c2<T> Mtri[NB][NB + 1];
+  __shared__ c2<T> Stmp[TB][NB];
+  // srcmap[r - k0] = original row now at position r (rows k0 .. n-1, n <= 4096)
+  __shared__ int srcmap[4096];
+  __shared__ int nv[2 * RP_W];
+  __shared__ unsigned char emitted[4096];
+  for (int i = t; i < n - k0; i += 256) { srcmap[i] = k0 + i; emitted[i] = 0; }
+  __syncthreads();
+  for (int q = 0; q < 4; ++q) {
+    const int* R = sub + ((long long)b * 4 + q) * RP_EX;
+    const int cnt = R[0];
+    if (t < cnt) nv[t] = srcmap[R[1 + 2 * RP_W + t] - k0];   // sources before this leaf
+    __syncthreads();
+    if (t < cnt) srcmap[R[1 + t] - k0] = nv[t];
+    __syncthreads();
+  }
+  if (t == 0) {
+    // record: the top rows k0 .. k0+63 in order, then every other position that moved
+    int* P = perm + (long long)b * perm_stride + (long long)step * (1 + 4 * NB);
+    int cnt = 0;
+    for (int k = 0; k < NB; ++k) { P[1 + cnt] = k0 + k; P[1 + 2 * NB + cnt] = srcmap[k]; ++cnt; }
+    for (int q = 0; q < 4; ++q) {
+      const int* R = sub + ((long long)b * 4 + q) * RP_EX;
+      for (int i = 0; i < R[0]; ++i) {
+        const int pos = R[1 + i];
+        if (pos >= k0 + NB && !emitted[pos - k0] && srcmap[pos - k0] != pos && cnt < 2 * NB) {
+          emitted[pos - k0] = 1;
+          P[1 + cnt] = pos;
+          P[1 + 2 * NB + cnt] = srcmap[pos - k0];
+          ++cnt;
+        }
+      }
+    }
+    for (int e = cnt; e < 2 * NB; ++e) { P[1 + e] = -1; P[1 + 2 * NB + e] = -1; }
+    P[0] = cnt;
+  }
+  for (int e = t; e < NB * NB; e += 256) Mtri[e / NB][e % NB] = A[(long long)(k0 + e / NB) * n + k0 + e % NB];
+  __syncthreads();
+  c2<T>* Li = Linv + (long long)b * inv_stride + (long long)step * NB * NB;
+  c2<T>* Ui = Uinv + (long long)b * inv_stride + (long long)step * NB * NB;
+  inv_unit_lower<T, NB, 256>(Mtri, Stmp, NB);
+  for (int e = t; e < NB * NB; e += 256) {
+    const int r = e / NB, c = e % NB;
+    Li[e] = (r == c) ? cmk<T>(T(1), T(0)) : (c < r ? Mtri[r][c] : czero<T>());
+  }
+  __syncthreads();
+  for (int e = t; e < NB * NB; e += 256) Mtri[e / NB][e % NB] = A[(long long)(k0 + e / NB) * n + k0 + e % NB];
+  __syncthreads();
+  inv_upper<T, NB, 256>(Mtri, Stmp, NB);
+  for (int e = t; e < NB * NB; e += 256) {
+    const int r = e / NB, c = e % NB;
+    Ui[e] = (c >= r) ? Mtri[r][c] : czero<T>();
   }
 }
 
@@ -1404,7 +1677,7 @@ static void launch_trailing(c2<T>* W, long long mstride, int n, int nbatch, int 
 }
 
 size_t lu_factor_scratch_bytes(int n, size_t elem_bytes) {
-  const size_t partial = sizeof(int) * (size_t)n;
+  const size_t partial = sizeof(int) * ((size_t)n + 4 * RP_EX);
   const size_t tournament = 2 * sizeof(int) * 64 * 64 + elem_bytes * (size_t)LU_NB * LU_NB;
   return partial > tournament ? partial : tournament;
 }
@@ -1432,6 +1705,26 @@ hipError_t lu_factor_batch(c2<T>* W, long long mstride, int n, int nbatch, void*
     } else if (rows <= 256) {
       tslu_root_kernel<T, NB, 256, true><<<nbatch, 1024, 0, st>>>(W, mstride, n, k0, nbk, s, 0, nullptr, perm,
                                                                    perm_stride, nullptr, Linv, Uinv, inv_stride, info);
+    } else if (pivot == LU_PIVOT_PARTIAL && (rows <= RP_NT || (sizeof(T) == 4 && rows <= 2 * RP_NT))) {
+      // recursive panel: four register leaves with rank-16 updates between them
+      int* sub = ipiv + (size_t)nbatch * n;
+      for (int q = 0; q < 4; ++q) {
+        if constexpr (sizeof(T) == 4) {
+          if (rows > RP_NT) {
+            rpanel_leaf_kernel<T, 2><<<nbatch, RP_NT, 0, st>>>(W, mstride, n, k0, q, sub, info);
+          } else {
+            rpanel_leaf_kernel<T, 1><<<nbatch, RP_NT, 0, st>>>(W, mstride, n, k0, q, sub, info);
+          }
+        } else {
+          rpanel_leaf_kernel<T, 1><<<nbatch, RP_NT, 0, st>>>(W, mstride, n, k0, q, sub, info);
+        }
+        if (q < 3) {
+          const int tiles = (n - (k0 + RP_W * q) - RP_W + 63) / 64;
+          rpanel_update_kernel<T><<<dim3((unsigned)(nbatch * tiles)), 256, 0, st>>>(W, mstride, n, k0, q, tiles);
+        }
+      }
+      rpanel_finish_kernel<T, NB><<<nbatch, 256, 0, st>>>(W, mstride, n, k0, s, sub, perm, perm_stride, Linv, Uinv,
+                                                          inv_stride);
     } else if (pivot == LU_PIVOT_PARTIAL) {
       // panel rows n - k0 <= threads * rows-per-thread
       if (n <= 1024)
