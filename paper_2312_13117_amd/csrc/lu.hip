@@ -1115,10 +1115,20 @@ __global__ __launch_bounds__(256) void rpanel_finish_kernel(const c2<T>* __restr
 // so the panels L21 / U12 it re-reads stay in that XCD's L2.
 // GEMM_PANEL (tournament panel): rows below the diagonal block, L21 = A21 inv(U11),
 // A21 read from the row's source under the step's row exchange.
-enum { GEMM_UPDATE = 0, GEMM_TRSM = 1, GEMM_PANEL = 2 };
+// Delayed updates: panels are taken in pairs (s, s+1).  After panel s and its U12,
+// GEMM_UPDATE with one column tile makes panel s+1 current; after panel s+1,
+//   GEMM_PREUPD    the top rows of block s+1 under its exchange with step s's update
+//                  applied, C = A[src] - L_s[src] U_s (and the exchange's displaced rows
+//                  moved unchanged),
+//   GEMM_TRSM_ID   U12 of block s+1 = inv(L11) C in place,
+//   GEMM_UPDATE2   the trailing matrix once for both steps, K = 128:
+//                  C -= [L_s[src'] | L_{s+1}] [U_s; U_{s+1}], src' the row a position
+//                  holds after step s+1's exchange.
+// The trailing matrix is then read and written once per two panels.
+enum { GEMM_UPDATE = 0, GEMM_TRSM = 1, GEMM_PANEL = 2, GEMM_PREUPD = 3, GEMM_TRSM_ID = 4, GEMM_UPDATE2 = 5 };
 
 template <typename T, int MODE>
-__global__ __launch_bounds__(256) void lu_gemm_kernel(c2<T>* __restrict__ W, long long mstride, int n, int k0,
+__global__ __launch_bounds__(256, 2) void lu_gemm_kernel(c2<T>* __restrict__ W, long long mstride, int n, int k0,
                                                       int nbk, int step, int nbatch, int tiles_r, int tiles_c,
                                                       const int* __restrict__ perm, long long perm_stride,
                                                       const c2<T>* __restrict__ Linv, long long inv_stride,
@@ -1134,22 +1144,40 @@ __global__ __launch_bounds__(256) void lu_gemm_kernel(c2<T>* __restrict__ W, lon
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   c2<T>* A = W + (long long)b * mstride;
   const int kend = k0 + nbk;
-  const int R0 = (MODE == GEMM_TRSM ? k0 : kend) + tr * 64;
+  const int k0p = k0 - NBMAX;                       // paired modes: the previous block
+  constexpr bool TOP = MODE == GEMM_TRSM || MODE == GEMM_TRSM_ID || MODE == GEMM_PREUPD;
+  constexpr bool SUB = MODE == GEMM_UPDATE || MODE == GEMM_UPDATE2 || MODE == GEMM_PREUPD;   // C - A B
+  const int R0 = (TOP ? k0 : kend) + tr * 64;
   const int C0 = (MODE == GEMM_PANEL ? k0 : kend) + tcn * 64;
-  const int rlim = (MODE == GEMM_TRSM) ? kend : n;
+  const int rlim = TOP ? kend : n;
   const int clim = (MODE == GEMM_PANEL) ? kend : n;
+  const int ktot = MODE == GEMM_PREUPD ? NBMAX : (MODE == GEMM_UPDATE2 ? NBMAX + nbk : nbk);
   const int rb = R0 + (wave >> 1) * 32, cb = C0 + (wave & 1) * 32;
   const int l16 = lane & 15, kq = lane >> 4;
 
   __shared__ int s_src[2 * NBMAX], s_pos[2 * NBMAX];
   __shared__ int s_cnt;
   const c2<T>* Li = nullptr;
-  if (MODE == GEMM_TRSM) {
+  if (MODE == GEMM_TRSM || MODE == GEMM_PREUPD) {
     const int* P = perm + (long long)b * perm_stride + (long long)step * (1 + 4 * NBMAX);
     if (t == 0) s_cnt = P[0];
     for (int i = t; i < 2 * NBMAX; i += 256) { s_pos[i] = P[1 + i]; s_src[i] = P[1 + 2 * NBMAX + i]; }
     __syncthreads();
+  }
+  if (MODE == GEMM_TRSM || MODE == GEMM_TRSM_ID)
     Li = Linv + (long long)b * inv_stride + (long long)step * NBMAX * NBMAX;
+  // GEMM_UPDATE2: s_from[i] = the row whose step-s multipliers position R0 + i uses
+  __shared__ int s_from[64];
+  if (MODE == GEMM_UPDATE2) {
+    const int* P = perm + (long long)b * perm_stride + (long long)step * (1 + 4 * NBMAX);
+    if (t < 64) s_from[t] = R0 + t;
+    __syncthreads();
+    const int cnt = P[0];
+    if (t < cnt - nbk) {
+      const int pos = P[1 + nbk + t];
+      if (pos >= R0 && pos < R0 + 64) s_from[pos - R0] = P[1 + 2 * NBMAX + nbk + t];
+    }
+    __syncthreads();
   }
   // GEMM_PANEL: Linv carries inv(U11); s_slot[i] = saved-row slot of tile row i, or -1
   __shared__ int s_slot[64];
@@ -1178,7 +1206,7 @@ __global__ __launch_bounds__(256) void lu_gemm_kernel(c2<T>* __restrict__ W, lon
   // (re, im): in the other modes a third accumulator would cost occupancy, and in
   // complex64 the larger rounding error of 3M more than doubled the nodes whose
   // refinement fails (delay workload: 230 instead of 96 of 49152).
-  constexpr bool G3 = MODE == GEMM_UPDATE && sizeof(T) == 8;
+  constexpr bool G3 = (MODE == GEMM_UPDATE || MODE == GEMM_UPDATE2) && sizeof(T) == 8;
   acc4<T> c1[2][2], c2a[2][2], c3[2][2];
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
@@ -1187,13 +1215,14 @@ __global__ __launch_bounds__(256) void lu_gemm_kernel(c2<T>* __restrict__ W, lon
       c1[bi][bj] = acc_zero<T>();
       c2a[bi][bj] = acc_zero<T>();
       c3[bi][bj] = acc_zero<T>();
-      if (MODE == GEMM_UPDATE) {
+      if (SUB) {
         const int col = cb + bj * 16 + l16;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = rb + bi * 16 + acc_row<T>(lane, r);
-          if (row < n && col < n) {
-            const c2<T> v = A[(long long)row * n + col];
+          if (row < rlim && col < n) {
+            const int srow = MODE == GEMM_PREUPD ? s_src[row - k0] : row;
+            const c2<T> v = A[(long long)srow * n + col];
             c1[bi][bj][r] = v.x;
             c3[bi][bj][r] = G3 ? v.y + v.x : v.y;
           }
@@ -1205,7 +1234,7 @@ __global__ __launch_bounds__(256) void lu_gemm_kernel(c2<T>* __restrict__ W, lon
   constexpr int DMAX = (NBMAX * 64) / 256;
   c2<T> dval[DMAX];
   int ndisp = 0;
-  if (MODE == GEMM_TRSM) {
+  if (MODE == GEMM_TRSM || MODE == GEMM_PREUPD) {
     ndisp = s_cnt - nbk;
 #pragma unroll
     for (int q = 0; q < DMAX; ++q) {
@@ -1224,6 +1253,11 @@ __global__ __launch_bounds__(256) void lu_gemm_kernel(c2<T>* __restrict__ W, lon
   const int arow = t >> 2, akq = (t & 3) * 4;     // A chunk: row, first of 4 k
   const int bk = t >> 4, bcq = (t & 15) * 4;      // B chunk: k row, first of 4 columns
   c2<T> ra[4], rbv[4];
+  long long a_lo = 0, a_hi = 0;                   // GEMM_UPDATE2: A-operand row bases
+  if (MODE == GEMM_UPDATE2) {
+    a_lo = (long long)s_from[arow] * n + k0p;
+    a_hi = (long long)(R0 + arow) * n + k0 - NBMAX;
+  }
   auto load_chunk = [&](int kc) {
     const int row = R0 + arow;
 #pragma unroll
@@ -1231,8 +1265,12 @@ __global__ __launch_bounds__(256) void lu_gemm_kernel(c2<T>* __restrict__ W, lon
       const int k = kc + akq + u;
       if (MODE == GEMM_UPDATE)
         ra[u] = (row < n && k < nbk) ? A[(long long)row * n + k0 + k] : czero<T>();
-      else if (MODE == GEMM_TRSM)
+      else if (MODE == GEMM_TRSM || MODE == GEMM_TRSM_ID)
         ra[u] = (row < kend && k < nbk) ? Li[(row - k0) * NBMAX + k] : czero<T>();
+      else if (MODE == GEMM_PREUPD)
+        ra[u] = (row < kend && k < NBMAX) ? A[(long long)s_src[row - k0] * n + k0p + k] : czero<T>();
+      else if (MODE == GEMM_UPDATE2)   // a chunk lies wholly in one of the two blocks
+        ra[u] = (row < n && k < ktot) ? A[(kc < NBMAX ? a_lo : a_hi) + k] : czero<T>();
       else if (row < n && k < nbk)
         ra[u] = s_slot[arow] >= 0 ? sv[s_slot[arow] * NBMAX + k] : A[(long long)row * n + k0 + k];
       else
@@ -1244,11 +1282,16 @@ __global__ __launch_bounds__(256) void lu_gemm_kernel(c2<T>* __restrict__ W, lon
       for (int u = 0; u < 4; ++u) rbv[u] = (k < nbk) ? Li[k * NBMAX + bcq + u] : czero<T>();
       return;
     }
-    const int srow = (k < nbk) ? ((MODE == GEMM_UPDATE) ? (k0 + k) : s_src[k]) : 0;
+    int srow = 0;
+    if (k < ktot) {
+      if (MODE == GEMM_TRSM) srow = s_src[k];
+      else if (MODE == GEMM_PREUPD || MODE == GEMM_UPDATE2) srow = k0p + k;
+      else srow = k0 + k;
+    }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int col = C0 + bcq + u;
-      rbv[u] = (k < nbk && col < n) ? A[(long long)srow * n + col] : czero<T>();
+      rbv[u] = (k < ktot && col < n) ? A[(long long)srow * n + col] : czero<T>();
     }
   };
   auto store_chunk = [&](int buf) {
@@ -1258,7 +1301,7 @@ __global__ __launch_bounds__(256) void lu_gemm_kernel(c2<T>* __restrict__ W, lon
       Bs[buf][bk][bcq + u] = rbv[u];
     }
   };
-  const int nch = (nbk + KC - 1) / KC;
+  const int nch = (ktot + KC - 1) / KC;
   load_chunk(0);
   store_chunk(0);
   if (nch > 1) load_chunk(KC);
@@ -1273,7 +1316,7 @@ __global__ __launch_bounds__(256) void lu_gemm_kernel(c2<T>* __restrict__ W, lon
       for (int bi = 0; bi < 2; ++bi) af[bi] = As[buf][wr * 32 + bi * 16 + l16][k];
 #pragma unroll
       for (int bj = 0; bj < 2; ++bj) bf[bj] = Bs[buf][k][wc * 32 + bj * 16 + l16];
-      if (MODE == GEMM_UPDATE) {
+      if (SUB) {
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi) af[bi] = cmk<T>(-af[bi].x, -af[bi].y);   // C - A B
       }
@@ -1321,7 +1364,7 @@ __global__ __launch_bounds__(256) void lu_gemm_kernel(c2<T>* __restrict__ W, lon
     }
     __syncthreads();
   }
-  if (MODE == GEMM_TRSM) __syncthreads();   // every wave has read its operands
+  if (TOP) __syncthreads();   // every wave has read its operands (and C's source rows)
 
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
@@ -1342,7 +1385,7 @@ __global__ __launch_bounds__(256) void lu_gemm_kernel(c2<T>* __restrict__ W, lon
         }
       }
     }
-  if (MODE == GEMM_TRSM) {
+  if (MODE == GEMM_TRSM || MODE == GEMM_PREUPD) {
 #pragma unroll
     for (int q = 0; q < DMAX; ++q) {
       const int e = t + q * 256;
@@ -1696,7 +1739,7 @@ hipError_t lu_factor_batch(c2<T>* W, long long mstride, int n, int nbatch, void*
   int* cand0 = static_cast<int*>(scratch);
   int* cand1 = cand0 + (size_t)nbatch * 64 * 64;
   c2<T>* saved = reinterpret_cast<c2<T>*>(cand1 + (size_t)nbatch * 64 * 64);
-  for (int s = 0; s < nsteps; ++s) {
+  auto panel = [&](int s) {
     const int k0 = s * NB, nbk = min(NB, n - k0), rows = n - k0;
     if (rows <= 128) {
       // the whole panel in registers (either pivot choice: this is partial pivoting)
@@ -1753,7 +1796,53 @@ hipError_t lu_factor_batch(c2<T>* W, long long mstride, int n, int nbatch, void*
       lu_gemm_kernel<T, GEMM_PANEL><<<dim3((unsigned)(groups * 8 * tr)), 256, 0, st>>>(
           W, mstride, n, k0, nbk, s, nbatch, tr, 1, perm, perm_stride, Uinv, inv_stride, saved);
     }
-    launch_trailing<T>(W, mstride, n, nbatch, k0, nbk, s, perm, perm_stride, Linv, inv_stride, st, tm);
+  };
+  const long long groups = (nbatch + 7) / 8;
+  auto timed_update = [&](int mode, int k0, int nbk, int s, int m, int kdepth) {
+    const int tc = (m + 63) / 64;
+    const bool timed = tm && tm->ev_enabled && tm->npairs < LuTimers::MAXP;
+    if (timed) hipEventRecord(tm->ev[2 * tm->npairs], st);
+    const dim3 grid((unsigned)(groups * 8 * tc * tc));
+    if (mode == GEMM_UPDATE2)
+      lu_gemm_kernel<T, GEMM_UPDATE2><<<grid, 256, 0, st>>>(W, mstride, n, k0, nbk, s, nbatch, tc, tc, perm,
+                                                             perm_stride, Linv, inv_stride);
+    else
+      lu_gemm_kernel<T, GEMM_UPDATE><<<grid, 256, 0, st>>>(W, mstride, n, k0, nbk, s, nbatch, tc, tc, perm,
+                                                            perm_stride, Linv, inv_stride);
+    if (timed) {
+      hipEventRecord(tm->ev[2 * tm->npairs + 1], st);
+      tm->npairs++;
+      tm->gemm_launches += 1;   // launches and flops of the timed launches only
+      tm->gemm_flops += 8.0 * (double)m * (double)m * (double)kdepth * (double)nbatch;
+    }
+  };
+  for (int s = 0; s < nsteps;) {
+    const int k0 = s * NB, nbk = min(NB, n - k0), kend = k0 + nbk, m = n - kend;
+    panel(s);
+    if (m <= 0) break;
+    const int tc = (m + 63) / 64;
+    lu_gemm_kernel<T, GEMM_TRSM><<<dim3((unsigned)(groups * 8 * tc)), 256, 0, st>>>(
+        W, mstride, n, k0, nbk, s, nbatch, 1, tc, perm, perm_stride, Linv, inv_stride);
+    if (s + 1 == nsteps - 1 || m <= NB) {
+      // the next panel is the last one: one plain update
+      timed_update(GEMM_UPDATE, k0, nbk, s, m, nbk);
+      ++s;
+      continue;
+    }
+    // delayed pair (s, s+1): make panel s+1 current, factor it, then one pass over the
+    // trailing matrix for both steps
+    const int tr = (m + 63) / 64;
+    lu_gemm_kernel<T, GEMM_UPDATE><<<dim3((unsigned)(groups * 8 * tr)), 256, 0, st>>>(
+        W, mstride, n, k0, nbk, s, nbatch, tr, 1, perm, perm_stride, Linv, inv_stride);
+    panel(s + 1);
+    const int k1 = kend, nb1 = min(NB, n - k1), m1 = n - k1 - nb1;   // m1 > 0 here
+    const int tc1 = (m1 + 63) / 64;
+    lu_gemm_kernel<T, GEMM_PREUPD><<<dim3((unsigned)(groups * 8 * tc1)), 256, 0, st>>>(
+        W, mstride, n, k1, nb1, s + 1, nbatch, 1, tc1, perm, perm_stride, Linv, inv_stride);
+    lu_gemm_kernel<T, GEMM_TRSM_ID><<<dim3((unsigned)(groups * 8 * tc1)), 256, 0, st>>>(
+        W, mstride, n, k1, nb1, s + 1, nbatch, 1, tc1, perm, perm_stride, Linv, inv_stride);
+    timed_update(GEMM_UPDATE2, k1, nb1, s + 1, m1, NB + nb1);
+    s += 2;
   }
   return hipGetLastError();
 }
