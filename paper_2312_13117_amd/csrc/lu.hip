@@ -1696,6 +1696,129 @@ __global__ __launch_bounds__(256) void lu_solve_kernel(const c2<T>* __restrict__
   }
 }
 
+// ----------------------------------------------------------------------------- step-parallel solve
+// The forward and backward substitutions of lu_solve_kernel, spread over many
+// workgroups per matrix: per step one launch of one workgroup per matrix forms the
+// step's block of the solution (forward: exchange the rows, then inv(L11) times the top
+// rows; backward: inv(U11) times the top rows), and one launch over 64-row tiles
+// subtracts the step's block column times that block from the rows below (forward) or
+// above (backward).  Same arithmetic as lu_solve_kernel (products in T, X in
+// complex128), many more loads in flight.
+template <typename T, int NB, bool FWD>
+__global__ __launch_bounds__(256) void solve_top_kernel(const c2<T>* __restrict__ W, long long mstride, int n,
+                                                        int step, const int* __restrict__ perm,
+                                                        long long perm_stride, const c2<T>* __restrict__ Inv,
+                                                        long long inv_stride, double2* __restrict__ X,
+                                                        long long xstride, int m, const int* __restrict__ active) {
+  constexpr int MMAX = SolveTile<T>::MMAX, KC = SolveTile<T>::KC;
+  const int b = blockIdx.x;
+  if (active && !active[b]) return;
+  const int t = threadIdx.x;
+  double2* Xb = X + (long long)b * xstride;
+  const int k0 = step * NB, nbk = min(NB, n - k0);
+  __shared__ c2<T> Ash[NB][KC + 1];
+  __shared__ c2<T> Bsh[NB][MMAX];
+  __shared__ int s_pos[2 * NB], s_src[2 * NB], s_cnt;
+  // rows of the top block (after the exchange) into Bsh; displaced rows into registers
+  constexpr int DV = NB * MMAX / 256;
+  double2 dv[DV];
+  int cnt = nbk;
+  if (FWD) {
+    const int* P = perm + (long long)b * perm_stride + (long long)step * (1 + 4 * NB);
+    if (t == 0) s_cnt = P[0];
+    for (int i = t; i < 2 * NB; i += 256) { s_pos[i] = P[1 + i]; s_src[i] = P[1 + 2 * NB + i]; }
+    __syncthreads();
+    cnt = s_cnt;
+  }
+  for (int e = t; e < NB * MMAX; e += 256) {
+    const int i = e / MMAX, c = e % MMAX;
+    const int r = FWD ? s_src[min(i, nbk - 1)] : k0 + i;
+    Bsh[i][c] = (i < nbk && c < m) ? ccast<T, double>(Xb[(long long)r * m + c]) : czero<T>();
+  }
+  const int nd = cnt - nbk;
+#pragma unroll
+  for (int q = 0; q < DV; ++q) {
+    const int e = t + q * 256, i = e / MMAX, c = e % MMAX;
+    dv[q] = (FWD && i < nd && c < m) ? Xb[(long long)s_src[nbk + i] * m + c] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  if (FWD) {
+#pragma unroll
+    for (int q = 0; q < DV; ++q) {
+      const int e = t + q * 256, i = e / MMAX, c = e % MMAX;
+      if (i < nd && c < m) Xb[(long long)s_pos[nbk + i] * m + c] = dv[q];
+    }
+  }
+  const c2<T>* Ib = Inv + (long long)b * inv_stride + (long long)step * NB * NB;
+  SolveTile<T> tile;
+  tile.zero();
+  for (int kc = 0; kc < nbk; kc += KC) {
+    const int kk = min(KC, nbk - kc);
+    __syncthreads();
+    for (int e = t; e < NB * KC; e += 256) {
+      const int i = e / KC, k = e % KC;
+      Ash[i][k] = (i < nbk && k < kk) ? Ib[(long long)i * NB + kc + k] : czero<T>();
+    }
+    __syncthreads();
+    tile.template mma<false>(Ash, Bsh, kc, kk);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = tile.r0 + i, c = tile.cb + 8 * j;
+      if (r < nbk && c < m) Xb[(long long)(k0 + r) * m + c] = ccast<double, T>(tile.acc[i][j]);
+    }
+}
+
+// X[r, :] -= F[r, k0:k0+nbk] X[k0:k0+nbk, :] for the 64 rows of tile `tile` of the
+// range [r_lo, r_hi) (forward: rows below the block, backward: rows above it)
+template <typename T, int NB>
+__global__ __launch_bounds__(256) void solve_rows_kernel(const c2<T>* __restrict__ W, long long mstride, int n,
+                                                         int step, int r_lo, int r_hi, int tiles,
+                                                         double2* __restrict__ X, long long xstride, int m,
+                                                         const int* __restrict__ active) {
+  constexpr int MMAX = SolveTile<T>::MMAX, KC = SolveTile<T>::KC;
+  const int b = blockIdx.x / tiles, tl = blockIdx.x % tiles;
+  if (active && !active[b]) return;
+  const int t = threadIdx.x;
+  const c2<T>* A = W + (long long)b * mstride;
+  double2* Xb = X + (long long)b * xstride;
+  const int k0 = step * NB, nbk = min(NB, n - k0);
+  const int R0 = r_lo + tl * 64, nr = min(64, r_hi - R0);
+  __shared__ c2<T> Ash[NB][KC + 1];
+  __shared__ c2<T> Bsh[NB][MMAX];
+  for (int e = t; e < NB * MMAX; e += 256) {
+    const int i = e / MMAX, c = e % MMAX;
+    Bsh[i][c] = (i < nbk && c < m) ? ccast<T, double>(Xb[(long long)(k0 + i) * m + c]) : czero<T>();
+  }
+  SolveTile<T> tile;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = tile.r0 + i, c = tile.cb + 8 * j;
+      tile.acc[i][j] = (r < nr && c < m) ? ccast<T, double>(Xb[(long long)(R0 + r) * m + c]) : czero<T>();
+    }
+  for (int kc = 0; kc < nbk; kc += KC) {
+    const int kk = min(KC, nbk - kc);
+    __syncthreads();
+    for (int e = t; e < NB * KC; e += 256) {
+      const int i = e / KC, k = e % KC;
+      Ash[i][k] = (i < nr && k < kk) ? A[(long long)(R0 + i) * n + k0 + kc + k] : czero<T>();
+    }
+    __syncthreads();
+    tile.template mma<true>(Ash, Bsh, kc, kk);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = tile.r0 + i, c = tile.cb + 8 * j;
+      if (r < nr && c < m) Xb[(long long)(R0 + r) * m + c] = ccast<double, T>(tile.acc[i][j]);
+    }
+}
+
 // ----------------------------------------------------------------------------- launchers
 template <typename T>
 static void launch_trailing(c2<T>* W, long long mstride, int n, int nbatch, int k0, int nbk, int s, int* perm,
@@ -1852,10 +1975,34 @@ hipError_t lu_solve_batch(const c2<T>* W, long long mstride, int n, int nbatch, 
                           const c2<T>* Linv, const c2<T>* Uinv, long long inv_stride, double2* X, long long xstride,
                           int m, bool trans, const int* active, hipStream_t st) {
   if (m > 32 || m < 1) return hipErrorInvalidValue;
-  if (trans)
+  if (trans) {
     lu_solve_kernel<T, LU_NB, true><<<nbatch, 256, 0, st>>>(W, mstride, n, perm, perm_stride, Linv, Uinv, inv_stride, X, xstride, m, active);
-  else
+  } else if (n < LU_SOLVE_SPLIT_N || m > LU_SOLVE_SPLIT_M) {
     lu_solve_kernel<T, LU_NB, false><<<nbatch, 256, 0, st>>>(W, mstride, n, perm, perm_stride, Linv, Uinv, inv_stride, X, xstride, m, active);
+  } else {
+    constexpr int NB = LU_NB;
+    const int nsteps = (n + NB - 1) / NB;
+    for (int s = 0; s < nsteps; ++s) {
+      const int k0 = s * NB, kend = min(n, k0 + NB);
+      solve_top_kernel<T, NB, true><<<nbatch, 256, 0, st>>>(W, mstride, n, s, perm, perm_stride, Linv, inv_stride,
+                                                            X, xstride, m, active);
+      if (kend < n) {
+        const int tiles = (n - kend + 63) / 64;
+        solve_rows_kernel<T, NB><<<dim3((unsigned)(nbatch * tiles)), 256, 0, st>>>(W, mstride, n, s, kend, n, tiles,
+                                                                                  X, xstride, m, active);
+      }
+    }
+    for (int s = nsteps - 1; s >= 0; --s) {
+      const int k0 = s * NB;
+      solve_top_kernel<T, NB, false><<<nbatch, 256, 0, st>>>(W, mstride, n, s, perm, perm_stride, Uinv, inv_stride,
+                                                             X, xstride, m, active);
+      if (k0 > 0) {
+        const int tiles = (k0 + 63) / 64;
+        solve_rows_kernel<T, NB><<<dim3((unsigned)(nbatch * tiles)), 256, 0, st>>>(W, mstride, n, s, 0, k0, tiles,
+                                                                                  X, xstride, m, active);
+      }
+    }
+  }
   return hipGetLastError();
 }
 
