@@ -206,8 +206,8 @@ def measured_traffic(workload: str, prec: str):
 def roofline(st, prec, workload=None):
     achieved = st["gemm_flops"] / (st["ms_gemm"] * 1e-3) if st["ms_gemm"] > 0 else 0.0
     traffic = measured_traffic(workload, prec) if workload else None
-    return {"kernel": "lu_gemm_kernel<UPDATE2> (trailing update of the batched LU, two panels per pass, K = 128; "
-                      "a single panel's update when one panel is left)", "bound": "mfma",
+    return {"kernel": "lu_gemm_kernel<UPDATE2> (trailing update of the batched LU, two panels per pass, K = 128)",
+            "bound": "mfma",
             "achieved": achieved / 1e12, "peak": PEAK[prec] / 1e12, "unit": "TFLOP/s",
             "frac": achieved / PEAK[prec], "traffic": traffic, "traffic_unit": "bytes per launch (HBM, counters)",
             "launches": st["gemm_launches"],

@@ -165,7 +165,7 @@ typedef struct nep_stats {
   double ms_solve;           /* triangular solves                                     */
   double ms_refine;          /* residuals + correction solves                         */
   double ms_sums;            /* quadrature sums, profiles, indicators                 */
-  double ms_gemm;            /* the trailing-update kernel alone (timed launches)     */
+  double ms_gemm;            /* the paired trailing update alone (timed launches)      */
   int64_t gemm_launches;     /* its timed launches (the first 2048 of the call)       */
   double gemm_flops;         /* its algorithmic flops over those launches             */
 } nep_stats;

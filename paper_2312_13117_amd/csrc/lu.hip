@@ -1923,7 +1923,8 @@ hipError_t lu_factor_batch(c2<T>* W, long long mstride, int n, int nbatch, void*
   const long long groups = (nbatch + 7) / 8;
   auto timed_update = [&](int mode, int k0, int nbk, int s, int m, int kdepth) {
     const int tc = (m + 63) / 64;
-    const bool timed = tm && tm->ev_enabled && tm->npairs < LuTimers::MAXP;
+    // the timers follow the paired update only (the dominant kernel)
+    const bool timed = mode == GEMM_UPDATE2 && tm && tm->ev_enabled && tm->npairs < LuTimers::MAXP;
     if (timed) hipEventRecord(tm->ev[2 * tm->npairs], st);
     const dim3 grid((unsigned)(groups * 8 * tc * tc));
     if (mode == GEMM_UPDATE2)
