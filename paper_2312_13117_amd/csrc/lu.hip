@@ -841,8 +841,12 @@ __global__ __launch_bounds__(4 * R) void tslu_root_kernel(c2<T>* __restrict__ W,
 // 16 rows of U to its right inside the panel.  A rank-16 update of the rows below
 // follows as a launch of its own (many workgroups per matrix).  A finishing kernel
 // composes the four exchanges into the step's one and forms inv(L11) and inv(U11).
-constexpr int RP_W = 16, RP_NT = 1024, RP_NW = RP_NT / 64;
-constexpr int RP_EX = 1 + 4 * RP_W;   // leaf exchange record: cnt, pos[2W], src[2W]
+// Leaf shapes: complex128 uses 8-column leaves of 512 threads (two rows each), whose
+// registers leave room on the CU for a workgroup of the other stream's update;
+// complex64 uses 16-column leaves of 1024 threads (one or two rows each).
+constexpr int RP_NTMAX = 1024, RP_WMAX = 16;
+constexpr int rp_ex(int w) { return 1 + 4 * w; }   // leaf exchange record: cnt, pos[2W], src[2W]
+constexpr int RP_EXMAX = rp_ex(8) * 8;             // ints per matrix for the records of one step
 
 __device__ inline unsigned long long rp_key(double m, int i) {
   return ((unsigned long long)__double_as_longlong(m) & ~4095ull) | (unsigned long long)(4095 - i);
@@ -851,12 +855,13 @@ __device__ inline unsigned long long rp_key(float m, int i) {
   return ((unsigned long long)__float_as_uint(m) << 16) | (unsigned long long)(4095 - i);
 }
 
-template <typename T, int RPT>
+template <typename T, int RP_W, int RP_NT, int RPT>
 __global__ __launch_bounds__(RP_NT) void rpanel_leaf_kernel(c2<T>* __restrict__ W, long long mstride, int n,
                                                             int k0, int q, int* __restrict__ sub,
                                                             int* __restrict__ info) {
   using K = unsigned long long;
   constexpr K MASK = 4095;
+  constexpr int RP_NW = RP_NT / 64, NL = 64 / RP_W, OC = 64 - RP_W, RP_EX = rp_ex(RP_W);
   const int b = blockIdx.x, t = threadIdx.x, lane = t & 63, wave = t >> 6;
   c2<T>* A = W + (long long)b * mstride;
   const int c0 = k0 + RP_W * q, r0 = c0;           // the leaf's first column and first row
@@ -868,7 +873,7 @@ __global__ __launch_bounds__(RP_NT) void rpanel_leaf_kernel(c2<T>* __restrict__ 
   __shared__ int s_pos[2 * RP_W], s_src[2 * RP_W], s_cnt, s_sing;
   __shared__ int s_dest[RP_W];
   __shared__ unsigned char s_top[RP_W];
-  __shared__ c2<T> xbuf[2 * RP_W][48];             // exchanged rows of the other 48 panel columns
+  __shared__ c2<T> xbuf[2 * RP_W][OC];             // exchanged rows of the other panel columns
   __shared__ c2<T> Lqq[RP_W][RP_W + 1];
 
   c2<T> a[RPT][RP_W];
@@ -963,7 +968,7 @@ __global__ __launch_bounds__(RP_NT) void rpanel_leaf_kernel(c2<T>* __restrict__ 
     }
     s_cnt = cnt;
     if (s_sing && info[b] == 0) info[b] = c0 + 1;
-    int* R = sub + ((long long)b * 4 + q) * RP_EX;
+    int* R = sub + ((long long)b * NL + q) * RP_EX;
     R[0] = cnt;
     for (int i = 0; i < 2 * RP_W; ++i) {
       R[1 + i] = i < cnt ? s_pos[i] : -1;
@@ -990,16 +995,16 @@ __global__ __launch_bounds__(RP_NT) void rpanel_leaf_kernel(c2<T>* __restrict__ 
       for (int u = 0; u < RP_W; ++u) A[(long long)dest * n + c0 + u] = a[p][u];
     }
   }
-  // ---- the exchange on the other 48 panel columns (gathered before any is written)
+  // ---- the exchange on the other panel columns (gathered before any is written)
   auto ocol = [&](int cc) { return cc < RP_W * q ? k0 + cc : k0 + RP_W + cc; };
-  for (int e = t; e < cnt * 48; e += RP_NT) {
-    const int i = e / 48, cc = e % 48;
+  for (int e = t; e < cnt * OC; e += RP_NT) {
+    const int i = e / OC, cc = e % OC;
     xbuf[i][cc] = A[(long long)s_src[i] * n + ocol(cc)];
   }
   __syncthreads();
   const int cright = RP_W * q;                      // xbuf columns >= cright lie right of the leaf
-  for (int e = t; e < cnt * 48; e += RP_NT) {
-    const int i = e / 48, cc = e % 48;
+  for (int e = t; e < cnt * OC; e += RP_NT) {
+    const int i = e / OC, cc = e % OC;
     if (i < RP_W && cc >= cright) continue;         // the top rows' right part: U, written below
     A[(long long)s_pos[i] * n + ocol(cc)] = xbuf[i][cc];
   }
@@ -1018,14 +1023,14 @@ __global__ __launch_bounds__(RP_NT) void rpanel_leaf_kernel(c2<T>* __restrict__ 
 
 // rank-16 update of the panel columns right of leaf q, rows below the leaf's top rows:
 // A[r, cr:k0+64] -= L[r, c0:c0+16] U[r0:r0+16, cr:k0+64]; 64 rows per workgroup
-template <typename T>
+template <typename T, int RP_W>
 __global__ __launch_bounds__(256) void rpanel_update_kernel(c2<T>* __restrict__ W, long long mstride, int n, int k0,
                                                             int q, int tiles) {
   const int b = blockIdx.x / tiles, tile = blockIdx.x % tiles, t = threadIdx.x;
   c2<T>* A = W + (long long)b * mstride;
   const int c0 = k0 + RP_W * q, r0 = c0, cr = c0 + RP_W, wr = k0 + 64 - cr;
   const int R0 = r0 + RP_W + tile * 64;
-  __shared__ c2<T> U[RP_W][48];
+  __shared__ c2<T> U[RP_W][64 - RP_W];
   __shared__ c2<T> Lt[64][RP_W + 1];
   for (int e = t; e < RP_W * wr; e += 256) U[e / wr][e % wr] = A[(long long)(r0 + e / wr) * n + cr + e % wr];
   for (int e = t; e < 64 * RP_W; e += 256) {
@@ -1045,12 +1050,13 @@ __global__ __launch_bounds__(256) void rpanel_update_kernel(c2<T>* __restrict__ 
 
 // the step's exchange (the four leaf exchanges composed, top rows first) and the
 // inverses of the factored 64 x 64 diagonal block
-template <typename T, int NB>
+template <typename T, int NB, int RP_W>
 __global__ __launch_bounds__(256) void rpanel_finish_kernel(const c2<T>* __restrict__ W, long long mstride, int n,
                                                             int k0, int step, const int* __restrict__ sub,
                                                             int* __restrict__ perm, long long perm_stride,
                                                             c2<T>* __restrict__ Linv, c2<T>* __restrict__ Uinv,
                                                             long long inv_stride) {
+  constexpr int NL = NB / RP_W, RP_EX = rp_ex(RP_W);
   const int b = blockIdx.x, t = threadIdx.x;
   const c2<T>* A = W + (long long)b * mstride;
   __shared__ c2<T> Mtri[NB][NB + 1];
@@ -1061,8 +1067,8 @@ __global__ __launch_bounds__(256) void rpanel_finish_kernel(const c2<T>* __restr
   __shared__ unsigned char emitted[4096];
   for (int i = t; i < n - k0; i += 256) { srcmap[i] = k0 + i; emitted[i] = 0; }
   __syncthreads();
-  for (int q = 0; q < 4; ++q) {
-    const int* R = sub + ((long long)b * 4 + q) * RP_EX;
+  for (int q = 0; q < NL; ++q) {
+    const int* R = sub + ((long long)b * NL + q) * RP_EX;
     const int cnt = R[0];
     if (t < cnt) nv[t] = srcmap[R[1 + 2 * RP_W + t] - k0];   // sources before this leaf
     __syncthreads();
@@ -1074,8 +1080,8 @@ __global__ __launch_bounds__(256) void rpanel_finish_kernel(const c2<T>* __restr
     int* P = perm + (long long)b * perm_stride + (long long)step * (1 + 4 * NB);
     int cnt = 0;
     for (int k = 0; k < NB; ++k) { P[1 + cnt] = k0 + k; P[1 + 2 * NB + cnt] = srcmap[k]; ++cnt; }
-    for (int q = 0; q < 4; ++q) {
-      const int* R = sub + ((long long)b * 4 + q) * RP_EX;
+    for (int q = 0; q < NL; ++q) {
+      const int* R = sub + ((long long)b * NL + q) * RP_EX;
       for (int i = 0; i < R[0]; ++i) {
         const int pos = R[1 + i];
         if (pos >= k0 + NB && !emitted[pos - k0] && srcmap[pos - k0] != pos && cnt < 2 * NB) {
@@ -1843,7 +1849,7 @@ static void launch_trailing(c2<T>* W, long long mstride, int n, int nbatch, int 
 }
 
 size_t lu_factor_scratch_bytes(int n, size_t elem_bytes) {
-  const size_t partial = sizeof(int) * ((size_t)n + 4 * RP_EX);
+  const size_t partial = sizeof(int) * ((size_t)n + RP_EXMAX);
   const size_t tournament = 2 * sizeof(int) * 64 * 64 + elem_bytes * (size_t)LU_NB * LU_NB;
   return partial > tournament ? partial : tournament;
 }
@@ -1871,26 +1877,26 @@ hipError_t lu_factor_batch(c2<T>* W, long long mstride, int n, int nbatch, void*
     } else if (rows <= 256) {
       tslu_root_kernel<T, NB, 256, true><<<nbatch, 1024, 0, st>>>(W, mstride, n, k0, nbk, s, 0, nullptr, perm,
                                                                    perm_stride, nullptr, Linv, Uinv, inv_stride, info);
-    } else if (pivot == LU_PIVOT_PARTIAL && (rows <= RP_NT || (sizeof(T) == 4 && rows <= 2 * RP_NT))) {
-      // recursive panel: four register leaves with rank-16 updates between them
+    } else if (pivot == LU_PIVOT_PARTIAL && rows <= (sizeof(T) == 4 ? 2 : 1) * RP_NTMAX) {
+      // recursive panel: register leaves with rank-W updates between them
       int* sub = ipiv + (size_t)nbatch * n;
-      for (int q = 0; q < 4; ++q) {
-        if constexpr (sizeof(T) == 4) {
-          if (rows > RP_NT) {
-            rpanel_leaf_kernel<T, 2><<<nbatch, RP_NT, 0, st>>>(W, mstride, n, k0, q, sub, info);
-          } else {
-            rpanel_leaf_kernel<T, 1><<<nbatch, RP_NT, 0, st>>>(W, mstride, n, k0, q, sub, info);
-          }
+      constexpr int LW = sizeof(T) == 8 ? 8 : 16;          // leaf width
+      for (int q = 0; q < NB / LW; ++q) {
+        if constexpr (sizeof(T) == 8) {
+          rpanel_leaf_kernel<T, 8, 512, 2><<<nbatch, 512, 0, st>>>(W, mstride, n, k0, q, sub, info);
         } else {
-          rpanel_leaf_kernel<T, 1><<<nbatch, RP_NT, 0, st>>>(W, mstride, n, k0, q, sub, info);
+          if (rows > RP_NTMAX)
+            rpanel_leaf_kernel<T, 16, 1024, 2><<<nbatch, 1024, 0, st>>>(W, mstride, n, k0, q, sub, info);
+          else
+            rpanel_leaf_kernel<T, 16, 1024, 1><<<nbatch, 1024, 0, st>>>(W, mstride, n, k0, q, sub, info);
         }
-        if (q < 3) {
-          const int tiles = (n - (k0 + RP_W * q) - RP_W + 63) / 64;
-          rpanel_update_kernel<T><<<dim3((unsigned)(nbatch * tiles)), 256, 0, st>>>(W, mstride, n, k0, q, tiles);
+        if (q < NB / LW - 1) {
+          const int tiles = (n - (k0 + LW * q) - LW + 63) / 64;
+          rpanel_update_kernel<T, LW><<<dim3((unsigned)(nbatch * tiles)), 256, 0, st>>>(W, mstride, n, k0, q, tiles);
         }
       }
-      rpanel_finish_kernel<T, NB><<<nbatch, 256, 0, st>>>(W, mstride, n, k0, s, sub, perm, perm_stride, Linv, Uinv,
-                                                          inv_stride);
+      rpanel_finish_kernel<T, NB, LW><<<nbatch, 256, 0, st>>>(W, mstride, n, k0, s, sub, perm, perm_stride, Linv, Uinv,
+                                                              inv_stride);
     } else if (pivot == LU_PIVOT_PARTIAL) {
       // panel rows n - k0 <= threads * rows-per-thread
       if (n <= 1024)

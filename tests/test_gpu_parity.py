@@ -68,12 +68,16 @@ def check_sums(N, plan, prob, reg, opts, F, V, tol, disks=None):
 
 
 # pivot 0 = partial pivoting, 1 = tournament (panels of > 128 rows go through the
-# chunk/merge tree: n = 300 and 700 take one and two merge levels)
+# chunk/merge tree: n = 300 and 700 take one and two merge levels).  Panel kernels by
+# rows: <= 256 in registers; <= 1024 (complex128) / 2048 (complex64, two rows per
+# thread above 1024) recursive leaves; more: the streaming panel (n = 1100,
+# complex128).  Orders >= 256 with <= 8 columns take the step-parallel solve.
 @pytest.mark.parametrize("n,Nn,s,L,prec,pivot", [(4, 8, 1, 2, 0, 0), (37, 8, 1, 4, 0, 0), (100, 16, 2, 6, 0, 0),
                                                  (200, 16, 1, 8, 0, 0), (200, 16, 1, 8, 1, 0),
                                                  (130, 12, 3, 5, 1, 0), (300, 8, 1, 4, 0, 0), (700, 8, 1, 4, 1, 0),
                                                  (4, 8, 1, 2, 0, 1), (200, 16, 1, 8, 0, 1), (130, 12, 3, 5, 1, 1),
-                                                 (300, 8, 1, 4, 0, 1), (700, 8, 1, 4, 1, 1)])
+                                                 (300, 8, 1, 4, 0, 1), (700, 8, 1, 4, 1, 1),
+                                                 (1100, 4, 1, 2, 0, 0), (1100, 4, 1, 2, 1, 0)])
 def test_sums_ragged_sizes(N, n, Nn, s, L, prec, pivot):
     say(f"case sums n={n} N={Nn} s={s} L={L} precision={prec} pivot={pivot}")
     A = gen.gaussian(100 + n, n)
