@@ -17,6 +17,8 @@
  *   Step 3   verification of each candidate by sigma_min(T(lambda)) < tol_ver
  *            (Step 3, with the smallest singular value in place of the smallest
  *            eigenvalue)                                        -> nep_verify
+ *   (added)  candidates moved to the eigenvalue they approximate by the two-sided
+ *            Rayleigh functional, then verified                 -> nep_refine
  *
  * Conventions for every entry point
  *   - Complex numbers are interleaved (re, im) pairs of IEEE doubles, the layout of
@@ -235,6 +237,27 @@ nep_status nep_beyn(nep_plan_t* plan, const int32_t* disk_ids, int ndisks,
  *   accepted   host uint8 [m]
  * Errors: NEP_ERR_ARG.                                                            */
 nep_status nep_verify(nep_plan_t* plan, const int32_t* prob_ids, const void* lam, int m,
+                      double* sigma_min, uint8_t* accepted);
+
+/* nep_refine -- candidates moved onto the eigenvalues they approximate, then verified
+ * as by nep_verify.  Not a step of the paper's method: Beyn's candidates carry the
+ * quadrature error of their disk (largest for eigenvalues near the circle), and a cell
+ * split by the saturation remedy (end of Section 3.2) can leave one there.  Each of
+ * `iters` updates runs the inverse iteration of nep_verify at lambda, takes its left
+ * and right singular-vector estimates u, v, forms a_k = u^H A_k v on the device and
+ * moves lambda to the nearby root of the two-sided Rayleigh functional
+ * u^H T(rho) v = sum_k phi_k(rho) a_k (Newton on the host); a final inverse iteration
+ * gives sigma_min.  Each candidate returns the point of smallest sigma_min met, so
+ * the result is never worse than the input; iters = 0 is nep_verify.
+ *   prob_ids   host int32 [m]: problem of each candidate
+ *   lam        host complex128 [m], in: candidates, out: refined values
+ *   iters      0 .. NEP_REFINE_MAX_ITERS (2 takes a candidate within 1e-4 relative of
+ *              a simple eigenvalue to rounding level)
+ *   sigma_min  host double [m]: at the returned value
+ *   accepted   host uint8 [m]: sigma_min < tol_ver
+ * Cost: (iters + 1) complex128 LUs per candidate.  Errors: NEP_ERR_ARG.           */
+#define NEP_REFINE_MAX_ITERS 8
+nep_status nep_refine(nep_plan_t* plan, const int32_t* prob_ids, void* lam, int m, int iters,
                       double* sigma_min, uint8_t* accepted);
 
 /* nep_copy_sums -- copy the quadrature sums of disks [first, first + count) of the last

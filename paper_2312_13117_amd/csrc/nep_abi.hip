@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -903,17 +904,55 @@ extern "C" nep_status nep_beyn(nep_plan_t* P, const int32_t* disk_ids, int ndisk
   return sat ? NEP_WARN_SATURATED : NEP_OK;
 }
 
-// ---------------------------------------------------------------------------- verify
-extern "C" nep_status nep_verify(nep_plan_t* P, const int32_t* prob_ids, const void* lam, int m, double* sigma_min,
-                                 uint8_t* accepted) {
-  if (!P) return NEP_ERR_ARG;
-  if (m < 0 || (m > 0 && (!prob_ids || !lam || !sigma_min || !accepted))) return fail(P, NEP_ERR_ARG, "null argument");
-  for (int i = 0; i < m; ++i)
-    if (prob_ids[i] < 0 || prob_ids[i] >= P->nprob) return fail(P, NEP_ERR_ARG, "problem id out of range");
-  if (m == 0) return NEP_OK;
+// ---------------------------------------------------------------------------- verify / refine
+// phi_k(z) and its derivative on the host (the scalar Newton of the refinement)
+static std::complex<double> phi_host(int kind, double par, std::complex<double> z, std::complex<double>* d) {
+  switch (kind) {
+    case PHI_ONE: *d = 0.0; return 1.0;
+    case PHI_Z: *d = 1.0; return z;
+    case PHI_Z2: *d = 2.0 * z; return z * z;
+    case PHI_NEG_Z: *d = -1.0; return -z;
+    case PHI_EXP_NEG_TAU_Z: {
+      const std::complex<double> e = std::exp(-par * z);
+      *d = -par * e;
+      return e;
+    }
+  }
+  *d = 0.0;
+  return 0.0;
+}
+
+// Root of f(rho) = sum_k phi_k(rho) a_k by Newton from z (at most 30 steps, stopping when
+// a step is below 4 eps |rho|); returns z itself when the iteration leaves the finite range.
+static std::complex<double> rayleigh_root(const ProblemDev& pd, const double2* a, std::complex<double> z) {
+  std::complex<double> rho = z;
+  for (int t = 0; t < 30; ++t) {
+    std::complex<double> f = 0.0, fp = 0.0;
+    for (int k = 0; k < pd.nterms; ++k) {
+      std::complex<double> d;
+      const std::complex<double> ak(a[k].x, a[k].y);
+      f += phi_host(pd.kind[k], pd.param[k], rho, &d) * ak;
+      fp += d * ak;
+    }
+    if (std::abs(fp) == 0.0) break;
+    const std::complex<double> step = f / fp;
+    rho -= step;
+    if (!std::isfinite(rho.real()) || !std::isfinite(rho.imag())) return z;
+    if (std::abs(step) <= 4.0 * 2.220446049250313e-16 * std::abs(rho)) break;
+  }
+  return rho;
+}
+
+// sigma_min(T(lambda)) by inverse iteration on the complex128 LU, after `iters` two-sided
+// Rayleigh-functional updates of lambda (iters = 0: verification only).  Each update
+// takes the left and right singular-vector estimates u, v of the last inverse iteration,
+// forms a_k = u^H A_k v on the device and moves lambda to the nearby root of
+// u^H T(rho) v = sum_k phi_k(rho) a_k; every candidate keeps the point of smallest
+// sigma_min seen, so an update never returns a worse value than its input.
+static nep_status verify_refine(nep_plan_t* P, const int32_t* prob_ids, const double2* lam_in, double2* lam_out,
+                                int m, int iters, double* sigma_min, uint8_t* accepted) {
   reset_stats(P);
   tmark(P, PH_TOTAL, true, P->st);
-  const double2* lh = static_cast<const double2*>(lam);
   constexpr int ITERS = 4;
   for (int prob = 0; prob < P->nprob; ++prob) {
     std::vector<int> idx;
@@ -925,37 +964,60 @@ extern "C" nep_status nep_verify(nep_plan_t* P, const int32_t* prob_ids, const v
     const int B = std::min<int>((int)idx.size(), choose_batch(n, NEP_FP64, (int)idx.size(), 0));
     nep_status e = ensure_fp64_ws(P, n, B);
     if (e != NEP_OK) return e;
-    HIPCHK(P, P->vest.alloc(sizeof(double) * (B + 2) + sizeof(double2) * (size_t)B * n + sizeof(double2) * B));
+    const size_t vecs = iters > 0 ? 2 : 1;
+    HIPCHK(P, P->vest.alloc(sizeof(double) * (B + 2) + sizeof(double2) * vecs * (size_t)B * n +
+                            sizeof(double2) * (size_t)B * (1 + MAX_TERMS)));
     double* est = P->vest.as<double>();
     double2* xv = reinterpret_cast<double2*>(est + B + (B & 1));
-    double2* zn = xv + (size_t)B * n;
+    double2* uv = xv + (size_t)B * n;                       // left vectors (iters > 0)
+    double2* zn = xv + vecs * (size_t)B * n;
+    double2* terms = zn + B;
     for (size_t c0 = 0; c0 < idx.size(); c0 += B) {
       const int nb = (int)std::min<size_t>(B, idx.size() - c0);
-      std::vector<double2> z(nb);
-      for (int b = 0; b < nb; ++b) z[b] = lh[idx[c0 + b]];
-      HIPCHK(P, hipMemcpyAsync(zn, z.data(), sizeof(double2) * nb, hipMemcpyHostToDevice, P->st));
-      e = factor_chunk<double>(P, P->w64, pd, zn, nb);
-      if (e != NEP_OK) return e;
-      HIPCHK(P, launch_start(xv, n, n, est, nb, P->st));
-      HIPCHK(P, launch_normalize(xv, n, n, est, 0, nb, P->st));
-      for (int it = 0; it < ITERS; ++it) {
-        e = solve_chunk<double>(P, P->w64, n, nb, xv, 1, true, nullptr);
-        if (e != NEP_OK) return e;
-        HIPCHK(P, launch_normalize(xv, n, n, est, 1, nb, P->st));
-        e = solve_chunk<double>(P, P->w64, n, nb, xv, 1, false, nullptr);
-        if (e != NEP_OK) return e;
-        HIPCHK(P, launch_normalize(xv, n, n, est, 1, nb, P->st));
-      }
-      std::vector<double> hest(nb);
+      std::vector<double2> z(nb), zbest(nb), ha((size_t)nb * MAX_TERMS);
+      std::vector<double> sbest(nb, INFINITY), hest(nb);
       std::vector<int> hinf(nb);
-      HIPCHK(P, hipMemcpyAsync(hest.data(), est, sizeof(double) * nb, hipMemcpyDeviceToHost, P->st));
-      HIPCHK(P, hipMemcpyAsync(hinf.data(), P->w64.info.p, sizeof(int) * nb, hipMemcpyDeviceToHost, P->st));
-      HIPCHK(P, hipStreamSynchronize(P->st));
+      for (int b = 0; b < nb; ++b) z[b] = zbest[b] = lam_in[idx[c0 + b]];
+      for (int it = 0; it <= iters; ++it) {
+        const bool upd = it < iters;
+        HIPCHK(P, hipMemcpyAsync(zn, z.data(), sizeof(double2) * nb, hipMemcpyHostToDevice, P->st));
+        e = factor_chunk<double>(P, P->w64, pd, zn, nb);
+        if (e != NEP_OK) return e;
+        HIPCHK(P, launch_start(xv, n, n, est, nb, P->st));
+        HIPCHK(P, launch_normalize(xv, n, n, est, 0, nb, P->st));
+        for (int k = 0; k < ITERS; ++k) {
+          e = solve_chunk<double>(P, P->w64, n, nb, xv, 1, true, nullptr);
+          if (e != NEP_OK) return e;
+          HIPCHK(P, launch_normalize(xv, n, n, est, 1, nb, P->st));
+          if (upd && k == ITERS - 1)
+            HIPCHK(P, hipMemcpyAsync(uv, xv, sizeof(double2) * (size_t)nb * n, hipMemcpyDeviceToDevice, P->st));
+          e = solve_chunk<double>(P, P->w64, n, nb, xv, 1, false, nullptr);
+          if (e != NEP_OK) return e;
+          HIPCHK(P, launch_normalize(xv, n, n, est, 1, nb, P->st));
+        }
+        if (upd) {
+          HIPCHK(P, launch_rayleigh_terms(pd, uv, xv, n, nb, terms, P->st));
+          HIPCHK(P, hipMemcpyAsync(ha.data(), terms, sizeof(double2) * (size_t)nb * MAX_TERMS, hipMemcpyDeviceToHost,
+                                   P->st));
+        }
+        HIPCHK(P, hipMemcpyAsync(hest.data(), est, sizeof(double) * nb, hipMemcpyDeviceToHost, P->st));
+        HIPCHK(P, hipMemcpyAsync(hinf.data(), P->w64.info.p, sizeof(int) * nb, hipMemcpyDeviceToHost, P->st));
+        HIPCHK(P, hipStreamSynchronize(P->st));
+        for (int b = 0; b < nb; ++b) {
+          const double sgm = hinf[b] ? 0.0 : hest[b];
+          if (sgm < sbest[b]) { sbest[b] = sgm; zbest[b] = z[b]; }
+          // an exactly singular T(z) (zero pivot) leaves nothing to improve
+          if (upd && !hinf[b]) {
+            const std::complex<double> r = rayleigh_root(pd, &ha[(size_t)b * MAX_TERMS], {z[b].x, z[b].y});
+            z[b] = make_double2(r.real(), r.imag());
+          }
+        }
+      }
       for (int b = 0; b < nb; ++b) {
         const int i = idx[c0 + b];
-        const double sgm = hinf[b] ? 0.0 : hest[b];
-        sigma_min[i] = sgm;
-        accepted[i] = (sgm < P->opt.tol_ver) ? 1 : 0;
+        sigma_min[i] = sbest[b];
+        accepted[i] = (sbest[b] < P->opt.tol_ver) ? 1 : 0;
+        if (lam_out) lam_out[i] = zbest[b];
       }
     }
   }
@@ -963,6 +1025,32 @@ extern "C" nep_status nep_verify(nep_plan_t* P, const int32_t* prob_ids, const v
   HIPCHK(P, hipStreamSynchronize(P->st));
   finish_stats(P);
   return NEP_OK;
+}
+
+static nep_status check_candidates(nep_plan_t* P, const int32_t* prob_ids, const void* lam, int m, double* sigma_min,
+                                   uint8_t* accepted) {
+  if (m < 0 || (m > 0 && (!prob_ids || !lam || !sigma_min || !accepted))) return fail(P, NEP_ERR_ARG, "null argument");
+  for (int i = 0; i < m; ++i)
+    if (prob_ids[i] < 0 || prob_ids[i] >= P->nprob) return fail(P, NEP_ERR_ARG, "problem id out of range");
+  return NEP_OK;
+}
+
+extern "C" nep_status nep_verify(nep_plan_t* P, const int32_t* prob_ids, const void* lam, int m, double* sigma_min,
+                                 uint8_t* accepted) {
+  if (!P) return NEP_ERR_ARG;
+  nep_status e = check_candidates(P, prob_ids, lam, m, sigma_min, accepted);
+  if (e != NEP_OK || m == 0) return e;
+  return verify_refine(P, prob_ids, static_cast<const double2*>(lam), nullptr, m, 0, sigma_min, accepted);
+}
+
+extern "C" nep_status nep_refine(nep_plan_t* P, const int32_t* prob_ids, void* lam, int m, int iters,
+                                 double* sigma_min, uint8_t* accepted) {
+  if (!P) return NEP_ERR_ARG;
+  nep_status e = check_candidates(P, prob_ids, lam, m, sigma_min, accepted);
+  if (e != NEP_OK || m == 0) return e;
+  if (iters < 0 || iters > NEP_REFINE_MAX_ITERS) return fail(P, NEP_ERR_ARG, "iters out of range");
+  double2* l = static_cast<double2*>(lam);
+  return verify_refine(P, prob_ids, l, l, m, iters, sigma_min, accepted);
 }
 
 // ---------------------------------------------------------------------------- accessors

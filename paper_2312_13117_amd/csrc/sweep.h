@@ -47,5 +47,7 @@ hipError_t launch_axpy(double2* X, const double2* D, long long xstride, int len,
 hipError_t launch_fill_int(int* a, int v, int n, hipStream_t st);
 hipError_t launch_mark_singular(const int* info, int nb, int* sing, hipStream_t st);
 hipError_t launch_or_flags(const int* a, const int* c, int nb, int* out, hipStream_t st);
+hipError_t launch_rayleigh_terms(const ProblemDev& pd, const double2* U, const double2* V, long long xstride,
+                                 int nb, double2* out, hipStream_t st);
 
 }  // namespace nep

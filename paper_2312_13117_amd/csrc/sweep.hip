@@ -415,6 +415,44 @@ hipError_t launch_or_flags(const int* a, const int* c, int nb, int* out, hipStre
   return hipGetLastError();
 }
 
+// a[b * MAX_TERMS + k] = u_b^H A_k v_b (u_b^H v_b for an identity coefficient): the
+// scalars of the two-sided Rayleigh functional u^H T(rho) v = sum_k phi_k(rho) a_k.
+// grid (nb, nterms); one wave per row of A_k, its lanes across the row (coalesced).
+__global__ __launch_bounds__(256) void rayleigh_terms_kernel(ProblemDev pd, const double2* __restrict__ U,
+                                                             const double2* __restrict__ Vv, long long xstride,
+                                                             double2* __restrict__ out) {
+  const int b = blockIdx.x, k = blockIdx.y, n = pd.n;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const double2* u = U + (long long)b * xstride;
+  const double2* v = Vv + (long long)b * xstride;
+  const double2* A = pd.A[k];
+  double2 acc = cmk<double>(0, 0);
+  if (A) {
+    for (int i = w; i < n; i += 4) {
+      double2 r = cmk<double>(0, 0);
+      for (int j = lane; j < n; j += 64) r = cfma<double>(r, A[(long long)i * n + j], v[j]);
+      acc = cfma<double>(acc, cmk<double>(u[i].x, -u[i].y), r);
+    }
+  } else {
+    for (int i = threadIdx.x; i < n; i += 256) acc = cfma<double>(acc, cmk<double>(u[i].x, -u[i].y), v[i]);
+  }
+  acc.x = wave_sum(acc.x);
+  acc.y = wave_sum(acc.y);
+  __shared__ double2 part[4];
+  if (lane == 0) part[w] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    out[(long long)b * MAX_TERMS + k] =
+        cmk<double>(part[0].x + part[1].x + part[2].x + part[3].x, part[0].y + part[1].y + part[2].y + part[3].y);
+}
+
+hipError_t launch_rayleigh_terms(const ProblemDev& pd, const double2* U, const double2* V, long long xstride,
+                                 int nb, double2* out, hipStream_t st) {
+  if (pd.nterms < 1 || pd.nterms > MAX_TERMS || nb < 1) return hipErrorInvalidValue;
+  rayleigh_terms_kernel<<<dim3(nb, pd.nterms), 256, 0, st>>>(pd, U, V, xstride, out);
+  return hipGetLastError();
+}
+
 // a[i] = v for i < n (a fill kernel instead of a memset node, so graph captures replay it)
 __global__ void fill_int_kernel(int* a, int v, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;

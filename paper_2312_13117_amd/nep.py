@@ -62,6 +62,7 @@ def lib():
     L.nep_indicator.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), dp, u8p, dp]
     L.nep_beyn.argtypes = [vp, ip, C.c_int, C.POINTER(vp), vp, ip, dp, u8p, vp]
     L.nep_verify.argtypes = [vp, ip, vp, C.c_int, dp, u8p]
+    L.nep_refine.argtypes = [vp, ip, vp, C.c_int, C.c_int, dp, u8p]
     L.nep_copy_sums.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp, vp]
     L.nep_dedup.argtypes = [vp, dp, C.c_int, C.c_double, u8p]
     L.nep_total_disks.argtypes = [vp]
@@ -81,7 +82,7 @@ def lib():
     L.nep_mlp_grad.argtypes = [fp, fp, fp, fp, C.c_int, fp, C.POINTER(C.c_float), fp, vp]
     L.nep_mlp_adam.argtypes = [fp, fp, fp, fp, C.c_int, C.c_float, C.c_float, C.c_float, C.c_float, vp]
     L.nep_mlp_features.argtypes = [fp, C.c_int, C.c_int, fp, C.c_int, fp, fp, fp, vp]
-    for f in ("nep_plan", "nep_indicator", "nep_beyn", "nep_verify", "nep_copy_sums", "nep_dedup",
+    for f in ("nep_plan", "nep_indicator", "nep_beyn", "nep_verify", "nep_refine", "nep_copy_sums", "nep_dedup",
               "nep_total_disks", "nep_disk_offset", "nep_get_stats", "nep_mlp_param_count", "nep_mlp_forward",
               "nep_mlp_grad", "nep_mlp_adam", "nep_mlp_features"):
         getattr(L, f).restype = C.c_int
@@ -237,6 +238,20 @@ def nep_verify(plan: Plan, prob_ids: Sequence[int], lam: Sequence[complex]):
                       sig.ctypes.data_as(C.POINTER(C.c_double)), acc.ctypes.data_as(C.POINTER(C.c_uint8)))
     _check(st, plan.handle)
     return sig, acc.astype(bool)
+
+
+def nep_refine(plan: Plan, prob_ids: Sequence[int], lam: Sequence[complex], iters: int = 2):
+    """(refined lambda, sigma_min at it, accepted) -- see nep_refine in nep.h."""
+    L = lib()
+    m = len(lam)
+    pid = np.ascontiguousarray(np.asarray(prob_ids, dtype=np.int32))
+    la = np.array(lam, dtype=np.complex128, copy=True, order="C")
+    sig = np.zeros(m)
+    acc = np.zeros(m, np.uint8)
+    st = L.nep_refine(plan.handle, pid.ctypes.data_as(C.POINTER(C.c_int32)), _ptr(la), m, int(iters),
+                      sig.ctypes.data_as(C.POINTER(C.c_double)), acc.ctypes.data_as(C.POINTER(C.c_uint8)))
+    _check(st, plan.handle)
+    return la, sig, acc.astype(bool)
 
 
 def _copy_sums_uniform(plan: Plan, first: int, count: int, n: int):

@@ -1,0 +1,96 @@
+"""The saturation remedy (cells whose disk saturates are split 2 x 2 until no flagged
+disk saturates, end of Section 3.2) against the exact spectrum: on the n = 64
+workload, whose flagged disks all hold more eigenvalues than the 8 Beyn columns, the
+adaptive driver must return every eigenvalue of the companion linearisation inside
+Omega and nothing else."""
+import sys
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def A():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2312_13117_amd import adaptive, nep
+    nep.lib()
+    return adaptive
+
+
+def test_adaptive_small_workload_complete(A):
+    w = gen.workload_small_qep()
+    say("case adaptive small workload n=64, 4x4 disks, L=8")
+    res = A.pmcimb_adaptive(w.problems[0], w.regions[0], w.opts, w.F[0], w.V[0])
+    say("  levels", res.levels, "swept", res.disks_swept, "saturated", res.saturated, "found", len(res.eigs))
+    ref = oracle.brute.companion_eigs(w.problems[0])
+    r = w.regions[0]
+    inside = ref[(ref.real > r.x0) & (ref.real < r.x1) & (ref.imag > r.y0) & (ref.imag < r.y1)]
+    assert res.unresolved == 0
+    assert len(res.eigs) == len(inside), (len(res.eigs), len(inside))
+    err = max(np.min(np.abs(res.eigs - v)) / max(1.0, abs(v)) for v in inside)
+    say("  max relative error vs companion", err)
+    assert err <= 1e-8
+    assert np.all(res.sigma < w.opts.tol_ver)
+
+
+def _perturb(lam, seed, rel):
+    rng = np.random.default_rng(seed)
+    d = rng.standard_normal(len(lam)) + 1j * rng.standard_normal(len(lam))
+    return lam + rel * np.maximum(1.0, np.abs(lam)) * d
+
+
+def _refine_case(prob, region, opts, exact, seed):
+    from paper_2312_13117_amd import nep as N
+    start = _perturb(exact, seed, 1e-5)
+    plan = N.nep_plan([prob], [region], opts)
+    try:
+        lam, sig, acc = N.nep_refine(plan, [0] * len(start), start, 2)
+        sig_v, acc_v = N.nep_verify(plan, [0] * len(start), start)
+        lam0, sig0, acc0 = N.nep_refine(plan, [0] * len(start), start, 0)
+    finally:
+        N.nep_destroy(plan)
+    err = np.abs(lam - exact) / np.maximum(1.0, np.abs(exact))
+    say("  start error", np.max(np.abs(start - exact) / np.maximum(1.0, np.abs(exact))), "refined", err.max())
+    # iters = 0 is the verification itself, bit for bit, and leaves lambda alone
+    assert np.array_equal(lam0, start) and np.array_equal(sig0, sig_v) and np.array_equal(acc0, acc_v)
+    assert acc.all() and np.all(sig <= sig_v)
+    return err
+
+
+def test_refine_qep_companion(A):
+    """Candidates 1e-5 (relative) off the companion eigenvalues of the n = 64 QEP return
+    to them within 1e-11 after two Rayleigh-functional updates."""
+    w = gen.workload_small_qep()
+    ref = oracle.brute.companion_eigs(w.problems[0])
+    inside = ref[(np.abs(ref.real) < 2) & (np.abs(ref.imag) < 2)]
+    say("case refine qep n=64,", len(inside), "eigenvalues")
+    err = _refine_case(w.problems[0], w.regions[0], w.opts, inside, 11)
+    assert err.max() <= 1e-11
+
+
+def test_refine_delay_lambert(A):
+    """A delay problem Q diag(-z + a_i + b_i e^{-tau z}) Q^H (Q a seeded unitary), whose
+    eigenvalues are the Lambert-W roots of the scalar equations: the principal-branch
+    roots, perturbed by 1e-5, are recovered within 1e-11."""
+    n, tau = 96, 1.3
+    rng = np.random.default_rng(21)
+    a = rng.uniform(-2, 0.5, n) + 1j * rng.uniform(-1, 1, n)
+    b = rng.uniform(-1, 1, n) + 1j * rng.uniform(-0.5, 0.5, n)
+    Z = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    Q, _ = np.linalg.qr(Z)
+    prob = gen.delay(Q @ np.diag(a) @ Q.conj().T, Q @ np.diag(b) @ Q.conj().T, tau)
+    exact = np.array([oracle.brute.delay_scalar_roots(a[i], b[i], tau, [0])[0] for i in range(n)])
+    say("case refine delay n=96 tau=1.3")
+    err = _refine_case(prob, gen.Region(-4, 2, -4, 4, 2, 2), gen.Options(N=32, s=1, L=8), exact, 12)
+    assert err.max() <= 1e-11
