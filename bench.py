@@ -16,6 +16,11 @@ Prints ONE JSON line.
   rate, speedup, and agreement with the complex128 sweep.
 - `eigenpairs_unsaturated` = eigenpairs/s where the rank test is not cut by the probe
   count (the workload as configured saturates every flagged disk).
+- `eigenpairs_complete` = the complete spectrum of the dense workload (2048
+  eigenvalues) by the saturation remedy (cells split 2 x 2 until no flagged disk
+  saturates, candidates refined and verified), complex128 and mixed sweeps: wall time,
+  eigenpairs/s, and the worst relative error against the companion pencil stored
+  under tests/golden/.
 - `roofline` = the dominant kernel (trailing-update kernel of the batched LU). Its
   durations come from the library's own HIP events recorded on the stream the
   kernel runs on.
@@ -179,6 +184,50 @@ def copy_calibration(nbytes: int = 1 << 30, reps: int = 3):
     return {"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps, "GBps": 2 * nbytes / dt / 1e9}
 
 
+def golden_dense_eigs():
+    """The dense workload's 2048 companion-pencil eigenvalues stored under tests/golden/
+    (written from the oracle by tests/golden/make_golden.py --dense), or None."""
+    path = os.path.join(ROOT, "tests", "golden", "dense_qep_n1024_eigs.txt")
+    if not os.path.exists(path):
+        return None
+    a = np.loadtxt(path)
+    return a[:, 0] + 1j * a[:, 1]
+
+
+def complete_spectrum(pivot: int, reps: int = 1):
+    """The saturation remedy on the dense workload (cells split until no flagged disk
+    saturates, candidates refined and verified): eigenpairs/s of the complete spectrum
+    and the worst relative error against the companion pencil, per precision."""
+    import torch
+    from paper_2312_13117_amd import adaptive
+    ref = golden_dense_eigs()
+    res = {}
+    for tag, precision in (("fp64", 0), ("mixed", 1)):
+        w = build_workload("dense" if precision == 0 else "dense_mixed", pivot=pivot)
+        run = lambda: adaptive.pmcimb_adaptive(w.problems[0], w.regions[0], w.opts, w.F[0], w.V[0], max_depth=8)
+        ts, r = [], None                  # the library is warm from the sweep benchmark
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = run()
+            ts.append(time.perf_counter() - t0)
+        t = float(np.median(ts))
+        e = {"eigenpairs": int(len(r.eigs)), "seconds": t, "eigenpairs_per_s": len(r.eigs) / t,
+             "node_solves": int(r.node_solves), "levels": r.levels, "disks_swept": r.disks_swept,
+             "unresolved": r.unresolved}
+        if ref is not None and len(r.eigs):
+            d = np.abs(r.eigs[:, None] - ref[None, :])
+            near = np.argmin(d, axis=1)
+            e["max_rel_err_vs_companion"] = float(np.max(d[np.arange(len(r.eigs)), near] /
+                                                         np.maximum(1.0, np.abs(ref[near]))))
+            e["companion_eigenvalues"] = int(len(ref))
+            e["one_to_one"] = bool(len(set(near.tolist())) == len(r.eigs))
+        res[tag] = e
+        _log(f"complete spectrum {tag}: {e}")
+    res["speedup_mixed_vs_fp64"] = res["fp64"]["seconds"] / res["mixed"]["seconds"]
+    return res
+
+
 def phase_dict(st):
     return {k: st[k] for k in ("ms_assemble", "ms_lu", "ms_solve", "ms_refine", "ms_sums", "ms_total")}
 
@@ -310,6 +359,8 @@ def main():
             eo[tag] = {"eigenpairs": int(len(oe["eigs"])), "ms_per_step": Te * 1e3,
                        "eigenpairs_per_s": len(oe["eigs"]) / Te}
         out["eigenpairs_unsaturated"] = {"workload": "qep_n64_4x4_L31", **eo}
+    if args.workload == "dense" and not args.no_eigen and not args.no_mixed:
+        out["eigenpairs_complete"] = {"workload": w.name + "_adaptive", **complete_spectrum(pivot)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_disks)
     print(json.dumps(out))

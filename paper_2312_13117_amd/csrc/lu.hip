@@ -833,14 +833,14 @@ __global__ __launch_bounds__(4 * R) void tslu_root_kernel(c2<T>* __restrict__ W,
 }
 
 // ----------------------------------------------------------------------------- recursive panel
-// Panels of more than 256 rows under partial pivoting, as four 16-column leaves.  A
-// leaf holds rows r0 .. n-1 of its 16 columns in registers (RPT rows per thread, 1024
+// Panels of more than 256 rows under partial pivoting, as leaves of W columns.  A
+// leaf holds rows r0 .. n-1 of its W columns in registers (RPT rows per thread, NT
 // threads), runs partial pivoting on them (one barrier per column; 64-bit keys hold
 // the magnitude's top bits and the row), writes the factored columns at their
-// exchanged rows, applies its exchange to the panel's other 48 columns and forms the
-// 16 rows of U to its right inside the panel.  A rank-16 update of the rows below
+// exchanged rows, applies its exchange to the panel's other 64 - W columns and forms
+// the W rows of U to its right inside the panel.  A rank-W update of the rows below
 // follows as a launch of its own (many workgroups per matrix).  A finishing kernel
-// composes the four exchanges into the step's one and forms inv(L11) and inv(U11).
+// composes the leaves' exchanges into the step's one and forms inv(L11) and inv(U11).
 // Leaf shapes: complex128 uses 8-column leaves of 512 threads (two rows each), whose
 // registers leave room on the CU for a workgroup of the other stream's update;
 // complex64 uses 16-column leaves of 1024 threads (one or two rows each).

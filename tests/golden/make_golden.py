@@ -3,6 +3,10 @@
 paper_demo_qep.txt: the 4x4 quadratic printed in the paper's appendix routine that
 generates T(z) (T2 = diag(3,1,3,1), T1, T0 as printed there), and its 8 eigenvalues
 from the companion linearisation (a library generalized eigensolver).
+
+dense_qep_n1024_eigs.txt (with --dense; minutes of CPU): the 2048 eigenvalues of the
+dense n = 1024 QEP (K = A + A^T, C = 0.1 B, M = I + 0.1 G G^T, seeds 0, 1, 2) from
+its companion pencil, sorted by (Re, Im).
 """
 import os
 import sys
@@ -16,7 +20,23 @@ import gen  # noqa: E402
 from oracle import brute  # noqa: E402
 
 
+def dense():
+    w = gen.workload_dense_qep(1024)
+    ev = brute.companion_eigs(w.problems[0])
+    ev = ev[np.lexsort((ev.imag, ev.real))]
+    with open(os.path.join(HERE, "dense_qep_n1024_eigs.txt"), "w") as f:
+        f.write("# All 2n = 2048 eigenvalues of the dense n = 1024 QEP K + z C + z^2 M with\n")
+        f.write("# K = A + A^T, C = 0.1 B, M = I + 0.1 G G^T (Gaussian entries / sqrt(n), seeds 0, 1, 2),\n")
+        f.write("# from the companion pencil; columns: Re Im, sorted by (Re, Im).\n")
+        f.write("# Written by tests/golden/make_golden.py --dense (oracle only).\n")
+        for v in ev:
+            f.write(f"{v.real:.17e} {v.imag:.17e}\n")
+
+
 def main():
+    if "--dense" in sys.argv:
+        dense()
+        return
     p = gen.paper_demo_problem()
     ev = brute.companion_eigs(p)
     ev = np.sort(ev.real[np.argsort(ev.real)])

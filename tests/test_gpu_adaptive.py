@@ -94,3 +94,36 @@ def test_refine_delay_lambert(A):
     say("case refine delay n=96 tau=1.3")
     err = _refine_case(prob, gen.Region(-4, 2, -4, 4, 2, 2), gen.Options(N=32, s=1, L=8), exact, 12)
     assert err.max() <= 1e-11
+
+
+def _golden_dense():
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "dense_qep_n1024_eigs.txt")
+    a = np.loadtxt(path)
+    return a[:, 0] + 1j * a[:, 1]
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-8)])
+def test_adaptive_dense_complete(A, precision, tol):
+    """The dense n = 1024 QEP over [-4,4]^2 (16 x 16 cells, L = 16: every flagged disk
+    saturated at level 0): the adaptive driver returns all 2048 eigenvalues of the
+    companion pencil, within 1e-10 (complex128 sweeps) or 1e-8 (complex64 sweeps with
+    refinement) relative."""
+    ref = _golden_dense()
+    w = gen.workload_dense_qep(1024, precision=precision)
+    r = w.regions[0]
+    inside = ref[(ref.real > r.x0) & (ref.real < r.x1) & (ref.imag > r.y0) & (ref.imag < r.y1)]
+    say(f"case adaptive dense n=1024 precision={precision}: {len(inside)} eigenvalues in Omega")
+    res = A.pmcimb_adaptive(w.problems[0], r, w.opts, w.F[0], w.V[0], max_depth=8,
+                            log=lambda m: say("  " + m))
+    say("  levels", res.levels, "swept", res.disks_swept, "saturated", res.saturated, "found", len(res.eigs),
+        f"{res.seconds:.2f} s")
+    assert res.unresolved == 0
+    d = np.abs(res.eigs[:, None] - inside[None, :])
+    near = np.argmin(d, axis=1)
+    err = d[np.arange(len(res.eigs)), near] / np.maximum(1.0, np.abs(inside[near]))
+    say("  max relative error vs companion", err.max() if len(err) else None)
+    assert len(res.eigs) == len(inside)
+    assert len(set(near.tolist())) == len(inside)      # a one-to-one match
+    assert err.max() <= tol
+    assert np.all(res.sigma < w.opts.tol_ver)
