@@ -13,3 +13,4 @@ brute force or library routines (tests/test_oracle_*.py).
 """
 from .nep import *  # noqa: F401,F403
 from . import brute  # noqa: F401
+from . import pmcima  # noqa: F401,E402
