@@ -255,10 +255,15 @@ nep_status nep_verify(nep_plan_t* plan, const int32_t* prob_ids, const void* lam
  *              a simple eigenvalue to rounding level)
  *   sigma_min  host double [m]: at the returned value
  *   accepted   host uint8 [m]: sigma_min < tol_ver
+ *   vec        NULL, or host complex128 [m * ldv]: row i receives the right singular
+ *              vector of sigma_min(T(lambda_i)) at the returned value (the eigenvector
+ *              of pmCIMa's Step 2, Section 3.1): unit 2-norm, its largest-modulus
+ *              entry real and positive; entries past the candidate's n are untouched
+ *   ldv        >= n of every listed candidate's problem when vec is given
  * Cost: (iters + 1) complex128 LUs per candidate.  Errors: NEP_ERR_ARG.           */
 #define NEP_REFINE_MAX_ITERS 8
 nep_status nep_refine(nep_plan_t* plan, const int32_t* prob_ids, void* lam, int m, int iters,
-                      double* sigma_min, uint8_t* accepted);
+                      double* sigma_min, uint8_t* accepted, void* vec, int ldv);
 
 /* nep_copy_sums -- copy the quadrature sums of disks [first, first + count) of the last
  * sweep to host buffers (any may be NULL): PfN, PfN2 as n x s, C0, C1 as n x L per disk,

@@ -169,7 +169,7 @@ def pmcimb_adaptive(problem, region, opts, F, V, max_depth: int = 5, N_beyn: int
         # refinement onto the eigenvalues, ownership across cells, verification, merge
         if cands:
             lam = np.asarray([l for _, l in cands], dtype=np.complex128)
-            lam, sig, acc = N.nep_refine(plan0, np.zeros(len(lam), np.int32), lam, refine_iters)
+            lam, sig, acc, _ = N.nep_refine(plan0, np.zeros(len(lam), np.int32), lam, refine_iters)
             cands = [(c, l) for (c, _), l in zip(cands, lam)]
             sel = _owned(cands) & acc
             al, asg = lam[sel], sig[sel]

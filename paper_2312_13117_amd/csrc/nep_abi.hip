@@ -943,6 +943,20 @@ static std::complex<double> rayleigh_root(const ProblemDev& pd, const double2* a
   return rho;
 }
 
+// a unit vector with its largest-modulus entry (the first of equal ones) real and positive
+static void store_vector(const double2* v, int n, double2* out) {
+  int im = 0;
+  double best = -1, nrm = 0;
+  for (int i = 0; i < n; ++i) {
+    const double a = v[i].x * v[i].x + v[i].y * v[i].y;
+    nrm += a;
+    if (a > best) { best = a; im = i; }
+  }
+  const double am = std::sqrt(best), sc = (am > 0 && nrm > 0) ? 1.0 / (am * std::sqrt(nrm)) : 0.0;
+  const double px = v[im].x * sc, py = -v[im].y * sc;   // conj(v_im) / (|v_im| ||v||)
+  for (int i = 0; i < n; ++i) out[i] = make_double2(v[i].x * px - v[i].y * py, v[i].x * py + v[i].y * px);
+}
+
 // sigma_min(T(lambda)) by inverse iteration on the complex128 LU, after `iters` two-sided
 // Rayleigh-functional updates of lambda (iters = 0: verification only).  Each update
 // takes the left and right singular-vector estimates u, v of the last inverse iteration,
@@ -950,7 +964,7 @@ static std::complex<double> rayleigh_root(const ProblemDev& pd, const double2* a
 // u^H T(rho) v = sum_k phi_k(rho) a_k; every candidate keeps the point of smallest
 // sigma_min seen, so an update never returns a worse value than its input.
 static nep_status verify_refine(nep_plan_t* P, const int32_t* prob_ids, const double2* lam_in, double2* lam_out,
-                                int m, int iters, double* sigma_min, uint8_t* accepted) {
+                                int m, int iters, double* sigma_min, uint8_t* accepted, double2* vec, int ldv) {
   reset_stats(P);
   tmark(P, PH_TOTAL, true, P->st);
   constexpr int ITERS = 4;
@@ -977,6 +991,7 @@ static nep_status verify_refine(nep_plan_t* P, const int32_t* prob_ids, const do
       std::vector<double2> z(nb), zbest(nb), ha((size_t)nb * MAX_TERMS);
       std::vector<double> sbest(nb, INFINITY), hest(nb);
       std::vector<int> hinf(nb);
+      std::vector<double2> hv(vec ? (size_t)nb * n : 0);
       for (int b = 0; b < nb; ++b) z[b] = zbest[b] = lam_in[idx[c0 + b]];
       for (int it = 0; it <= iters; ++it) {
         const bool upd = it < iters;
@@ -1002,10 +1017,16 @@ static nep_status verify_refine(nep_plan_t* P, const int32_t* prob_ids, const do
         }
         HIPCHK(P, hipMemcpyAsync(hest.data(), est, sizeof(double) * nb, hipMemcpyDeviceToHost, P->st));
         HIPCHK(P, hipMemcpyAsync(hinf.data(), P->w64.info.p, sizeof(int) * nb, hipMemcpyDeviceToHost, P->st));
+        if (vec)
+          HIPCHK(P, hipMemcpyAsync(hv.data(), xv, sizeof(double2) * (size_t)nb * n, hipMemcpyDeviceToHost, P->st));
         HIPCHK(P, hipStreamSynchronize(P->st));
         for (int b = 0; b < nb; ++b) {
           const double sgm = hinf[b] ? 0.0 : hest[b];
-          if (sgm < sbest[b]) { sbest[b] = sgm; zbest[b] = z[b]; }
+          if (sgm < sbest[b] || it == 0) {
+            sbest[b] = sgm;
+            zbest[b] = z[b];
+            if (vec) store_vector(&hv[(size_t)b * n], n, vec + (size_t)idx[c0 + b] * ldv);
+          }
           // an exactly singular T(z) (zero pivot) leaves nothing to improve
           if (upd && !hinf[b]) {
             const std::complex<double> r = rayleigh_root(pd, &ha[(size_t)b * MAX_TERMS], {z[b].x, z[b].y});
@@ -1040,17 +1061,21 @@ extern "C" nep_status nep_verify(nep_plan_t* P, const int32_t* prob_ids, const v
   if (!P) return NEP_ERR_ARG;
   nep_status e = check_candidates(P, prob_ids, lam, m, sigma_min, accepted);
   if (e != NEP_OK || m == 0) return e;
-  return verify_refine(P, prob_ids, static_cast<const double2*>(lam), nullptr, m, 0, sigma_min, accepted);
+  return verify_refine(P, prob_ids, static_cast<const double2*>(lam), nullptr, m, 0, sigma_min, accepted, nullptr,
+                       0);
 }
 
 extern "C" nep_status nep_refine(nep_plan_t* P, const int32_t* prob_ids, void* lam, int m, int iters,
-                                 double* sigma_min, uint8_t* accepted) {
+                                 double* sigma_min, uint8_t* accepted, void* vec, int ldv) {
   if (!P) return NEP_ERR_ARG;
   nep_status e = check_candidates(P, prob_ids, lam, m, sigma_min, accepted);
   if (e != NEP_OK || m == 0) return e;
   if (iters < 0 || iters > NEP_REFINE_MAX_ITERS) return fail(P, NEP_ERR_ARG, "iters out of range");
+  if (vec)
+    for (int i = 0; i < m; ++i)
+      if (ldv < P->pd[prob_ids[i]].n) return fail(P, NEP_ERR_ARG, "ldv smaller than a candidate's order");
   double2* l = static_cast<double2*>(lam);
-  return verify_refine(P, prob_ids, l, l, m, iters, sigma_min, accepted);
+  return verify_refine(P, prob_ids, l, l, m, iters, sigma_min, accepted, static_cast<double2*>(vec), ldv);
 }
 
 // ---------------------------------------------------------------------------- accessors

@@ -62,7 +62,7 @@ def lib():
     L.nep_indicator.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), dp, u8p, dp]
     L.nep_beyn.argtypes = [vp, ip, C.c_int, C.POINTER(vp), vp, ip, dp, u8p, vp]
     L.nep_verify.argtypes = [vp, ip, vp, C.c_int, dp, u8p]
-    L.nep_refine.argtypes = [vp, ip, vp, C.c_int, C.c_int, dp, u8p]
+    L.nep_refine.argtypes = [vp, ip, vp, C.c_int, C.c_int, dp, u8p, vp, C.c_int]
     L.nep_copy_sums.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp, vp]
     L.nep_dedup.argtypes = [vp, dp, C.c_int, C.c_double, u8p]
     L.nep_total_disks.argtypes = [vp]
@@ -240,18 +240,23 @@ def nep_verify(plan: Plan, prob_ids: Sequence[int], lam: Sequence[complex]):
     return sig, acc.astype(bool)
 
 
-def nep_refine(plan: Plan, prob_ids: Sequence[int], lam: Sequence[complex], iters: int = 2):
-    """(refined lambda, sigma_min at it, accepted) -- see nep_refine in nep.h."""
+def nep_refine(plan: Plan, prob_ids: Sequence[int], lam: Sequence[complex], iters: int = 2,
+               want_vectors: bool = False):
+    """(refined lambda, sigma_min at it, accepted, vectors [m x max n] or None) -- see
+    nep_refine in nep.h."""
     L = lib()
     m = len(lam)
     pid = np.ascontiguousarray(np.asarray(prob_ids, dtype=np.int32))
     la = np.array(lam, dtype=np.complex128, copy=True, order="C")
     sig = np.zeros(m)
     acc = np.zeros(m, np.uint8)
+    ldv = max(plan.n) if want_vectors else 0
+    vec = np.zeros((m, ldv), np.complex128) if want_vectors else None
     st = L.nep_refine(plan.handle, pid.ctypes.data_as(C.POINTER(C.c_int32)), _ptr(la), m, int(iters),
-                      sig.ctypes.data_as(C.POINTER(C.c_double)), acc.ctypes.data_as(C.POINTER(C.c_uint8)))
+                      sig.ctypes.data_as(C.POINTER(C.c_double)), acc.ctypes.data_as(C.POINTER(C.c_uint8)),
+                      _ptr(vec) if vec is not None else None, ldv)
     _check(st, plan.handle)
-    return la, sig, acc.astype(bool)
+    return la, sig, acc.astype(bool), vec
 
 
 def _copy_sums_uniform(plan: Plan, first: int, count: int, n: int):

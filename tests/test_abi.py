@@ -61,7 +61,7 @@ def test_null_plan_calls():
     N, L = _lib()
     assert L.nep_indicator(None, None, None, None, None, None) == -1
     assert L.nep_verify(None, None, None, 0, None, None) == -1
-    assert L.nep_refine(None, None, None, 0, 2, None, None) == -1
+    assert L.nep_refine(None, None, None, 0, 2, None, None, None, 0) == -1
     assert L.nep_total_disks(None) == 0
     L.nep_destroy(None)
     for s in (0, 1, 2, 3, -1, -2, -3, -4, -5, -6, 99):

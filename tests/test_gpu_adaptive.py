@@ -55,9 +55,9 @@ def _refine_case(prob, region, opts, exact, seed):
     start = _perturb(exact, seed, 1e-5)
     plan = N.nep_plan([prob], [region], opts)
     try:
-        lam, sig, acc = N.nep_refine(plan, [0] * len(start), start, 2)
+        lam, sig, acc, _ = N.nep_refine(plan, [0] * len(start), start, 2)
         sig_v, acc_v = N.nep_verify(plan, [0] * len(start), start)
-        lam0, sig0, acc0 = N.nep_refine(plan, [0] * len(start), start, 0)
+        lam0, sig0, acc0, _ = N.nep_refine(plan, [0] * len(start), start, 0)
     finally:
         N.nep_destroy(plan)
     err = np.abs(lam - exact) / np.maximum(1.0, np.abs(exact))
