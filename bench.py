@@ -16,6 +16,8 @@ Prints ONE JSON line.
   rate, speedup, and agreement with the complex128 sweep.
 - `eigenpairs_unsaturated` = eigenpairs/s where the rank test is not cut by the probe
   count (the workload as configured saturates every flagged disk).
+- `pmcima` = pmCIMa (indicator levels down to tol_eps = 1e-6, merge, Step 2 vectors,
+  then refinement) on the n = 64 workload: time, node solves and accuracy.
 - `eigenpairs_complete` = the complete spectrum of the dense workload (2048
   eigenvalues) by the saturation remedy (cells split 2 x 2 until no flagged disk
   saturates, candidates refined and verified), complex128 and mixed sweeps: wall time,
@@ -184,14 +186,43 @@ def copy_calibration(nbytes: int = 1 << 30, reps: int = 3):
     return {"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps, "GBps": 2 * nbytes / dt / 1e9}
 
 
-def golden_dense_eigs():
-    """The dense workload's 2048 companion-pencil eigenvalues stored under tests/golden/
-    (written from the oracle by tests/golden/make_golden.py --dense), or None."""
-    path = os.path.join(ROOT, "tests", "golden", "dense_qep_n1024_eigs.txt")
+def golden_eigs(name: str):
+    path = os.path.join(ROOT, "tests", "golden", name)
     if not os.path.exists(path):
         return None
     a = np.loadtxt(path)
     return a[:, 0] + 1j * a[:, 1]
+
+
+def _match_err(found, ref):
+    """(worst relative error of found values against their nearest reference, whether
+    the nearest references are all different)."""
+    if ref is None or not len(found):
+        return None, None
+    d = np.abs(found[:, None] - ref[None, :])
+    near = np.argmin(d, axis=1)
+    err = float(np.max(d[np.arange(len(found)), near] / np.maximum(1.0, np.abs(ref[near]))))
+    return err, bool(len(set(near.tolist())) == len(found))
+
+
+def pmcima_run():
+    """pmCIMa (Section 3.1) on the n = 64 workload's cover with N = 16, tol_eps = 1e-6,
+    then two refinement updates: time, node solves, and accuracy of the merged and the
+    refined values against the companion pencil."""
+    import gen
+    from paper_2312_13117_amd import pmcima
+    w = gen.workload_small_qep()
+    ref = golden_eigs("small_qep_n64_eigs.txt")
+    run = lambda: pmcima.pmcima(w.problems[0], w.regions[0], w.F[0], refine_iters=2)
+    run()
+    r = run()
+    e_m, _ = _match_err(r.eigs, ref)
+    e_r, one = _match_err(r.refined, ref)
+    return {"workload": "qep_n64_4x4_pmcima_N16_tol1e-6", "levels": r.levels,
+            "disks": int(sum(len(d) for d in r.disks)), "node_solves": int(r.node_solves), "seconds": r.seconds,
+            "solves_per_s": r.node_solves / r.seconds, "merged_values": int(len(r.eigs)),
+            "max_rel_err_merged": e_m, "refined_eigenpairs": int(len(r.refined)), "max_rel_err_refined": e_r,
+            "refined_one_to_one": one, "eigenpairs_per_s": len(r.refined) / r.seconds}
 
 
 def complete_spectrum(pivot: int, reps: int = 1):
@@ -200,7 +231,7 @@ def complete_spectrum(pivot: int, reps: int = 1):
     and the worst relative error against the companion pencil, per precision."""
     import torch
     from paper_2312_13117_amd import adaptive
-    ref = golden_dense_eigs()
+    ref = golden_eigs("dense_qep_n1024_eigs.txt")
     res = {}
     for tag, precision in (("fp64", 0), ("mixed", 1)):
         w = build_workload("dense" if precision == 0 else "dense_mixed", pivot=pivot)
@@ -215,13 +246,9 @@ def complete_spectrum(pivot: int, reps: int = 1):
         e = {"eigenpairs": int(len(r.eigs)), "seconds": t, "eigenpairs_per_s": len(r.eigs) / t,
              "node_solves": int(r.node_solves), "levels": r.levels, "disks_swept": r.disks_swept,
              "unresolved": r.unresolved}
-        if ref is not None and len(r.eigs):
-            d = np.abs(r.eigs[:, None] - ref[None, :])
-            near = np.argmin(d, axis=1)
-            e["max_rel_err_vs_companion"] = float(np.max(d[np.arange(len(r.eigs)), near] /
-                                                         np.maximum(1.0, np.abs(ref[near]))))
+        if ref is not None:
+            e["max_rel_err_vs_companion"], e["one_to_one"] = _match_err(r.eigs, ref)
             e["companion_eigenvalues"] = int(len(ref))
-            e["one_to_one"] = bool(len(set(near.tolist())) == len(r.eigs))
         res[tag] = e
         _log(f"complete spectrum {tag}: {e}")
     res["speedup_mixed_vs_fp64"] = res["fp64"]["seconds"] / res["mixed"]["seconds"]
@@ -361,6 +388,8 @@ def main():
         out["eigenpairs_unsaturated"] = {"workload": "qep_n64_4x4_L31", **eo}
     if args.workload == "dense" and not args.no_eigen and not args.no_mixed:
         out["eigenpairs_complete"] = {"workload": w.name + "_adaptive", **complete_spectrum(pivot)}
+    if args.workload == "dense" and not args.no_eigen:
+        out["pmcima"] = pmcima_run()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_disks)
     print(json.dumps(out))

@@ -4,6 +4,9 @@ paper_demo_qep.txt: the 4x4 quadratic printed in the paper's appendix routine th
 generates T(z) (T2 = diag(3,1,3,1), T1, T0 as printed there), and its 8 eigenvalues
 from the companion linearisation (a library generalized eigensolver).
 
+small_qep_n64_eigs.txt: the 128 eigenvalues of the n = 64 QEP (K = A + A^T, C = 0.1 B,
+M = I, seeds 0, 1) from its companion pencil, sorted by (Re, Im).
+
 dense_qep_n1024_eigs.txt (with --dense; minutes of CPU): the 2048 eigenvalues of the
 dense n = 1024 QEP (K = A + A^T, C = 0.1 B, M = I + 0.1 G G^T, seeds 0, 1, 2) from
 its companion pencil, sorted by (Re, Im).
@@ -33,10 +36,23 @@ def dense():
             f.write(f"{v.real:.17e} {v.imag:.17e}\n")
 
 
+def small():
+    w = gen.workload_small_qep()
+    ev = brute.companion_eigs(w.problems[0])
+    ev = ev[np.lexsort((ev.imag, ev.real))]
+    with open(os.path.join(HERE, "small_qep_n64_eigs.txt"), "w") as f:
+        f.write("# All 2n = 128 eigenvalues of the n = 64 QEP K + z C + z^2 I with K = A + A^T,\n")
+        f.write("# C = 0.1 B (Gaussian entries / sqrt(n), seeds 0, 1), from the companion pencil;\n")
+        f.write("# columns: Re Im, sorted by (Re, Im).  Written by tests/golden/make_golden.py (oracle only).\n")
+        for v in ev:
+            f.write(f"{v.real:.17e} {v.imag:.17e}\n")
+
+
 def main():
     if "--dense" in sys.argv:
         dense()
         return
+    small()
     p = gen.paper_demo_problem()
     ev = brute.companion_eigs(p)
     ev = np.sort(ev.real[np.argsort(ev.real)])
