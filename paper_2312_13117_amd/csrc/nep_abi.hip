@@ -492,7 +492,7 @@ static nep_status fallback_solves(nep_plan_t* P, int prob, const SweepCall& sc, 
 
 // One batch of node systems: assemble, factor, solve, refine (mixed precision).
 static nep_status sweep_batch(nep_plan_t* P, Workspace& w, int prob, const double2* zb, double2* Xb, int nb,
-                              const SweepCall& sc, int* sing_out, int* fb_out, bool* fallback) {
+                              const SweepCall& sc, int* sing_out, int* fb_out) {
   const ProblemDev& pd = P->pd[prob];
   const int n = pd.n, s = sc.s, L = sc.L, m = s + L;
   const double2* F = static_cast<const double2*>(sc.F[prob]);
@@ -522,26 +522,11 @@ static nep_status sweep_batch(nep_plan_t* P, Workspace& w, int prob, const doubl
   tmark(P, PH_REFINE, true, w.st);
   HIPCHK(P, launch_fill_int(w.active.as<int>(), 1, nb, w.st));
   HIPCHK(P, launch_fill_int(w.active.as<int>() + nb, 0, nb, w.st));   // diverged flags
-  if (P->capturing) {
-    // graph mode: every sweep is recorded (tasks that have converged are masked
-    // off inside the kernels, so the result equals the eager loop's), no host
-    // decisions; the tasks needing a complex128 re-solve are listed for the host
-    for (int it = 0; it < P->opt.max_refine; ++it) {
-      P->stats.refine_sweeps++;
-      HIPCHK(P, launch_residual(pd, zb, Xb, F, s, V, L, (long long)n * m, m, nb, Rb, w.active.as<int>(), w.st));
-      r = solve_chunk<float>(P, w, n, nb, Rb, m, false, w.active.as<int>());
-      if (r != NEP_OK) return r;
-      HIPCHK(P, launch_axpy(Xb, Rb, (long long)n * m, n * m, w.active.as<int>(), nb, w.st));
-      int* cnt = w.counter.as<int>();
-      HIPCHK(P, launch_fill_int(cnt, 0, 1, w.st));
-      HIPCHK(P, launch_refine_check(Rb, Xb, (long long)n * m, n * m, tol, w.rn2.as<double>(), it == 0,
-                                    w.active.as<int>(), w.active.as<int>() + nb, nb, cnt, w.st));
-    }
-    HIPCHK(P, launch_or_flags(w.active.as<int>(), w.active.as<int>() + nb, nb, fb_out, w.st));
-    return NEP_OK;
-  }
-  int nact = nb;
-  for (int it = 0; it < P->opt.max_refine && nact > 0; ++it) {
+  // every sweep is issued (tasks that have converged are masked off inside the
+  // kernels) and no decision waits for the host, so the other worker stream never
+  // runs dry; the tasks needing a complex128 re-solve are listed in fb_out and
+  // re-solved after the whole sweep (resolve_fallbacks)
+  for (int it = 0; it < P->opt.max_refine; ++it) {
     P->stats.refine_sweeps++;
     HIPCHK(P, launch_residual(pd, zb, Xb, F, s, V, L, (long long)n * m, m, nb, Rb, w.active.as<int>(), w.st));
     r = solve_chunk<float>(P, w, n, nb, Rb, m, false, w.active.as<int>());
@@ -551,26 +536,8 @@ static nep_status sweep_batch(nep_plan_t* P, Workspace& w, int prob, const doubl
     HIPCHK(P, launch_fill_int(cnt, 0, 1, w.st));
     HIPCHK(P, launch_refine_check(Rb, Xb, (long long)n * m, n * m, tol, w.rn2.as<double>(), it == 0,
                                   w.active.as<int>(), w.active.as<int>() + nb, nb, cnt, w.st));
-    HIPCHK(P, hipMemcpyAsync(&nact, cnt, sizeof(int), hipMemcpyDeviceToHost, w.st));
-    HIPCHK(P, hipStreamSynchronize(w.st));
   }
-  {
-    // still active after max_refine sweeps, or diverged: re-solve in complex128
-    std::vector<int> act(2 * (size_t)nb);
-    HIPCHK(P, hipMemcpyAsync(act.data(), w.active.p, sizeof(int) * 2 * nb, hipMemcpyDeviceToHost, w.st));
-    HIPCHK(P, hipStreamSynchronize(w.st));
-    for (int b = 0; b < nb; ++b) act[b] = act[b] || act[nb + b];
-    nact = 0;
-    for (int b = 0; b < nb; ++b) nact += act[b];
-    if (nact > 0) {
-      std::vector<FbTask> tasks;
-      for (int b = 0; b < nb; ++b)
-        if (act[b]) tasks.push_back({zb + b, Xb + (long long)b * n * m});
-      *fallback = true;
-      nep_status e = fallback_solves(P, prob, sc, tasks);
-      if (e != NEP_OK) return e;
-    }
-  }
+  HIPCHK(P, launch_or_flags(w.active.as<int>(), w.active.as<int>() + nb, nb, fb_out, w.st));
   tmark(P, PH_REFINE, false, w.st);
   return NEP_OK;
 }
@@ -638,7 +605,7 @@ static nep_status run_sums(nep_plan_t* P, const SweepCall& sc, const SweepLayout
 // The device work of a sweep (stream-ordered, no host synchronisation unless the
 // mixed-precision refinement runs eagerly): batches of node systems alternate
 // between the worker streams, then the sums.
-static nep_status run_sweep_device(nep_plan_t* P, const SweepCall& sc, const SweepLayout& lay, bool* fallback) {
+static nep_status run_sweep_device(nep_plan_t* P, const SweepCall& sc, const SweepLayout& lay) {
   const int N = P->opt.N, m = sc.s + sc.L;
   const int nl = (int)sc.disks.size();
   HIPCHK(P, launch_fill_int(P->sing.as<int>(), 0, nl * N, P->st));
@@ -658,7 +625,7 @@ static nep_status run_sweep_device(nep_plan_t* P, const SweepCall& sc, const Swe
       Workspace& w = P->ws[P->nstreams == 2 ? (k & 1) : 0];
       const long long task0 = (long long)g.li * N + t0;
       nep_status r = sweep_batch(P, w, prob, tn + task0, X + lay.xoff[g.li] + t0 * (long long)n * m, nb, sc,
-                                 P->sing.as<int>() + task0, P->fbflag.as<int>() + task0, fallback);
+                                 P->sing.as<int>() + task0, P->fbflag.as<int>() + task0);
       if (r != NEP_OK) return r;
     }
   }
@@ -671,16 +638,9 @@ static nep_status run_sweep_device(nep_plan_t* P, const SweepCall& sc, const Swe
   return run_sums(P, sc, lay);
 }
 
-static nep_status run_sweep(nep_plan_t* P, const SweepCall& sc, bool* fallback) {
-  SweepLayout lay;
-  nep_status r = upload_layout(P, sc, lay);
-  if (r != NEP_OK) return r;
-  return run_sweep_device(P, sc, lay, fallback);
-}
-
-// complex128 re-solves of the tasks a captured mixed-precision sweep listed, then the
-// sums again; returns the number of re-solved tasks
-static nep_status graph_fallbacks(nep_plan_t* P, const SweepCall& sc, const SweepLayout& lay, int* count) {
+// complex128 re-solves of the tasks a mixed-precision sweep listed (eager or replayed),
+// then the sums again; returns the number of re-solved tasks
+static nep_status resolve_fallbacks(nep_plan_t* P, const SweepCall& sc, const SweepLayout& lay, int* count) {
   const int N = P->opt.N, s = sc.s, L = sc.L, m = s + L;
   const int nl = (int)sc.disks.size();
   *count = 0;
@@ -703,6 +663,18 @@ static nep_status graph_fallbacks(nep_plan_t* P, const SweepCall& sc, const Swee
   return NEP_OK;
 }
 
+static nep_status run_sweep(nep_plan_t* P, const SweepCall& sc, bool* fallback) {
+  SweepLayout lay;
+  nep_status r = upload_layout(P, sc, lay);
+  if (r != NEP_OK) return r;
+  r = run_sweep_device(P, sc, lay);
+  if (r != NEP_OK || P->opt.precision != NEP_FP32_REFINE) return r;
+  int cnt = 0;
+  r = resolve_fallbacks(P, sc, lay, &cnt);
+  if (cnt > 0) *fallback = true;
+  return r;
+}
+
 // Graph mode: capture the device work of the full sweep (every disk) and the
 // indicator kernel once, replay it on later calls with the same probe blocks.
 static nep_status capture_sweep(nep_plan_t* P, const SweepCall& sc, const SweepLayout& lay) {
@@ -718,11 +690,10 @@ static nep_status capture_sweep(nep_plan_t* P, const SweepCall& sc, const SweepL
   // stream
   hipStream_t orig = P->st;
   P->st = P->cap_st;
-  bool fb = false;
   nep_status r = NEP_OK;
   hipError_t e = hipStreamBeginCapture(P->st, hipStreamCaptureModeGlobal);
   if (e == hipSuccess) {
-    r = run_sweep_device(P, sc, lay, &fb);
+    r = run_sweep_device(P, sc, lay);
     if (r == NEP_OK)
       r = (launch_indicator(P->PfN.as<double2>(), P->PfN2.as<double2>(), P->dev_dn.as<int>(),
                             P->dev_soff.as<long long>(), P->opt.s, P->opt.tol_ind, P->ind.as<double>(),
@@ -781,7 +752,7 @@ extern "C" nep_status nep_indicator(nep_plan_t* P, const void* const* F_dev, con
     HIPCHK(P, hipGraphLaunch(P->gexec, P->st));
     if (P->opt.precision == NEP_FP32_REFINE) {
       int cnt = 0;
-      r = graph_fallbacks(P, sc, lay, &cnt);
+      r = resolve_fallbacks(P, sc, lay, &cnt);
       if (r != NEP_OK) return r;
       if (cnt > 0) {
         fb = true;
