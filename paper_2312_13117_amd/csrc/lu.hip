@@ -1133,8 +1133,13 @@ __global__ __launch_bounds__(256) void rpanel_finish_kernel(const c2<T>* __restr
 // The trailing matrix is then read and written once per two panels.
 enum { GEMM_UPDATE = 0, GEMM_TRSM = 1, GEMM_PANEL = 2, GEMM_PREUPD = 3, GEMM_TRSM_ID = 4, GEMM_UPDATE2 = 5 };
 
+// three workgroups per CU, except the modes that keep a panel's displaced rows in
+// registers (two: three would spill them)
+template <int MODE>
+constexpr int gemm_min_blocks() { return (MODE == GEMM_TRSM || MODE == GEMM_PREUPD) ? 2 : 3; }
+
 template <typename T, int MODE>
-__global__ __launch_bounds__(256, 2) void lu_gemm_kernel(c2<T>* __restrict__ W, long long mstride, int n, int k0,
+__global__ __launch_bounds__(256, gemm_min_blocks<MODE>()) void lu_gemm_kernel(c2<T>* __restrict__ W, long long mstride, int n, int k0,
                                                       int nbk, int step, int nbatch, int tiles_r, int tiles_c,
                                                       const int* __restrict__ perm, long long perm_stride,
                                                       const c2<T>* __restrict__ Linv, long long inv_stride,
@@ -1250,15 +1255,19 @@ __global__ __launch_bounds__(256, 2) void lu_gemm_kernel(c2<T>* __restrict__ W, 
     }
   }
 
-  // Operand chunks of KC = 16 columns of A (64 x 16) and rows of B (16 x 64) are loaded
-  // cooperatively (4 entries per thread each), double-buffered in LDS, one chunk ahead.
-  constexpr int KC = 16, AP = KC + 1;
+  // Operand chunks of KC columns of A (64 x KC) and rows of B (KC x 64) are loaded
+  // cooperatively (EPT entries per thread each), double-buffered in LDS, one chunk
+  // ahead.  complex128 takes KC = 8: 35 KB of LDS and at most 168 VGPRs leave room for
+  // three workgroups per CU (3 waves per SIMD; 16-deep chunks allowed two and ran the
+  // paired update at 36 instead of 48 TFLOP/s); complex64 keeps 16-deep chunks.
+  constexpr int KC = sizeof(T) == 8 ? 8 : 16, AP = KC + 1;
+  constexpr int EPT = KC * 64 / 256;
   __shared__ c2<T> As[2][64][AP];
   __shared__ c2<T> Bs[2][KC][64];
   const int wr = wave >> 1, wc = wave & 1;
-  const int arow = t >> 2, akq = (t & 3) * 4;     // A chunk: row, first of 4 k
-  const int bk = t >> 4, bcq = (t & 15) * 4;      // B chunk: k row, first of 4 columns
-  c2<T> ra[4], rbv[4];
+  const int arow = t / (KC / EPT), akq = (t % (KC / EPT)) * EPT;   // A chunk: row, first k
+  const int bk = t / (64 / EPT), bcq = (t % (64 / EPT)) * EPT;     // B chunk: k row, first column
+  c2<T> ra[EPT], rbv[EPT];
   long long a_lo = 0, a_hi = 0;                   // GEMM_UPDATE2: A-operand row bases
   if (MODE == GEMM_UPDATE2) {
     a_lo = (long long)s_from[arow] * n + k0p;
@@ -1267,7 +1276,7 @@ __global__ __launch_bounds__(256, 2) void lu_gemm_kernel(c2<T>* __restrict__ W, 
   auto load_chunk = [&](int kc) {
     const int row = R0 + arow;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < EPT; ++u) {
       const int k = kc + akq + u;
       if (MODE == GEMM_UPDATE)
         ra[u] = (row < n && k < nbk) ? A[(long long)row * n + k0 + k] : czero<T>();
@@ -1285,7 +1294,7 @@ __global__ __launch_bounds__(256, 2) void lu_gemm_kernel(c2<T>* __restrict__ W, 
     const int k = kc + bk;
     if (MODE == GEMM_PANEL) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) rbv[u] = (k < nbk) ? Li[k * NBMAX + bcq + u] : czero<T>();
+      for (int u = 0; u < EPT; ++u) rbv[u] = (k < nbk) ? Li[k * NBMAX + bcq + u] : czero<T>();
       return;
     }
     int srow = 0;
@@ -1295,14 +1304,14 @@ __global__ __launch_bounds__(256, 2) void lu_gemm_kernel(c2<T>* __restrict__ W, 
       else srow = k0 + k;
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < EPT; ++u) {
       const int col = C0 + bcq + u;
       rbv[u] = (k < ktot && col < n) ? A[(long long)srow * n + col] : czero<T>();
     }
   };
   auto store_chunk = [&](int buf) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < EPT; ++u) {
       As[buf][arow][akq + u] = ra[u];
       Bs[buf][bk][bcq + u] = rbv[u];
     }
