@@ -76,6 +76,7 @@ def tune(sizes, precisions=(0, 1), reps: int = 3, log=print) -> dict:
         for batch, streams, graph in itertools.product(cands, (1, 2), (0, 1)):
             o = gen.Options(N=32, s=4, L=16, precision=prec, batch=batch, streams=streams, graph=graph)
             rate = _time_config(w, o, reps)
+            log(f"  n={n} precision={prec} batch={batch} streams={streams} graph={graph}: {rate:.0f} solves/s")
             results.append({"batch": batch, "streams": streams, "graph": graph, "solves_per_s": rate})
             if best is None or rate > best["solves_per_s"]:
                 best = results[-1]
