@@ -46,6 +46,23 @@ class Problem:
 
 
 @dataclass
+class ElementwiseDelay:
+    """T(z) = -z I + A0 + A1 .* exp(-tau .* z): every entry of A1 with a delay of its
+    own (tau real n x n, >= 0).  With n^2 distinct delays T has no short split form, so
+    the GPU path assembles it by a caller-supplied assembler (the generic T(z) of the
+    paper's appendix routine that generates T) instead of the split coefficients."""
+    n: int
+    A0: np.ndarray
+    A1: np.ndarray
+    tau: np.ndarray
+
+    def __post_init__(self):
+        for X in (self.A0, self.A1):
+            assert X.shape == (self.n, self.n) and X.dtype == np.complex128
+        assert self.tau.shape == (self.n, self.n) and self.tau.dtype == np.float64
+
+
+@dataclass
 class Region:
     """Rectangle [x0,x1] x [y0,y1] split into nx x ny equal cells."""
     x0: float
@@ -160,6 +177,14 @@ def workload_delay(count: int = 64, sizes: Sequence[int] = (128, 256, 512, 1024,
     opts = Options(N=48, s=1, L=8, precision=precision)
     F = [probes(2000 + p, pr.n, 1) for p, pr in enumerate(probs)]
     return Workload("delay_uneven", probs, [reg] * len(probs), opts, F, [None] * len(probs))
+
+
+def elementwise_delay(n: int, seed: int, tau_lo: float = 0.5, tau_hi: float = 2.0) -> ElementwiseDelay:
+    """A0 = G0, A1 = G1 (Gaussian / sqrt(n), seeds `seed`, `seed` + 1), tau_ij ~
+    U[tau_lo, tau_hi] from rng(seed + 2)."""
+    c = lambda X: np.ascontiguousarray(X.astype(np.complex128))
+    tau = np.random.default_rng(seed + 2).uniform(tau_lo, tau_hi, size=(n, n))
+    return ElementwiseDelay(n, c(gaussian(seed, n)), c(gaussian(seed + 1, n)), np.ascontiguousarray(tau))
 
 
 def screener_problem(p: int, n: int = 256) -> Problem:

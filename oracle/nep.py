@@ -16,7 +16,7 @@ import numpy as np
 import scipy.linalg as sla
 
 from gen import (PHI_ONE, PHI_Z, PHI_Z2, PHI_NEG_Z, PHI_EXP_NEG_TAU_Z, Problem,
-                 Region, Options)
+                 Region, Options, ElementwiseDelay)
 
 # ---------------------------------------------------------------- T(z)
 
@@ -53,7 +53,12 @@ def dphi(kind: int, param: float, z: complex) -> complex:
 
 def assemble(prob: Problem, z: complex) -> np.ndarray:
     """T(z) = sum_k phi_k(z) A_k: the matrix function of eq (1.1), in the split form of
-    the appendix routine that generates T(z)."""
+    the appendix routine that generates T(z); an ElementwiseDelay problem is written out
+    entry by entry, -z I + A0 + A1 .* exp(-tau .* z)."""
+    if isinstance(prob, ElementwiseDelay):
+        T = prob.A0 + prob.A1 * np.exp(-prob.tau * complex(z))
+        T[np.diag_indices(prob.n)] -= complex(z)
+        return T
     T = np.zeros((prob.n, prob.n), dtype=np.complex128)
     for A, kind, par in zip(prob.coeffs, prob.phi_kind, prob.phi_param):
         f = phi(kind, par, z)
@@ -65,6 +70,10 @@ def assemble(prob: Problem, z: complex) -> np.ndarray:
 
 
 def assemble_derivative(prob: Problem, z: complex) -> np.ndarray:
+    if isinstance(prob, ElementwiseDelay):
+        T = -prob.tau * prob.A1 * np.exp(-prob.tau * complex(z))
+        T[np.diag_indices(prob.n)] -= 1.0
+        return T
     T = np.zeros((prob.n, prob.n), dtype=np.complex128)
     for A, kind, par in zip(prob.coeffs, prob.phi_kind, prob.phi_param):
         f = dphi(kind, par, z)
