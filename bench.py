@@ -16,6 +16,8 @@ Prints ONE JSON line.
   rate, speedup, and agreement with the complex128 sweep.
 - `eigenpairs_unsaturated` = eigenpairs/s where the rank test is not cut by the probe
   count (the workload as configured saturates every flagged disk).
+- `generic_assembly` = the whole step on a problem without a short split form (an
+  elementwise delay, n = 1024, written at every node by an assembler callback).
 - `pmcima` = pmCIMa (indicator levels down to tol_eps = 1e-6, merge, Step 2 vectors,
   then refinement) on the n = 64 workload: time, node solves and accuracy.
 - `eigenpairs_complete` = the complete spectrum of the dense workload (2048
@@ -225,6 +227,24 @@ def pmcima_run():
             "refined_one_to_one": one, "eigenpairs_per_s": len(r.refined) / r.seconds}
 
 
+def generic_run(steps: int):
+    """A problem without a short split form: the elementwise delay T(z) = -zI + A0 +
+    A1 .* exp(-tau .* z) at n = 1024 over the delay workload's rectangle (8 x 16 cells,
+    48 nodes, s = 1, L = 8), assembled at every node by the library's assembler
+    callback: the whole pmCIMb step in complex128."""
+    import gen
+    prob = gen.elementwise_delay(1024, seed=700)
+    w = gen.Workload("elementwise_delay_n1024_8x16", [prob], [gen.Region(-3.0, 1.0, -6.0, 6.0, 8, 16)],
+                     gen.Options(N=48, s=1, L=8), [gen.probes(7, 1024, 1)], [gen.probes(8, 1024, 8)])
+    r = Runner(w)
+    T, o = timed(r, steps, 1)
+    r.close()
+    st = o["stats"]
+    return {"workload": w.name, "value": st["node_solves"] / T, "unit": "solves/s", "ms_per_step": T * 1e3,
+            "flagged_disks": int(np.sum(o["flags"])), "verified_eigenpairs": int(len(o["eigs"])),
+            "phase_ms": phase_dict(st)}
+
+
 def complete_spectrum(pivot: int, reps: int = 1):
     """The saturation remedy on the dense workload (cells split until no flagged disk
     saturates, candidates refined and verified): eigenpairs/s of the complete spectrum
@@ -390,6 +410,7 @@ def main():
         out["eigenpairs_complete"] = {"workload": w.name + "_adaptive", **complete_spectrum(pivot)}
     if args.workload == "dense" and not args.no_eigen:
         out["pmcima"] = pmcima_run()
+        out["generic_assembly"] = generic_run(max(2, min(args.steps, 3)))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_disks)
     print(json.dumps(out))

@@ -95,6 +95,8 @@ enum {
  * T(z) = sum_{k < nterms} phi_{phi_kind[k]}(z) A_k, the structure of the paper's
  * appendix routine that generates T(z) (a quadratic T0 + z T1 + z^2 T2).
  *   n          matrix order, 1 <= n <= 4096
+ *   nterms     1 .. 4 split terms, or 0 for a problem written by an assembler
+ *              (nep_set_assembler, below)
  *   A_dev[k]   device pointer to A_k, complex128 row-major n x n; NULL means A_k = I
  *              (never materialised).  Borrowed until nep_destroy.
  *   phi_kind   host array of nterms NEP_PHI_* codes (copied at nep_plan)
@@ -106,6 +108,21 @@ typedef struct nep_problem {
   const int* phi_kind;
   const double* phi_param;
 } nep_problem;
+
+/* A problem with nterms = 0 has no split form: T(z) is written by a caller-supplied
+ * assembler (the general matrix function of eq (1.1), as the paper's appendix routine
+ * that generates T(z) leaves it), registered with nep_set_assembler before the first
+ * sweep.  A_dev, phi_kind and phi_param are then ignored.  Such problems need
+ * precision NEP_FP64 (the mixed path's complex128 residual uses the split
+ * coefficients), and nep_refine takes them with iters = 0 only.
+ *
+ * nep_assemble_fn -- write T(z_b) for b < nb, complex128 row-major n x n, at
+ * W_dev + b * mstride (complex elements), for the nodes z_dev[b] (device complex128).
+ * The function must only enqueue device work on `stream` (no synchronisation, no
+ * allocation, no host reads of device data): it is also recorded into HIP graphs.
+ * It returns 0 on success; any other value aborts the call with NEP_ERR_ARG.      */
+typedef int (*nep_assemble_fn)(void* ctx, int n, const void* z_dev, int nb, void* W_dev, long long mstride,
+                               hipStream_t stream);
 
 /* Omega = [x0, x1] x [y0, y1] split into nx x ny equal cells (Section 3).  Cell
  * (ix, iy) has centre (x0 + (2 ix + 1) hx, y0 + (2 iy + 1) hy), half-widths
@@ -264,6 +281,27 @@ nep_status nep_verify(nep_plan_t* plan, const int32_t* prob_ids, const void* lam
 #define NEP_REFINE_MAX_ITERS 8
 nep_status nep_refine(nep_plan_t* plan, const int32_t* prob_ids, void* lam, int m, int iters,
                       double* sigma_min, uint8_t* accepted, void* vec, int ldv);
+
+/* nep_set_assembler -- register the assembler of problem `problem` (which must have
+ * nterms = 0) and its context pointer (borrowed until nep_destroy or the next call).
+ * A captured sweep graph of the plan is dropped (the next graph-mode sweep captures
+ * again).  Errors: NEP_ERR_ARG.  Sweeps and verifications of a plan with an
+ * unregistered assembler fail with NEP_ERR_STATE.                                */
+nep_status nep_set_assembler(nep_plan_t* plan, int problem, nep_assemble_fn fn, void* ctx);
+
+/* An assembler shipped with the library: the elementwise delay problem
+ * T(z) = -z I + A0 + A1 .* exp(-tau .* z), each entry of A1 with a delay of its own
+ * (n^2 distinct delays: no short split form).  Pass nep_assemble_elementwise_delay as
+ * the function and a nep_elementwise_delay as the context.
+ *   A0_dev, A1_dev  device complex128 row-major n x n;  tau_dev  device double n x n */
+typedef struct nep_elementwise_delay {
+  int n;
+  const void* A0_dev;
+  const void* A1_dev;
+  const double* tau_dev;
+} nep_elementwise_delay;
+int nep_assemble_elementwise_delay(void* ctx, int n, const void* z_dev, int nb, void* W_dev, long long mstride,
+                                   hipStream_t stream);
 
 /* nep_copy_sums -- copy the quadrature sums of disks [first, first + count) of the last
  * sweep to host buffers (any may be NULL): PfN, PfN2 as n x s, C0, C1 as n x L per disk,

@@ -84,6 +84,9 @@ struct nep_plan {
   nep_options opt{};
   int nprob = 0;
   std::vector<ProblemDev> pd;
+  // problems without split terms: T(z_j) written by the caller's assembler
+  std::vector<nep_assemble_fn> asm_fn;
+  std::vector<void*> asm_ctx;
   std::vector<nep_region> reg;
   // disks (global numbering)
   int nd = 0;
@@ -227,7 +230,11 @@ extern "C" nep_status nep_plan(const nep_problem* probs, int nprob, const nep_re
   for (int p = 0; p < nprob; ++p) {
     const nep_problem& q = probs[p];
     if (q.n < 1 || q.n > 4096) return bad("n must be 1..4096");
-    if (q.nterms < 1 || q.nterms > MAX_TERMS || !q.A_dev || !q.phi_kind) return bad("bad problem terms");
+    if (q.nterms == 0) {
+      if (o.precision != NEP_FP64) return bad("a problem without split terms needs precision NEP_FP64");
+    } else if (q.nterms < 0 || q.nterms > MAX_TERMS || !q.A_dev || !q.phi_kind) {
+      return bad("bad problem terms");
+    }
     for (int k = 0; k < q.nterms; ++k)
       if (q.phi_kind[k] < NEP_PHI_ONE || q.phi_kind[k] > NEP_PHI_EXP_NEG_TAU_Z) return bad("unknown phi kind");
     const nep_region& r = regs[p];
@@ -251,6 +258,8 @@ extern "C" nep_status nep_plan(const nep_problem* probs, int nprob, const nep_re
       d.param[k] = q.phi_param ? q.phi_param[k] : 0.0;
     }
     P->pd.push_back(d);
+    P->asm_fn.push_back(nullptr);
+    P->asm_ctx.push_back(nullptr);
     P->nmax = std::max(P->nmax, q.n);
   }
   // cover: cells x-major, circumscribed circles; nodes/weights of eq (2.3)
@@ -357,6 +366,7 @@ extern "C" nep_status nep_plan(const nep_problem* probs, int nprob, const nep_re
     PCHK(rf.alloc(sizeof(int) * MAX_TERMS));
     for (int p = 0; p < nprob; ++p) {
       int h[MAX_TERMS] = {0, 0, 0, 0};
+      if (P->pd[p].nterms == 0) continue;
       PCHK(launch_is_real(P->pd[p], rf.as<int>(), P->st));
       PCHK(hipMemcpy(h, rf.p, sizeof(int) * P->pd[p].nterms, hipMemcpyDeviceToHost));
       for (int k = 0; k < P->pd[p].nterms; ++k) P->pd[p].real[k] = h[k];
@@ -406,15 +416,31 @@ struct SweepCall {
   const void* const* V;
 };
 
+static nep_status check_assemblers(nep_plan_t* P) {
+  for (int p = 0; p < P->nprob; ++p)
+    if (P->pd[p].nterms == 0 && !P->asm_fn[p])
+      return fail(P, NEP_ERR_STATE, "problem %d has no split terms and no assembler", p);
+  return NEP_OK;
+}
+
 template <typename T>
-static nep_status factor_chunk(nep_plan_t* P, Workspace& w, const ProblemDev& pd, const double2* znode, int nb) {
+static nep_status factor_chunk(nep_plan_t* P, Workspace& w, int prob, const double2* znode, int nb) {
+  const ProblemDev& pd = P->pd[prob];
   const int n = pd.n;
   const int steps = (n + LU_NB - 1) / LU_NB;
   const long long mstride = (long long)n * n;
   const long long pstride = (long long)steps * perm_ints_per_step();
   const long long istride = (long long)steps * LU_NB * LU_NB;
   tmark(P, PH_ASM, true, w.st);
-  HIPCHK(P, launch_assemble<T>(pd, znode, w.W.as<c2<T>>(), mstride, nb, w.st));
+  if (pd.nterms > 0) {
+    HIPCHK(P, launch_assemble<T>(pd, znode, w.W.as<c2<T>>(), mstride, nb, w.st));
+  } else {
+    // caller-assembled problem (complex128 only; nep_plan rejects it in complex64)
+    if (sizeof(T) != 8 || !P->asm_fn[prob]) return fail(P, NEP_ERR_STATE, "problem %d has no assembler", prob);
+    const int rc = P->asm_fn[prob](P->asm_ctx[prob], n, znode, nb, w.W.p, mstride, w.st);
+    if (rc != 0) return fail(P, NEP_ERR_ARG, "assembler of problem %d returned %d", prob, rc);
+    HIPCHK(P, hipGetLastError());
+  }
   tmark(P, PH_ASM, false, w.st);
   HIPCHK(P, launch_fill_int(w.info.as<int>(), 0, nb, w.st));
   tmark(P, PH_LU, true, w.st);
@@ -477,7 +503,7 @@ static nep_status fallback_solves(nep_plan_t* P, int prob, const SweepCall& sc, 
     for (int i = 0; i < c; ++i)
       HIPCHK(P, hipMemcpyAsync(zb + i, tasks[c0 + i].z, sizeof(double2), hipMemcpyDeviceToDevice, st));
     HIPCHK(P, launch_rhs(F, s, V, L, n, xb, (long long)n * m, c, st));
-    e = factor_chunk<double>(P, P->w64, P->pd[prob], zb, c);
+    e = factor_chunk<double>(P, P->w64, prob, zb, c);
     if (e != NEP_OK) return e;
     e = solve_chunk<double>(P, P->w64, n, c, xb, m, false, nullptr);
     if (e != NEP_OK) return e;
@@ -499,7 +525,7 @@ static nep_status sweep_batch(nep_plan_t* P, Workspace& w, int prob, const doubl
   const double2* V = (L > 0) ? static_cast<const double2*>(sc.V[prob]) : nullptr;
   HIPCHK(P, launch_rhs(F, s, V, L, n, Xb, (long long)n * m, nb, w.st));
   if (P->opt.precision != NEP_FP32_REFINE) {
-    nep_status r = factor_chunk<double>(P, w, pd, zb, nb);
+    nep_status r = factor_chunk<double>(P, w, prob, zb, nb);
     if (r != NEP_OK) return r;
     HIPCHK(P, launch_mark_singular(w.info.as<int>(), nb, sing_out, w.st));
     tmark(P, PH_SOLVE, true, w.st);
@@ -507,7 +533,7 @@ static nep_status sweep_batch(nep_plan_t* P, Workspace& w, int prob, const doubl
     tmark(P, PH_SOLVE, false, w.st);
     return r;
   }
-  nep_status r = factor_chunk<float>(P, w, pd, zb, nb);
+  nep_status r = factor_chunk<float>(P, w, prob, zb, nb);
   if (r != NEP_OK) return r;
   tmark(P, PH_SOLVE, true, w.st);
   r = solve_chunk<float>(P, w, n, nb, Xb, m, false, nullptr);
@@ -726,6 +752,10 @@ extern "C" nep_status nep_indicator(nep_plan_t* P, const void* const* F_dev, con
   if (!F_dev || !ind || !flags) return fail(P, NEP_ERR_ARG, "F_dev, ind and flags are required");
   for (int p = 0; p < P->nprob; ++p)
     if (!F_dev[p] || (V_dev && P->opt.L > 0 && !V_dev[p])) return fail(P, NEP_ERR_ARG, "null probe block");
+  {
+    const nep_status ea = check_assemblers(P);
+    if (ea != NEP_OK) return ea;
+  }
   reset_stats(P);
   SweepCall sc;
   sc.disks.resize(P->nd);
@@ -967,7 +997,7 @@ static nep_status verify_refine(nep_plan_t* P, const int32_t* prob_ids, const do
       for (int it = 0; it <= iters; ++it) {
         const bool upd = it < iters;
         HIPCHK(P, hipMemcpyAsync(zn, z.data(), sizeof(double2) * nb, hipMemcpyHostToDevice, P->st));
-        e = factor_chunk<double>(P, P->w64, pd, zn, nb);
+        e = factor_chunk<double>(P, P->w64, prob, zn, nb);
         if (e != NEP_OK) return e;
         HIPCHK(P, launch_start(xv, n, n, est, nb, P->st));
         HIPCHK(P, launch_normalize(xv, n, n, est, 0, nb, P->st));
@@ -1024,7 +1054,7 @@ static nep_status check_candidates(nep_plan_t* P, const int32_t* prob_ids, const
   if (m < 0 || (m > 0 && (!prob_ids || !lam || !sigma_min || !accepted))) return fail(P, NEP_ERR_ARG, "null argument");
   for (int i = 0; i < m; ++i)
     if (prob_ids[i] < 0 || prob_ids[i] >= P->nprob) return fail(P, NEP_ERR_ARG, "problem id out of range");
-  return NEP_OK;
+  return check_assemblers(P);
 }
 
 extern "C" nep_status nep_verify(nep_plan_t* P, const int32_t* prob_ids, const void* lam, int m, double* sigma_min,
@@ -1042,11 +1072,43 @@ extern "C" nep_status nep_refine(nep_plan_t* P, const int32_t* prob_ids, void* l
   nep_status e = check_candidates(P, prob_ids, lam, m, sigma_min, accepted);
   if (e != NEP_OK || m == 0) return e;
   if (iters < 0 || iters > NEP_REFINE_MAX_ITERS) return fail(P, NEP_ERR_ARG, "iters out of range");
+  if (iters > 0)
+    for (int i = 0; i < m; ++i)
+      if (P->pd[prob_ids[i]].nterms == 0) return fail(P, NEP_ERR_ARG, "refinement needs the split form (problem %d)",
+                                                     prob_ids[i]);
   if (vec)
     for (int i = 0; i < m; ++i)
       if (ldv < P->pd[prob_ids[i]].n) return fail(P, NEP_ERR_ARG, "ldv smaller than a candidate's order");
   double2* l = static_cast<double2*>(lam);
   return verify_refine(P, prob_ids, l, l, m, iters, sigma_min, accepted, static_cast<double2*>(vec), ldv);
+}
+
+// ---------------------------------------------------------------------------- assemblers
+extern "C" nep_status nep_set_assembler(nep_plan_t* P, int problem, nep_assemble_fn fn, void* ctx) {
+  if (!P) return NEP_ERR_ARG;
+  if (problem < 0 || problem >= P->nprob) return fail(P, NEP_ERR_ARG, "problem out of range");
+  if (P->pd[problem].nterms != 0) return fail(P, NEP_ERR_ARG, "problem %d has split terms", problem);
+  if (!fn) return fail(P, NEP_ERR_ARG, "null assembler");
+  P->asm_fn[problem] = fn;
+  P->asm_ctx[problem] = ctx;
+  // a captured sweep recorded the previous assembler's launches
+  if (P->gexec) { hipGraphExecDestroy(P->gexec); P->gexec = nullptr; }
+  if (P->graph) { hipGraphDestroy(P->graph); P->graph = nullptr; }
+  P->graph_F.clear();
+  P->graph_V.clear();
+  return NEP_OK;
+}
+
+extern "C" int nep_assemble_elementwise_delay(void* ctx, int n, const void* z_dev, int nb, void* W_dev,
+                                              long long mstride, hipStream_t stream) {
+  const nep_elementwise_delay* c = static_cast<const nep_elementwise_delay*>(ctx);
+  if (!c || c->n != n || !c->A0_dev || !c->A1_dev || !c->tau_dev || !z_dev || !W_dev || nb < 0 ||
+      mstride < (long long)n * n)
+    return 1;
+  if (nb == 0) return 0;
+  return launch_elementwise_delay(static_cast<const double2*>(c->A0_dev), static_cast<const double2*>(c->A1_dev),
+                                  c->tau_dev, n, static_cast<const double2*>(z_dev), nb,
+                                  static_cast<double2*>(W_dev), mstride, stream) == hipSuccess ? 0 : 2;
 }
 
 // ---------------------------------------------------------------------------- accessors

@@ -453,6 +453,38 @@ hipError_t launch_rayleigh_terms(const ProblemDev& pd, const double2* U, const d
   return hipGetLastError();
 }
 
+// W[b] = -z_b I + A0 + A1 .* exp(-tau .* z_b), one thread per entry (rows coalesced);
+// grid (ceil(n^2 / 256), nb)
+__global__ __launch_bounds__(256) void elementwise_delay_kernel(const double2* __restrict__ A0,
+                                                                const double2* __restrict__ A1,
+                                                                const double* __restrict__ tau, int n,
+                                                                const double2* __restrict__ z, double2* __restrict__ W,
+                                                                long long mstride) {
+  const long long nn = (long long)n * n;
+  const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+  const int b = blockIdx.y;
+  if (e >= nn) return;
+  const double2 zb = z[b];
+  const double t = tau[e];
+  const double m = exp(-t * zb.x);
+  double sn, cs;
+  sincos(-t * zb.y, &sn, &cs);
+  const double2 a0 = A0[e], a1 = A1[e];
+  double2 v = cmk<double>(a0.x + m * (a1.x * cs - a1.y * sn), a0.y + m * (a1.x * sn + a1.y * cs));
+  const int i = (int)(e / n), j = (int)(e - (long long)i * n);
+  if (i == j) { v.x -= zb.x; v.y -= zb.y; }
+  W[(long long)b * mstride + e] = v;
+}
+
+hipError_t launch_elementwise_delay(const double2* A0, const double2* A1, const double* tau, int n, const double2* z,
+                                    int nb, double2* W, long long mstride, hipStream_t st) {
+  if (n < 1 || nb < 1 || nb > 65535) return hipErrorInvalidValue;
+  const long long nn = (long long)n * n;
+  elementwise_delay_kernel<<<dim3((unsigned)((nn + 255) / 256), (unsigned)nb), 256, 0, st>>>(A0, A1, tau, n, z, W,
+                                                                                              mstride);
+  return hipGetLastError();
+}
+
 // a[i] = v for i < n (a fill kernel instead of a memset node, so graph captures replay it)
 __global__ void fill_int_kernel(int* a, int v, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;

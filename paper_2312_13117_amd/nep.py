@@ -24,6 +24,10 @@ class nep_problem(C.Structure):
                 ("phi_kind", C.POINTER(C.c_int)), ("phi_param", C.POINTER(C.c_double))]
 
 
+class nep_elementwise_delay(C.Structure):
+    _fields_ = [("n", C.c_int), ("A0_dev", C.c_void_p), ("A1_dev", C.c_void_p), ("tau_dev", C.c_void_p)]
+
+
 class nep_region(C.Structure):
     _fields_ = [("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
                 ("nx", C.c_int), ("ny", C.c_int)]
@@ -64,6 +68,8 @@ def lib():
     L.nep_verify.argtypes = [vp, ip, vp, C.c_int, dp, u8p]
     L.nep_refine.argtypes = [vp, ip, vp, C.c_int, C.c_int, dp, u8p, vp, C.c_int]
     L.nep_copy_sums.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp, vp]
+    L.nep_set_assembler.argtypes = [vp, C.c_int, vp, vp]
+    L.nep_assemble_elementwise_delay.argtypes = [vp, C.c_int, vp, C.c_int, vp, C.c_longlong, vp]
     L.nep_dedup.argtypes = [vp, dp, C.c_int, C.c_double, u8p]
     L.nep_total_disks.argtypes = [vp]
     L.nep_disk_offset.argtypes = [vp, C.c_int]
@@ -82,7 +88,8 @@ def lib():
     L.nep_mlp_grad.argtypes = [fp, fp, fp, fp, C.c_int, fp, C.POINTER(C.c_float), fp, vp]
     L.nep_mlp_adam.argtypes = [fp, fp, fp, fp, C.c_int, C.c_float, C.c_float, C.c_float, C.c_float, vp]
     L.nep_mlp_features.argtypes = [fp, C.c_int, C.c_int, fp, C.c_int, fp, fp, fp, vp]
-    for f in ("nep_plan", "nep_indicator", "nep_beyn", "nep_verify", "nep_refine", "nep_copy_sums", "nep_dedup",
+    for f in ("nep_plan", "nep_indicator", "nep_beyn", "nep_verify", "nep_refine", "nep_set_assembler",
+              "nep_assemble_elementwise_delay", "nep_copy_sums", "nep_dedup",
               "nep_total_disks", "nep_disk_offset", "nep_get_stats", "nep_mlp_param_count", "nep_mlp_forward",
               "nep_mlp_grad", "nep_mlp_adam", "nep_mlp_features"):
         getattr(L, f).restype = C.c_int
@@ -120,13 +127,28 @@ def _dev_complex(x, torch):
     return t.contiguous()
 
 
+def _is_assembled(pr) -> bool:
+    """An elementwise delay problem (no split form): assembled by the library's
+    nep_assemble_elementwise_delay."""
+    return hasattr(pr, "tau") and hasattr(pr, "A0")
+
+
+def _dev_real(x, torch):
+    if isinstance(x, torch.Tensor):
+        return x.to(device="cuda", dtype=torch.float64).contiguous()
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).to("cuda").contiguous()
+
+
 def upload_problem(pr):
-    """A copy of a gen.Problem whose coefficients are device tensors (uploaded once and
-    shared by every plan entry that refers to it)."""
+    """A copy of a gen.Problem (or gen.ElementwiseDelay) whose matrices are device
+    tensors (uploaded once and shared by every plan entry that refers to it)."""
     import copy
     import torch
     q = copy.copy(pr)
-    q.coeffs = [_dev_complex(A, torch) for A in pr.coeffs]
+    if _is_assembled(pr):
+        q.A0, q.A1, q.tau = _dev_complex(pr.A0, torch), _dev_complex(pr.A1, torch), _dev_real(pr.tau, torch)
+    else:
+        q.coeffs = [_dev_complex(A, torch) for A in pr.coeffs]
     return q
 
 
@@ -149,7 +171,15 @@ def nep_plan(problems, regions, opts, stream=None) -> Plan:
     L = lib()
     keep = []
     cp = (nep_problem * len(problems))()
+    assembled = []
     for i, pr in enumerate(problems):
+        if _is_assembled(pr):
+            t0, t1, tt = _dev_complex(pr.A0, torch), _dev_complex(pr.A1, torch), _dev_real(pr.tau, torch)
+            ctx = nep_elementwise_delay(pr.n, t0.data_ptr(), t1.data_ptr(), tt.data_ptr())
+            keep += [t0, t1, tt, ctx]
+            assembled.append((i, ctx))
+            cp[i] = nep_problem(pr.n, 0, None, None, None)
+            continue
         devs = []
         for A in pr.coeffs:
             t = _dev_complex(A, torch)
@@ -177,6 +207,12 @@ def nep_plan(problems, regions, opts, stream=None) -> Plan:
         stream = torch.cuda.current_stream().cuda_stream
     h = C.c_void_p()
     _check(L.nep_plan(cp, len(problems), cr, C.byref(co), C.c_void_p(stream), C.byref(h)), None)
+    for i, ctx in assembled:
+        st = L.nep_set_assembler(h, i, C.cast(L.nep_assemble_elementwise_delay, C.c_void_p), C.byref(ctx))
+        if st < 0:
+            msg = L.nep_last_error(h).decode()
+            L.nep_destroy(h)
+            raise NepError(st, msg)
     nd = L.nep_total_disks(h)
     return Plan(h, len(problems), [p.n for p in problems], opts.N, opts.s, opts.L, nd, keep)
 

@@ -52,6 +52,11 @@ def test_plan_rejects_bad_options():
     assert L.nep_plan(C.byref(prob), 1, C.byref(bad), C.byref(co), None, C.byref(h)) == -1
     prob_big = N.nep_problem(5000, 1, ptrs, kinds, None)
     assert L.nep_plan(C.byref(prob_big), 1, C.byref(reg), C.byref(co), None, C.byref(h)) == -1
+    # a problem without split terms (assembled by a caller function) needs complex128
+    co_mixed = N.nep_options(32, 1, 8, 0.1, 1e-6, 1e-6, 1, 3, 0, 0, 0, 0)
+    assert L.nep_plan(C.byref(N.nep_problem(16, 0, None, None, None)), 1, C.byref(reg), C.byref(co_mixed), None,
+                      C.byref(h)) == -1
+    assert "NEP_FP64" in L.nep_last_error(None).decode()
     kinds_bad = (C.c_int * 1)(9)
     assert L.nep_plan(C.byref(N.nep_problem(16, 1, ptrs, kinds_bad, None)), 1, C.byref(reg), C.byref(co), None,
                       C.byref(h)) == -1
@@ -62,6 +67,11 @@ def test_null_plan_calls():
     assert L.nep_indicator(None, None, None, None, None, None) == -1
     assert L.nep_verify(None, None, None, 0, None, None) == -1
     assert L.nep_refine(None, None, None, 0, 2, None, None, None, 0) == -1
+    assert L.nep_set_assembler(None, 0, None, None) == -1
+    # the shipped assembler rejects a missing context or a wrong order without launching
+    assert L.nep_assemble_elementwise_delay(None, 4, None, 1, None, 16, None) != 0
+    ctx = N.nep_elementwise_delay(4, None, None, None)
+    assert L.nep_assemble_elementwise_delay(C.byref(ctx), 4, None, 1, None, 16, None) != 0
     assert L.nep_total_disks(None) == 0
     L.nep_destroy(None)
     for s in (0, 1, 2, 3, -1, -2, -3, -4, -5, -6, 99):
