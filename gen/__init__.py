@@ -63,6 +63,18 @@ class ElementwiseDelay:
 
 
 @dataclass
+class CircleDoubleLayer:
+    """Scattering poles of the sound-soft unit disk: T(k) = (I + K_n(k)) / 2 with K the
+    double-layer operator (kernel 2 dPhi/dnu(y), Phi = (i/4) H0(k|x-y|)) on the unit
+    circle, discretised by the Nystrom rule with the logarithmic splitting of Kress on
+    n equispaced points (n even).  No split form: assembled by a device assembler."""
+    n: int
+
+    def __post_init__(self):
+        assert self.n >= 4 and self.n % 2 == 0
+
+
+@dataclass
 class Region:
     """Rectangle [x0,x1] x [y0,y1] split into nx x ny equal cells."""
     x0: float

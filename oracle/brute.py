@@ -82,3 +82,33 @@ def trapezoid_pole_half(delta: complex, N: int) -> complex:
         return 1.0 / (1.0 + delta ** h)
     q = 1.0 / delta
     return q ** h / (1.0 + q ** h)
+
+
+def hankel_zeros(m: int, x0: float, x1: float, y0: float, y1: float, grid: int = 24) -> np.ndarray:
+    """Zeros of H_m^(1) in the rectangle: Newton (H_m' = (H_{m-1} - H_{m+1}) / 2) from a
+    grid of starts, duplicates merged; the count is checked against the argument
+    principle (1/2 pi i) oint H_m'/H_m on the rectangle's boundary."""
+    h = lambda z: ssp.hankel1(m, z)
+    dh = lambda z: 0.5 * (ssp.hankel1(m - 1, z) - ssp.hankel1(m + 1, z))
+    found: List[complex] = []
+    for a in np.linspace(x0, x1, grid):
+        for b in np.linspace(y0, y1, grid):
+            z = complex(a, b)
+            for _ in range(60):
+                step = h(z) / dh(z)
+                z -= step
+                if not np.isfinite(z) or abs(step) < 1e-15 * max(1.0, abs(z)):
+                    break
+            if np.isfinite(z) and x0 < z.real < x1 and y0 < z.imag < y1 and abs(h(z)) < 1e-10:
+                if all(abs(z - w) > 1e-8 for w in found):
+                    found.append(z)
+    # argument principle on the boundary (a fine trapezoid rule per side)
+    pts = np.concatenate([np.linspace(complex(x0, y0), complex(x1, y0), 4000, endpoint=False),
+                          np.linspace(complex(x1, y0), complex(x1, y1), 4000, endpoint=False),
+                          np.linspace(complex(x1, y1), complex(x0, y1), 4000, endpoint=False),
+                          np.linspace(complex(x0, y1), complex(x0, y0), 4000, endpoint=False)])
+    nxt = np.roll(pts, -1)
+    mid = 0.5 * (pts + nxt)
+    count = np.sum(dh(mid) / h(mid) * (nxt - pts)) / (2j * np.pi)
+    assert abs(count - round(count.real)) < 1e-3 and round(count.real) == len(found), (m, count, found)
+    return np.asarray(found, dtype=np.complex128)

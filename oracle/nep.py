@@ -16,7 +16,7 @@ import numpy as np
 import scipy.linalg as sla
 
 from gen import (PHI_ONE, PHI_Z, PHI_Z2, PHI_NEG_Z, PHI_EXP_NEG_TAU_Z, Problem,
-                 Region, Options, ElementwiseDelay)
+                 Region, Options, ElementwiseDelay, CircleDoubleLayer)
 
 # ---------------------------------------------------------------- T(z)
 
@@ -51,6 +51,33 @@ def dphi(kind: int, param: float, z: complex) -> complex:
     raise ValueError(f"unknown phi kind {kind}")
 
 
+def circle_double_layer(n: int, k: complex) -> np.ndarray:
+    """T(k) = (I + K_n(k)) / 2 on n equispaced points t_j = 2 pi j / n of the unit
+    circle.  The kernel of K is 2 dPhi(x(t), y(s))/dnu(y) = -(i k r / 4) H1(k r),
+    r = |x - y| = 2 |sin((t - s)/2)|; it is split as L1 ln(4 sin^2((t - s)/2)) + L2
+    with L1 = (k r / (4 pi)) J1(k r) and L2 the rest (L2 = -1/(2 pi) on the diagonal),
+    and integrated by Kress's rule: the logarithmic part with the weights
+    R_j(t) = -(2 pi / m) sum_{l=1}^{m-1} cos(l (t - t_j)) / l - (pi / m^2) cos(m (t - t_j))
+    (m = n / 2), the smooth part by the trapezoid rule (pi / m) sum_j."""
+    import scipy.special as ssp
+    m = n // 2
+    t = 2.0 * np.pi * np.arange(n) / n
+    d = t[:, None] - t[None, :]
+    l = np.arange(1, m)
+    R = -(2.0 * np.pi / m) * (np.cos(d[..., None] * l) / l).sum(axis=-1) - (np.pi / m ** 2) * np.cos(m * d)
+    r = 2.0 * np.abs(np.sin(d / 2.0))
+    off = ~np.eye(n, dtype=bool)
+    z = complex(k) * r
+    K = np.zeros((n, n), dtype=np.complex128)
+    K[off] = -(1j * z[off] / 4.0) * ssp.hankel1(1, z[off])
+    L1 = np.zeros((n, n), dtype=np.complex128)
+    L1[off] = (z[off] / (4.0 * np.pi)) * ssp.jv(1, z[off])
+    L2 = np.full((n, n), -1.0 / (2.0 * np.pi), dtype=np.complex128)
+    L2[off] = K[off] - L1[off] * np.log(4.0 * np.sin(d[off] / 2.0) ** 2)
+    Kn = R * L1 + (np.pi / m) * L2
+    return 0.5 * (np.eye(n) + Kn)
+
+
 def assemble(prob: Problem, z: complex) -> np.ndarray:
     """T(z) = sum_k phi_k(z) A_k: the matrix function of eq (1.1), in the split form of
     the appendix routine that generates T(z); an ElementwiseDelay problem is written out
@@ -59,6 +86,8 @@ def assemble(prob: Problem, z: complex) -> np.ndarray:
         T = prob.A0 + prob.A1 * np.exp(-prob.tau * complex(z))
         T[np.diag_indices(prob.n)] -= complex(z)
         return T
+    if isinstance(prob, CircleDoubleLayer):
+        return circle_double_layer(prob.n, z)
     T = np.zeros((prob.n, prob.n), dtype=np.complex128)
     for A, kind, par in zip(prob.coeffs, prob.phi_kind, prob.phi_param):
         f = phi(kind, par, z)
