@@ -18,6 +18,8 @@ Prints ONE JSON line.
   count (the workload as configured saturates every flagged disk).
 - `generic_assembly` = the whole step on a problem without a short split form (an
   elementwise delay, n = 1024, written at every node by an assembler callback).
+- `scattering` = the paper's scattering-pole experiment (sound-soft unit disk, 100
+  squares) by pmCIMb and pmCIMa, poles against the Hankel-function zeros.
 - `pmcima` = pmCIMa (indicator levels down to tol_eps = 1e-6, merge, Step 2 vectors,
   then refinement) on the n = 64 workload: time, node solves and accuracy.
 - `eigenpairs_complete` = the complete spectrum of the dense workload (2048
@@ -245,6 +247,35 @@ def generic_run(steps: int):
             "phase_ms": phase_dict(st)}
 
 
+def scattering_run():
+    """Scattering poles of the sound-soft unit disk (the paper's second experiment, with
+    a self-written discretisation: the double-layer Nystrom matrix on 64 points of the
+    circle, assembled on the device): pmCIMb and pmCIMa over [0.2, 3.2] x [-3.2, -0.2]
+    split into 100 squares, poles against the stored Hankel-function zeros."""
+    import gen
+    import torch
+    from paper_2312_13117_amd import nep as N, pmcima
+    a = np.loadtxt(os.path.join(ROOT, "tests", "golden", "hankel_zeros_scattering.txt"))
+    ref = a[:, 1] + 1j * a[:, 2]
+    prob = gen.CircleDoubleLayer(64)
+    reg = gen.Region(0.2, 3.2, -3.2, -0.2, 10, 10)
+    w = gen.Workload("scattering_unit_disk_10x10", [prob], [reg], gen.Options(N=32, s=1, L=4),
+                     [gen.probes(11, 64, 1)], [gen.probes(12, 64, 4)])
+    r = Runner(w)
+    T, o = timed(r, 3, 1)
+    r.close()
+    e_b, one_b = _match_err(o["eigs"], ref)
+    pmcima.pmcima(prob, reg, w.F[0])
+    torch.cuda.synchronize()
+    pa = pmcima.pmcima(prob, reg, w.F[0])
+    e_a, _ = _match_err(pa.eigs, ref)
+    return {"workload": w.name, "hankel_zeros": int(len(ref)),
+            "pmcimb": {"ms_per_step": T * 1e3, "poles": int(len(o["eigs"])), "max_rel_err": e_b,
+                       "one_to_one": one_b, "node_solves": int(o["stats"]["node_solves"])},
+            "pmcima": {"seconds": pa.seconds, "poles": int(len(pa.eigs)), "max_rel_err": e_a,
+                       "levels": pa.levels, "node_solves": int(pa.node_solves)}}
+
+
 def complete_spectrum(pivot: int, reps: int = 1):
     """The saturation remedy on the dense workload (cells split until no flagged disk
     saturates, candidates refined and verified): eigenpairs/s of the complete spectrum
@@ -411,6 +442,7 @@ def main():
     if args.workload == "dense" and not args.no_eigen:
         out["pmcima"] = pmcima_run()
         out["generic_assembly"] = generic_run(max(2, min(args.steps, 3)))
+        out["scattering"] = scattering_run()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_disks)
     print(json.dumps(out))

@@ -303,6 +303,16 @@ typedef struct nep_elementwise_delay {
 int nep_assemble_elementwise_delay(void* ctx, int n, const void* z_dev, int nb, void* W_dev, long long mstride,
                                    hipStream_t stream);
 
+/* An assembler shipped with the library: the scattering poles of the sound-soft unit
+ * disk (Section 4.2).  T(k) = (I + K_n(k)) / 2 with K the double-layer operator
+ * (kernel 2 dPhi/dnu(y), Phi = (i/4) H0(k |x - y|)) on n equispaced points of the
+ * unit circle (n even), discretised by Kress's Nystrom rule with the logarithmic
+ * splitting; J1 and Y1 from their power series (accurate for |k| up to ~10).  The
+ * context is unused (NULL).  Its singular points in the lower half-plane are the
+ * zeros of the Hankel functions H_m, each double (modes m and -m).              */
+int nep_assemble_circle_double_layer(void* ctx, int n, const void* z_dev, int nb, void* W_dev, long long mstride,
+                                     hipStream_t stream);
+
 /* nep_copy_sums -- copy the quadrature sums of disks [first, first + count) of the last
  * sweep to host buffers (any may be NULL): PfN, PfN2 as n x s, C0, C1 as n x L per disk,
  * complex128 row-major, disks back to back.  All listed disks must share n.        */

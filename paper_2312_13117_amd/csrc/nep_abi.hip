@@ -1111,6 +1111,15 @@ extern "C" int nep_assemble_elementwise_delay(void* ctx, int n, const void* z_de
                                   static_cast<double2*>(W_dev), mstride, stream) == hipSuccess ? 0 : 2;
 }
 
+extern "C" int nep_assemble_circle_double_layer(void* ctx, int n, const void* z_dev, int nb, void* W_dev,
+                                                long long mstride, hipStream_t stream) {
+  (void)ctx;
+  if (n < 4 || (n & 1) || !z_dev || !W_dev || nb < 0 || mstride < (long long)n * n) return 1;
+  if (nb == 0) return 0;
+  return launch_circle_double_layer(n, static_cast<const double2*>(z_dev), nb, static_cast<double2*>(W_dev), mstride,
+                                    stream) == hipSuccess ? 0 : 2;
+}
+
 // ---------------------------------------------------------------------------- accessors
 extern "C" nep_status nep_copy_sums(nep_plan_t* P, int first, int count, void* PfN, void* PfN2, void* C0,
                                    void* C1) {

@@ -49,6 +49,7 @@ hipError_t launch_mark_singular(const int* info, int nb, int* sing, hipStream_t 
 hipError_t launch_or_flags(const int* a, const int* c, int nb, int* out, hipStream_t st);
 hipError_t launch_elementwise_delay(const double2* A0, const double2* A1, const double* tau, int n, const double2* z,
                                     int nb, double2* W, long long mstride, hipStream_t st);
+hipError_t launch_circle_double_layer(int P, const double2* k, int nb, double2* W, long long mstride, hipStream_t st);
 hipError_t launch_rayleigh_terms(const ProblemDev& pd, const double2* U, const double2* V, long long xstride,
                                  int nb, double2* out, hipStream_t st);
 

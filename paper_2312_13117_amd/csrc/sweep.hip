@@ -485,6 +485,67 @@ hipError_t launch_elementwise_delay(const double2* A0, const double2* A1, const 
   return hipGetLastError();
 }
 
+// Scattering poles of the sound-soft unit disk: W[b] = (I + K_n(k_b)) / 2 on P
+// equispaced points t_j = 2 pi j / P of the unit circle, K the double-layer operator
+// (kernel 2 dPhi/dnu(y) = -(i k r / 4) H1(k r), r = 2 |sin((t_i - t_j)/2)|), split as
+// L1 ln(4 sin^2) + L2 with L1 = (k r / 4 pi) J1(k r) and integrated by Kress's rule
+// (log weights R_ij, trapezoid pi / (P/2) for L2).  J1 and the logarithm-free part of
+// Y1 come from their power series in w = k r / 2 (|w| <= |k|: all terms decay after
+// q ~ |w|, at most 60 of them); L2 = -1/(2 pi) on the diagonal.  One thread per entry,
+// grid (ceil(P^2 / 256), nb).
+__global__ __launch_bounds__(256) void circle_double_layer_kernel(int P, const double2* __restrict__ kz,
+                                                                  double2* __restrict__ W, long long mstride) {
+  constexpr double PI = 3.141592653589793238, EULER = 0.5772156649015328606;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  const int b = blockIdx.y;
+  if (e >= P * P) return;
+  const int i = e / P, j = e - i * P;
+  const int m = P / 2;
+  const double2 k = kz[b];
+  const double d = 2.0 * PI * (double)(i - j) / (double)P;
+  double R = 0.0;
+  for (int l = 1; l < m; ++l) R += cos(l * d) / l;
+  R = -(2.0 * PI / m) * R - (PI / ((double)m * m)) * cos(m * d);
+  double2 L1 = cmk<double>(0.0, 0.0), L2 = cmk<double>(-1.0 / (2.0 * PI), 0.0);
+  if (i != j) {
+    const double r = 2.0 * fabs(sin(0.5 * d));
+    const double2 z = cmk<double>(k.x * r, k.y * r);
+    const double2 w = cmk<double>(0.5 * z.x, 0.5 * z.y);
+    const double2 mw2 = cmk<double>(-(w.x * w.x - w.y * w.y), -2.0 * w.x * w.y);   // -w^2
+    const double aw2 = w.x * w.x + w.y * w.y;
+    double2 term = w;                                  // (-1)^q w^(2q+1) / (q! (q+1)!)
+    double pa = -EULER, pb = 1.0 - EULER;              // psi(q+1), psi(q+2)
+    double2 J1 = term, SY = cscale<double>(term, pa + pb);
+    for (int q = 1; q < 60; ++q) {
+      term = cscale<double>(cmul<double>(term, mw2), 1.0 / ((double)q * (q + 1)));
+      pa += 1.0 / q;
+      pb += 1.0 / (q + 1);
+      J1 = cadd<double>(J1, term);
+      SY = cfma<double>(SY, term, cmk<double>(pa + pb, 0.0));
+      const double tm = sqrt(cabs2<double>(term)) * (pa + pb + 1.0);
+      if ((double)q * (q + 1) > aw2 && tm < 1e-18 * (sqrt(cabs2<double>(J1)) + sqrt(cabs2<double>(SY))))
+        break;
+    }
+    const double2 zJ1 = cmul<double>(z, J1);
+    L1 = cscale<double>(zJ1, 1.0 / (4.0 * PI));
+    const double2 lk = cmk<double>(log(0.5 * sqrt(k.x * k.x + k.y * k.y)), atan2(k.y, k.x));   // ln(k / 2)
+    // L2 = -(i/4) z J1 - 1/(2 pi) + z J1 ln(k/2) / (2 pi) - z SY / (4 pi)
+    const double2 a = cmul<double>(zJ1, lk), c = cmul<double>(z, SY);
+    L2 = cmk<double>(0.25 * zJ1.y - 1.0 / (2.0 * PI) + a.x / (2.0 * PI) - c.x / (4.0 * PI),
+                     -0.25 * zJ1.x + a.y / (2.0 * PI) - c.y / (4.0 * PI));
+  }
+  const double tw = PI / m;
+  double2 v = cmk<double>(0.5 * (R * L1.x + tw * L2.x), 0.5 * (R * L1.y + tw * L2.y));
+  if (i == j) v.x += 0.5;
+  W[(long long)b * mstride + e] = v;
+}
+
+hipError_t launch_circle_double_layer(int P, const double2* k, int nb, double2* W, long long mstride, hipStream_t st) {
+  if (P < 4 || (P & 1) || P > 4096 || nb < 1 || nb > 65535) return hipErrorInvalidValue;
+  circle_double_layer_kernel<<<dim3((unsigned)((P * P + 255) / 256), (unsigned)nb), 256, 0, st>>>(P, k, W, mstride);
+  return hipGetLastError();
+}
+
 // a[i] = v for i < n (a fill kernel instead of a memset node, so graph captures replay it)
 __global__ void fill_int_kernel(int* a, int v, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;

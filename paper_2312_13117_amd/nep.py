@@ -70,6 +70,7 @@ def lib():
     L.nep_copy_sums.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp, vp]
     L.nep_set_assembler.argtypes = [vp, C.c_int, vp, vp]
     L.nep_assemble_elementwise_delay.argtypes = [vp, C.c_int, vp, C.c_int, vp, C.c_longlong, vp]
+    L.nep_assemble_circle_double_layer.argtypes = [vp, C.c_int, vp, C.c_int, vp, C.c_longlong, vp]
     L.nep_dedup.argtypes = [vp, dp, C.c_int, C.c_double, u8p]
     L.nep_total_disks.argtypes = [vp]
     L.nep_disk_offset.argtypes = [vp, C.c_int]
@@ -89,7 +90,7 @@ def lib():
     L.nep_mlp_adam.argtypes = [fp, fp, fp, fp, C.c_int, C.c_float, C.c_float, C.c_float, C.c_float, vp]
     L.nep_mlp_features.argtypes = [fp, C.c_int, C.c_int, fp, C.c_int, fp, fp, fp, vp]
     for f in ("nep_plan", "nep_indicator", "nep_beyn", "nep_verify", "nep_refine", "nep_set_assembler",
-              "nep_assemble_elementwise_delay", "nep_copy_sums", "nep_dedup",
+              "nep_assemble_elementwise_delay", "nep_assemble_circle_double_layer", "nep_copy_sums", "nep_dedup",
               "nep_total_disks", "nep_disk_offset", "nep_get_stats", "nep_mlp_param_count", "nep_mlp_forward",
               "nep_mlp_grad", "nep_mlp_adam", "nep_mlp_features"):
         getattr(L, f).restype = C.c_int
@@ -133,6 +134,11 @@ def _is_assembled(pr) -> bool:
     return hasattr(pr, "tau") and hasattr(pr, "A0")
 
 
+def _is_circle(pr) -> bool:
+    """The unit disk's double-layer problem: assembled by nep_assemble_circle_double_layer."""
+    return type(pr).__name__ == "CircleDoubleLayer"
+
+
 def _dev_real(x, torch):
     if isinstance(x, torch.Tensor):
         return x.to(device="cuda", dtype=torch.float64).contiguous()
@@ -145,6 +151,8 @@ def upload_problem(pr):
     import copy
     import torch
     q = copy.copy(pr)
+    if _is_circle(pr):
+        return q
     if _is_assembled(pr):
         q.A0, q.A1, q.tau = _dev_complex(pr.A0, torch), _dev_complex(pr.A1, torch), _dev_real(pr.tau, torch)
     else:
@@ -173,6 +181,10 @@ def nep_plan(problems, regions, opts, stream=None) -> Plan:
     cp = (nep_problem * len(problems))()
     assembled = []
     for i, pr in enumerate(problems):
+        if _is_circle(pr):
+            assembled.append((i, None))
+            cp[i] = nep_problem(pr.n, 0, None, None, None)
+            continue
         if _is_assembled(pr):
             t0, t1, tt = _dev_complex(pr.A0, torch), _dev_complex(pr.A1, torch), _dev_real(pr.tau, torch)
             ctx = nep_elementwise_delay(pr.n, t0.data_ptr(), t1.data_ptr(), tt.data_ptr())
@@ -208,7 +220,10 @@ def nep_plan(problems, regions, opts, stream=None) -> Plan:
     h = C.c_void_p()
     _check(L.nep_plan(cp, len(problems), cr, C.byref(co), C.c_void_p(stream), C.byref(h)), None)
     for i, ctx in assembled:
-        st = L.nep_set_assembler(h, i, C.cast(L.nep_assemble_elementwise_delay, C.c_void_p), C.byref(ctx))
+        if ctx is None:
+            st = L.nep_set_assembler(h, i, C.cast(L.nep_assemble_circle_double_layer, C.c_void_p), None)
+        else:
+            st = L.nep_set_assembler(h, i, C.cast(L.nep_assemble_elementwise_delay, C.c_void_p), C.byref(ctx))
         if st < 0:
             msg = L.nep_last_error(h).decode()
             L.nep_destroy(h)

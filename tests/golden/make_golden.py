@@ -7,6 +7,10 @@ from the companion linearisation (a library generalized eigensolver).
 small_qep_n64_eigs.txt: the 128 eigenvalues of the n = 64 QEP (K = A + A^T, C = 0.1 B,
 M = I, seeds 0, 1) from its companion pencil, sorted by (Re, Im).
 
+hankel_zeros_scattering.txt: the zeros of the Hankel functions H_m^(1), m = 0..10, in
+[0.2, 3.2] x [-3.2, -0.2] (the scattering poles of the sound-soft unit disk in the
+region of the paper's scattering experiment), by Newton and argument-principle count.
+
 dense_qep_n1024_eigs.txt (with --dense; minutes of CPU): the 2048 eigenvalues of the
 dense n = 1024 QEP (K = A + A^T, C = 0.1 B, M = I + 0.1 G G^T, seeds 0, 1, 2) from
 its companion pencil, sorted by (Re, Im).
@@ -48,11 +52,22 @@ def small():
             f.write(f"{v.real:.17e} {v.imag:.17e}\n")
 
 
+def hankel():
+    zs = np.concatenate([brute.hankel_zeros(m, 0.2, 3.2, -3.2, -0.2) for m in range(0, 11)])
+    ms = np.concatenate([[m] * len(brute.hankel_zeros(m, 0.2, 3.2, -3.2, -0.2)) for m in range(0, 11)])
+    with open(os.path.join(HERE, "hankel_zeros_scattering.txt"), "w") as f:
+        f.write("# Zeros of H_m^(1) in [0.2, 3.2] x [-3.2, -0.2], m = 0..10 (each a double scattering pole of\n")
+        f.write("# the sound-soft unit disk); columns: m Re Im.  Written by tests/golden/make_golden.py (oracle only).\n")
+        for m, z in zip(ms, zs):
+            f.write(f"{int(m)} {z.real:.17e} {z.imag:.17e}\n")
+
+
 def main():
     if "--dense" in sys.argv:
         dense()
         return
     small()
+    hankel()
     p = gen.paper_demo_problem()
     ev = brute.companion_eigs(p)
     ev = np.sort(ev.real[np.argsort(ev.real)])

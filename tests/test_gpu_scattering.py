@@ -1,0 +1,81 @@
+"""Scattering poles of the sound-soft unit disk (Section 4.2) on the GPU: the double-layer
+Nystrom matrix written at every node by nep_assemble_circle_double_layer, against the
+oracle (library Bessel functions): quadrature sums, then pmCIMb and pmCIMa over the
+paper's region [0.2, 3.2] x [-3.2, -0.2] split into 100 squares, whose poles must be
+the zeros of the Hankel functions (stored by the oracle under tests/golden/)."""
+import os
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from test_gpu_parity import check_sums, say
+
+pytestmark = pytest.mark.gpu
+
+REGION = gen.Region(0.2, 3.2, -3.2, -0.2, 10, 10)
+
+
+def _zeros():
+    a = np.loadtxt(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "hankel_zeros_scattering.txt"))
+    return a[:, 1] + 1j * a[:, 2]
+
+
+@pytest.fixture(scope="module")
+def N():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2312_13117_amd import nep
+    nep.lib()
+    return nep
+
+
+@pytest.mark.parametrize("npts", [16, 64])
+def test_sums_double_layer(N, npts):
+    say(f"case scattering sums n={npts}")
+    prob = gen.CircleDoubleLayer(npts)
+    reg = gen.Region(0.2, 1.4, -1.8, -0.6, 2, 2)          # around the m = 2 and m = 3 poles
+    opts = gen.Options(N=32, s=1, L=4)
+    F, V = gen.probes(11, npts, 1), gen.probes(12, npts, 4)
+    plan = N.nep_plan([prob], [reg], opts)
+    try:
+        N.nep_indicator(plan, [F], [V])
+        check_sums(N, plan, prob, reg, opts, F, V, 1e-12)
+    finally:
+        N.nep_destroy(plan)
+
+
+def test_pmcimb_paper_region(N):
+    prob = gen.CircleDoubleLayer(64)
+    opts = gen.Options(N=32, s=1, L=4)
+    F, V = gen.probes(11, 64, 1), gen.probes(12, 64, 4)
+    say("case scattering pmCIMb, 100 squares")
+    plan = N.nep_plan([prob], [REGION], opts)
+    try:
+        res = N.pmcimb(plan, [F], [V])
+    finally:
+        N.nep_destroy(plan)
+    ref = oracle.pmcimb(prob, REGION, opts, F, V)
+    assert np.array_equal(res.flags, ref.flags)
+    zs = _zeros()
+    say(f"  {int(res.flags.sum())} flagged disks, poles {np.round(res.eigs, 6)}")
+    assert len(res.eigs) == len(zs) == len(ref.eigs) == 6
+    for z in zs:
+        assert np.min(np.abs(res.eigs - z)) < 1e-9 * abs(z)
+        assert np.min(np.abs(ref.eigs - z)) < 1e-9 * abs(z)
+
+
+def test_pmcima_paper_region(N):
+    from paper_2312_13117_amd import pmcima
+    prob = gen.CircleDoubleLayer(64)
+    say("case scattering pmCIMa, 100 squares")
+    r = pmcima.pmcima(prob, REGION, gen.probes(11, 64, 1))
+    zs = _zeros()
+    say(f"  levels {r.levels}, disks {sum(len(d) for d in r.disks)}, {len(r.eigs)} merged values, {r.seconds:.2f} s")
+    assert len(r.eigs) == len(zs)
+    d = np.abs(r.eigs[:, None] - zs[None, :])
+    assert d.min(axis=0).max() <= 0.5e-6 and d.min(axis=1).max() <= 0.5e-6
+    # Step 2: the vector is a null vector of T at the pole to O(tol_eps)
+    for lam, v in zip(r.eigs, r.vectors):
+        assert np.linalg.norm(oracle.assemble(prob, lam) @ v) < 1e-5
