@@ -275,7 +275,8 @@ nep_status nep_verify(nep_plan_t* plan, const int32_t* prob_ids, const void* lam
  *   vec        NULL, or host complex128 [m * ldv]: row i receives the right singular
  *              vector of sigma_min(T(lambda_i)) at the returned value (the eigenvector
  *              of pmCIMa's Step 2, Section 3.1): unit 2-norm, its largest-modulus
- *              entry real and positive; entries past the candidate's n are untouched
+ *              entry real and positive; entries past the candidate's n are untouched;
+ *              zeros where the LU of T(lambda_i) met an exact zero pivot (sigma 0)
  *   ldv        >= n of every listed candidate's problem when vec is given
  * Cost: (iters + 1) complex128 LUs per candidate.  Errors: NEP_ERR_ARG.           */
 #define NEP_REFINE_MAX_ITERS 8

@@ -1026,7 +1026,13 @@ static nep_status verify_refine(nep_plan_t* P, const int32_t* prob_ids, const do
           if (sgm < sbest[b] || it == 0) {
             sbest[b] = sgm;
             zbest[b] = z[b];
-            if (vec) store_vector(&hv[(size_t)b * n], n, vec + (size_t)idx[c0 + b] * ldv);
+            double2* out = vec ? vec + (size_t)idx[c0 + b] * ldv : nullptr;
+            if (out && hinf[b]) {
+              // an exact zero pivot: the inverse iteration has no finite vector
+              for (int r = 0; r < n; ++r) out[r] = make_double2(0.0, 0.0);
+            } else if (out) {
+              store_vector(&hv[(size_t)b * n], n, out);
+            }
           }
           // an exactly singular T(z) (zero pivot) leaves nothing to improve
           if (upd && !hinf[b]) {
