@@ -144,8 +144,9 @@ typedef struct nep_region {
  *   precision  NEP_FP64 or NEP_FP32_REFINE
  *   max_refine maximum refinement sweeps for NEP_FP32_REFINE (0..8)
  *   batch      node matrices factored together (0 = chosen by the library)
- *   streams    worker streams the batches alternate over (1 or 2; 0 = 2): with two,
- *              one batch's panel steps overlap the other batch's trailing updates
+ *   streams    worker streams the batches alternate over (1 .. 3; 0 = 2), each with a
+ *              workspace of its own: with two or more, one batch's panel steps
+ *              overlap another batch's trailing updates
  *   pivot      NEP_PIVOT_PARTIAL (0) or NEP_PIVOT_TOURNAMENT (1)
  *   graph      1: nep_indicator captures its device work (every batch on both worker
  *              streams, the sums and the indicator) into a HIP graph on its first

@@ -6,7 +6,7 @@ columns, 32 nodes per disk, enough disks for several batches) over the candidate
 configurations
 
     batch    node matrices factored together (library default, or fixed sizes)
-    streams  1 or 2 worker streams
+    streams  1, 2 or 3 worker streams
     graph    eager launches, or the sweep captured in a HIP graph and replayed
     pivot    partial or tournament pivoting (recorded, not applied: it changes the
              rounding of the results)
@@ -68,12 +68,12 @@ def tune(sizes, precisions=(0, 1), reps: int = 3, log=print) -> dict:
     entries = []
     for n, prec in itertools.product(sizes, precisions):
         eb = 16 if prec == 0 else 8
-        # batches that keep two workspaces under 16 GB
-        cands = [0] + [b for b in (32, 64, 128, 256, 512) if 2 * b * n * n * eb <= 16e9]
+        # batches that keep three workspaces under 24 GB
+        cands = [0] + [b for b in (32, 64, 128, 256, 512) if 3 * b * n * n * eb <= 24e9]
         big = max(b for b in cands if b) if len(cands) > 1 else 32
         w = _workload(n, prec, tasks=max(256, 3 * big))
         best, results = None, []
-        for batch, streams, graph in itertools.product(cands, (1, 2), (0, 1)):
+        for batch, streams, graph in itertools.product(cands, (1, 2, 3), (0, 1)):
             o = gen.Options(N=32, s=4, L=16, precision=prec, batch=batch, streams=streams, graph=graph)
             rate = _time_config(w, o, reps)
             log(f"  n={n} precision={prec} batch={batch} streams={streams} graph={graph}: {rate:.0f} solves/s")

@@ -103,9 +103,10 @@ struct nep_plan {
   DevBuf PfN, PfN2, C0, C1, prof, ind, flags;
   DevBuf X, xoff, tnode, dlist;
   // LU workspaces: two for the sweep (own streams), one complex128 on the plan stream
-  Workspace ws[2];
+  static constexpr int MAX_WS = 3;     // worker streams (each with its own workspace)
+  Workspace ws[MAX_WS];
   Workspace w64;
-  hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
+  hipEvent_t ev_fork = nullptr, ev_join[MAX_WS] = {nullptr, nullptr, nullptr};
   DevBuf sing;
   DevBuf bscr, beig, bp, bsv, bkeep, bstat, bvec, bids;
   DevBuf vest;
@@ -223,7 +224,7 @@ extern "C" nep_status nep_plan(const nep_problem* probs, int nprob, const nep_re
   if (o.L < 0 || o.L > 32 || o.s + o.L > 32) return bad("L must be 0..32 with s + L <= 32");
   if (o.precision != NEP_FP64 && o.precision != NEP_FP32_REFINE) return bad("unknown precision");
   if (o.max_refine < 0 || o.max_refine > 8) return bad("max_refine must be 0..8");
-  if (o.streams < 0 || o.streams > 2) return bad("streams must be 0, 1 or 2");
+  if (o.streams < 0 || o.streams > 3) return bad("streams must be 0..3");
   if (o.pivot != NEP_PIVOT_TOURNAMENT && o.pivot != NEP_PIVOT_PARTIAL) return bad("pivot must be 0 or 1");
   if (o.graph != 0 && o.graph != 1) return bad("graph must be 0 or 1");
   if (!(o.tol_ind >= 0) || !(o.tol_svd >= 0) || !(o.tol_ver >= 0)) return bad("tolerances must be >= 0");
@@ -338,7 +339,7 @@ extern "C" nep_status nep_plan(const nep_problem* probs, int nprob, const nep_re
   const int B = P->batch, nm = P->nmax;
   const int steps = (nm + LU_NB - 1) / LU_NB;
   const size_t eb = elem_bytes(o.precision);
-  P->nstreams = (o.streams == 1) ? 1 : 2;
+  P->nstreams = (o.streams == 0) ? 2 : o.streams;
   for (int k = 0; k < P->nstreams; ++k) {
     Workspace& w = P->ws[k];
     PCHK(hipStreamCreateWithFlags(&w.st, hipStreamNonBlocking));
@@ -359,8 +360,7 @@ extern "C" nep_status nep_plan(const nep_problem* probs, int nprob, const nep_re
   }
   P->w64.st = P->st;
   PCHK(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming));
-  PCHK(hipEventCreateWithFlags(&P->ev_join[0], hipEventDisableTiming));
-  PCHK(hipEventCreateWithFlags(&P->ev_join[1], hipEventDisableTiming));
+  for (int q = 0; q < nep_plan_t::MAX_WS; ++q) PCHK(hipEventCreateWithFlags(&P->ev_join[q], hipEventDisableTiming));
   {
     DevBuf rf;
     PCHK(rf.alloc(sizeof(int) * MAX_TERMS));
@@ -648,7 +648,7 @@ static nep_status run_sweep_device(nep_plan_t* P, const SweepCall& sc, const Swe
     const long long ntask = (long long)(g.lj - g.li) * N;
     for (long long t0 = 0; t0 < ntask; t0 += P->batch, ++k) {
       const int nb = (int)std::min<long long>(P->batch, ntask - t0);
-      Workspace& w = P->ws[P->nstreams == 2 ? (k & 1) : 0];
+      Workspace& w = P->ws[k % P->nstreams];
       const long long task0 = (long long)g.li * N + t0;
       nep_status r = sweep_batch(P, w, prob, tn + task0, X + lay.xoff[g.li] + t0 * (long long)n * m, nb, sc,
                                  P->sing.as<int>() + task0, P->fbflag.as<int>() + task0);

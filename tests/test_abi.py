@@ -35,7 +35,7 @@ def test_plan_rejects_bad_options():
     reg = N.nep_region(-1, 1, -1, 1, 2, 2)
     h = C.c_void_p()
     for o in (gen.Options(N=7), gen.Options(N=2), gen.Options(s=0), gen.Options(L=40), gen.Options(precision=5),
-              gen.Options(max_refine=-1), gen.Options(tol_ind=float("nan")), gen.Options(streams=3),
+              gen.Options(max_refine=-1), gen.Options(tol_ind=float("nan")), gen.Options(streams=4),
               gen.Options(pivot=2), gen.Options(graph=2)):
         co = N.nep_options(o.N, o.s, o.L, o.tol_ind, o.tol_svd, o.tol_ver, o.precision, o.max_refine, o.batch,
                            o.streams, o.pivot, o.graph)

@@ -293,16 +293,18 @@ def test_sweep_is_deterministic(N):
             assert np.array_equal(x, y)
     finally:
         N.nep_destroy(plan)
-    # one worker stream and small batches give the same bits (batches are independent)
-    o1 = gen.Options(N=32, s=1, L=8, streams=1, batch=24)
-    plan = N.nep_plan(w.problems, w.regions, o1)
-    try:
-        N.nep_indicator(plan, w.F, w.V)
-        c = N.nep_copy_sums(plan, 0, plan.total_disks)
-        for x, y in zip(a, c):
-            assert np.array_equal(x, y)
-    finally:
-        N.nep_destroy(plan)
+    # one or three worker streams and small batches give the same bits (batches are
+    # independent)
+    for streams, batch in ((1, 24), (3, 40)):
+        o1 = gen.Options(N=32, s=1, L=8, streams=streams, batch=batch)
+        plan = N.nep_plan(w.problems, w.regions, o1)
+        try:
+            N.nep_indicator(plan, w.F, w.V)
+            c = N.nep_copy_sums(plan, 0, plan.total_disks)
+            for x, y in zip(a, c):
+                assert np.array_equal(x, y)
+        finally:
+            N.nep_destroy(plan)
 
 
 def test_dense_workload_sampled(N):
