@@ -310,9 +310,10 @@ def phase_dict(st):
     return {k: st[k] for k in ("ms_assemble", "ms_lu", "ms_solve", "ms_refine", "ms_sums", "ms_total")}
 
 
-def measured_traffic(workload: str, prec: str):
-    """HBM bytes per launch of the update kernel from the committed counter summary,
-    or None when there is none for this workload or the LU source has changed since."""
+def measured_traffic(workload: str, prec: str, flops_per_launch: float = None):
+    """HBM bytes per launch of the update kernel from the committed counter summary, or
+    None when there is none for this workload, the LU source has changed since, or the
+    launches now have another shape (a different batch: flops per launch differ)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "lu_update_traffic_dense_n1024.md")
     try:
@@ -325,6 +326,9 @@ def measured_traffic(workload: str, prec: str):
         h = hashlib.sha256(open(src, "rb").read()).hexdigest()
         if h != kv["kernel_source_sha256"] or kv["workload"] != workload or kv["precision"] != prec:
             return None
+        if flops_per_launch is not None and \
+                abs(float(kv["flops_per_launch"]) - flops_per_launch) > 0.005 * flops_per_launch:
+            return None
         return float(kv["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
         return None
@@ -332,7 +336,8 @@ def measured_traffic(workload: str, prec: str):
 
 def roofline(st, prec, workload=None):
     achieved = st["gemm_flops"] / (st["ms_gemm"] * 1e-3) if st["ms_gemm"] > 0 else 0.0
-    traffic = measured_traffic(workload, prec) if workload else None
+    fpl = st["gemm_flops"] / max(1, st["gemm_launches"])
+    traffic = measured_traffic(workload, prec, fpl) if workload else None
     return {"kernel": "lu_gemm_kernel<UPDATE2> (trailing update of the batched LU, two panels per pass, K = 128)",
             "bound": "mfma",
             "achieved": achieved / 1e12, "peak": PEAK[prec] / 1e12, "unit": "TFLOP/s",

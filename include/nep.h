@@ -143,7 +143,8 @@ typedef struct nep_region {
  *   tol_ver    accept lambda iff sigma_min(T(lambda)) < tol_ver (Step 3)
  *   precision  NEP_FP64 or NEP_FP32_REFINE
  *   max_refine maximum refinement sweeps for NEP_FP32_REFINE (0..8)
- *   batch      node matrices factored together (0 = chosen by the library)
+ *   batch      node matrices factored together (0 = chosen by the library: a workspace
+ *              of 12% of the device memory per worker stream, at most 2048 matrices)
  *   streams    worker streams the batches alternate over (1 .. 3; 0 = 2), each with a
  *              workspace of its own: with two or more, one batch's panel steps
  *              overlap another batch's trailing updates

@@ -155,11 +155,22 @@ static thread_local std::string g_last_create_error;
 
 static size_t elem_bytes(int precision) { return precision == NEP_FP32_REFINE ? 8 : 16; }
 
+// Factor workspace per worker stream: 12% of the device's memory (34 GB of an MI355X's
+// 288 GB), at most 2048 matrices.  Larger batches amortise the latency-bound panel
+// launches over more matrices (n = 1024 complex128 sweep: +4% from 472 to 2048).
+static double workspace_budget() {
+  static double budget = 0;
+  if (budget == 0) {
+    size_t free_b = 0, total_b = 0;
+    budget = (hipMemGetInfo(&free_b, &total_b) == hipSuccess && total_b > 0) ? 0.12 * (double)total_b : 8.0e9;
+  }
+  return budget;
+}
+
 static int choose_batch(int n, int precision, int ntask_max, int requested) {
   if (requested > 0) return std::min(requested, std::max(1, ntask_max));
-  const double budget = 8.0e9;   // bytes of factor workspace
   const double per = (double)n * n * elem_bytes(precision);
-  int b = (int)std::min(512.0, std::max(1.0, std::floor(budget / per)));
+  int b = (int)std::min(2048.0, std::max(1.0, std::floor(workspace_budget() / per)));
   if (b >= 8) b -= b % 8;
   return std::max(1, std::min(b, std::max(1, ntask_max)));
 }
