@@ -82,11 +82,15 @@ def tune(sizes, precisions=(0, 1), reps: int = 3, log=print) -> dict:
     import gen
     import torch
     entries = []
+    total = torch.cuda.get_device_properties(0).total_memory
     for n, prec in itertools.product(sizes, precisions):
         eb = 16 if prec == 0 else 8
-        # batches that keep three workspaces under 24 GB
-        cands = [0] + [b for b in (32, 64, 128, 256, 512) if 3 * b * n * n * eb <= 24e9]
-        big = max(b for b in cands if b) if len(cands) > 1 else 32
+        # the library's default batch (12% of the device memory, at most 2048 matrices)
+        # and fixed ones that keep three workspaces under 24 GB; the workload holds
+        # three batches of the largest, so that two or three streams can overlap
+        default = int(min(2048, max(1, (0.12 * total) // (n * n * eb))))
+        cands = [0] + [b for b in (64, 256, 512) if 3 * b * n * n * eb <= 24e9]
+        big = max([default] + [b for b in cands if b])
         w = _workload(n, prec, tasks=max(256, 3 * big))
         best, results = None, []
         for batch, streams, graph in itertools.product(cands, (1, 2, 3), (0, 1)):
