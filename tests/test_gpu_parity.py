@@ -325,3 +325,28 @@ def test_dense_workload_sampled(N):
             assert flags[d] == (I > 0.1)
     finally:
         N.nep_destroy(plan)
+
+
+def test_results_do_not_depend_on_the_probes(N):
+    """Flags and eigenvalues are properties of T (P f = 0 exactly when a disk holds no
+    eigenvalue, for almost every probe): other probe draws give the same flags on the
+    n = 64 workload, and with 31 Beyn columns the same verified eigenvalues (to the
+    quadrature error; to rounding after refinement)."""
+    w = gen.workload_small_qep()
+    say("case probe independence")
+    out = []
+    for fs, vs in ((2, 3), (20, 30)):
+        o = gen.Options(N=32, s=1, L=31)
+        plan = N.nep_plan(w.problems, w.regions, o)
+        try:
+            res = N.pmcimb(plan, [gen.probes(fs, 64, 1)], [gen.probes(vs, 64, 31)])
+            lam, sig, acc, _ = N.nep_refine(plan, [0] * len(res.eigs), res.eigs, 2)
+            out.append((res.flags, np.sort_complex(res.eigs), np.sort_complex(lam)))
+        finally:
+            N.nep_destroy(plan)
+    assert np.array_equal(out[0][0], out[1][0])
+    a, b = out[0][1], out[1][1]
+    assert len(a) == len(b) and len(a) > 20
+    assert max(np.min(np.abs(b - v)) for v in a) < 1e-5
+    ra, rb = out[0][2], out[1][2]
+    assert max(np.min(np.abs(rb - v)) / max(1, abs(v)) for v in ra) < 1e-12
