@@ -371,7 +371,7 @@ def main():
         print(json.dumps(copy_calibration()))
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     w = build_workload(args.workload, args.delay_count, pivot)
     prec = "fp32" if w.opts.precision == 1 else "fp64"
