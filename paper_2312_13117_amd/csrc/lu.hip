@@ -1413,12 +1413,13 @@ __global__ __launch_bounds__(256, gemm_min_blocks<MODE>()) void lu_gemm_kernel(c
 // ----------------------------------------------------------------------------- solves
 // One workgroup of 256 threads per matrix; the right-hand sides X (n x m, m <= 32,
 // complex128, row-major) are solved in place in the factor's arithmetic T.
-// Every block product runs as a 64 x m tile (thread t owns rows 2(t/8)+{0,1} and
-// columns t%8 + 8{0..3}) over operand chunks staged in LDS.
-template <typename T>
+// Every block product runs as a 64 x 8 JN tile (thread t owns rows 2(t/8)+{0,1} and
+// columns t%8 + 8{0..JN-1}; JN = ceil(m / 8), so no column group is all padding) over
+// operand chunks staged in LDS.
+template <typename T, int JN>
 struct SolveTile {
   static constexpr int MMAX = 32, KC = 32;
-  c2<T> acc[2][4];
+  c2<T> acc[2][JN];
   int r0, cb;
   __device__ SolveTile() {
     r0 = 2 * (threadIdx.x >> 3);
@@ -1428,7 +1429,7 @@ struct SolveTile {
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = czero<T>();
+      for (int j = 0; j < JN; ++j) acc[i][j] = czero<T>();
   }
   // acc (+|-)= Ash[r][0:kc] * Bsh[kbase + 0:kc][c]
   template <bool SUB>
@@ -1436,7 +1437,7 @@ struct SolveTile {
     for (int k = 0; k < kc; ++k) {
       const c2<T> a0 = Ash[r0][k], a1 = Ash[r0 + 1][k];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < JN; ++j) {
         const c2<T> bv = Bsh[kbase + k][cb + 8 * j];
         if (SUB) {
           acc[0][j] = cfms<T>(acc[0][j], a0, bv);
@@ -1450,13 +1451,13 @@ struct SolveTile {
   }
 };
 
-template <typename T, int NB, bool TRANS>
+template <typename T, int NB, bool TRANS, int JN>
 __global__ __launch_bounds__(256) void lu_solve_kernel(const c2<T>* __restrict__ W, long long mstride, int n,
                                                        const int* __restrict__ perm, long long perm_stride,
                                                        const c2<T>* __restrict__ Linv, const c2<T>* __restrict__ Uinv,
                                                        long long inv_stride, double2* __restrict__ X,
                                                        long long xstride, int m, const int* __restrict__ active) {
-  constexpr int MMAX = 32, KC = SolveTile<T>::KC;
+  constexpr int MMAX = 32, KC = SolveTile<T, JN>::KC;
   const int b = blockIdx.x;
   if (active && !active[b]) return;
   const int t = threadIdx.x;
@@ -1469,7 +1470,7 @@ __global__ __launch_bounds__(256) void lu_solve_kernel(const c2<T>* __restrict__
   c2<T> (*Bsh)[MMAX] = reinterpret_cast<c2<T>(*)[MMAX]>(tiles + NB * (KC + 1));
   __shared__ int s_pos[2 * NB], s_src[2 * NB];
   __shared__ int s_cnt;
-  SolveTile<T> tile;
+  SolveTile<T, JN> tile;
 
   auto load_perm = [&](int s) {
     const int* P = perm + (long long)b * perm_stride + (long long)s * (1 + 4 * NB);
@@ -1514,7 +1515,7 @@ __global__ __launch_bounds__(256) void lu_solve_kernel(const c2<T>* __restrict__
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < JN; ++j) {
         const int r = tile.r0 + i, c = tile.cb + 8 * j;
         tile.acc[i][j] = (r < nr && c < m) ? ccast<T, double>(Xb[(long long)(xrow0 + r) * m + c]) : czero<T>();
       }
@@ -1523,7 +1524,7 @@ __global__ __launch_bounds__(256) void lu_solve_kernel(const c2<T>* __restrict__
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < JN; ++j) {
         const int r = tile.r0 + i, c = tile.cb + 8 * j;
         if (r < nr && c < m) Xb[(long long)(xrow0 + r) * m + c] = ccast<double, T>(tile.acc[i][j]);
       }
@@ -1532,7 +1533,7 @@ __global__ __launch_bounds__(256) void lu_solve_kernel(const c2<T>* __restrict__
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) Bsh[tile.r0 + i][tile.cb + 8 * j] = tile.acc[i][j];
+      for (int j = 0; j < JN; ++j) Bsh[tile.r0 + i][tile.cb + 8 * j] = tile.acc[i][j];
   };
 
   if (!TRANS) {
@@ -1719,13 +1720,13 @@ __global__ __launch_bounds__(256) void lu_solve_kernel(const c2<T>* __restrict__
 // subtracts the step's block column times that block from the rows below (forward) or
 // above (backward).  Same arithmetic as lu_solve_kernel (products in T, X in
 // complex128), many more loads in flight.
-template <typename T, int NB, bool FWD>
+template <typename T, int NB, bool FWD, int JN>
 __global__ __launch_bounds__(256) void solve_top_kernel(const c2<T>* __restrict__ W, long long mstride, int n,
                                                         int step, const int* __restrict__ perm,
                                                         long long perm_stride, const c2<T>* __restrict__ Inv,
                                                         long long inv_stride, double2* __restrict__ X,
                                                         long long xstride, int m, const int* __restrict__ active) {
-  constexpr int MMAX = SolveTile<T>::MMAX, KC = SolveTile<T>::KC;
+  constexpr int MMAX = SolveTile<T, JN>::MMAX, KC = SolveTile<T, JN>::KC;
   const int b = blockIdx.x;
   if (active && !active[b]) return;
   const int t = threadIdx.x;
@@ -1765,7 +1766,7 @@ __global__ __launch_bounds__(256) void solve_top_kernel(const c2<T>* __restrict_
     }
   }
   const c2<T>* Ib = Inv + (long long)b * inv_stride + (long long)step * NB * NB;
-  SolveTile<T> tile;
+  SolveTile<T, JN> tile;
   tile.zero();
   for (int kc = 0; kc < nbk; kc += KC) {
     const int kk = min(KC, nbk - kc);
@@ -1780,7 +1781,7 @@ __global__ __launch_bounds__(256) void solve_top_kernel(const c2<T>* __restrict_
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < JN; ++j) {
       const int r = tile.r0 + i, c = tile.cb + 8 * j;
       if (r < nbk && c < m) Xb[(long long)(k0 + r) * m + c] = ccast<double, T>(tile.acc[i][j]);
     }
@@ -1788,12 +1789,12 @@ __global__ __launch_bounds__(256) void solve_top_kernel(const c2<T>* __restrict_
 
 // X[r, :] -= F[r, k0:k0+nbk] X[k0:k0+nbk, :] for the 64 rows of tile `tile` of the
 // range [r_lo, r_hi) (forward: rows below the block, backward: rows above it)
-template <typename T, int NB>
+template <typename T, int NB, int JN>
 __global__ __launch_bounds__(256) void solve_rows_kernel(const c2<T>* __restrict__ W, long long mstride, int n,
                                                          int step, int r_lo, int r_hi, int tiles,
                                                          double2* __restrict__ X, long long xstride, int m,
                                                          const int* __restrict__ active) {
-  constexpr int MMAX = SolveTile<T>::MMAX, KC = SolveTile<T>::KC;
+  constexpr int MMAX = SolveTile<T, JN>::MMAX, KC = SolveTile<T, JN>::KC;
   const int b = blockIdx.x / tiles, tl = blockIdx.x % tiles;
   if (active && !active[b]) return;
   const int t = threadIdx.x;
@@ -1807,11 +1808,11 @@ __global__ __launch_bounds__(256) void solve_rows_kernel(const c2<T>* __restrict
     const int i = e / MMAX, c = e % MMAX;
     Bsh[i][c] = (i < nbk && c < m) ? ccast<T, double>(Xb[(long long)(k0 + i) * m + c]) : czero<T>();
   }
-  SolveTile<T> tile;
+  SolveTile<T, JN> tile;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < JN; ++j) {
       const int r = tile.r0 + i, c = tile.cb + 8 * j;
       tile.acc[i][j] = (r < nr && c < m) ? ccast<T, double>(Xb[(long long)(R0 + r) * m + c]) : czero<T>();
     }
@@ -1828,7 +1829,7 @@ __global__ __launch_bounds__(256) void solve_rows_kernel(const c2<T>* __restrict
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < JN; ++j) {
       const int r = tile.r0 + i, c = tile.cb + 8 * j;
       if (r < nr && c < m) Xb[(long long)(R0 + r) * m + c] = ccast<double, T>(tile.acc[i][j]);
     }
@@ -1986,38 +1987,51 @@ hipError_t lu_factor_batch(c2<T>* W, long long mstride, int n, int nbatch, void*
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t lu_solve_batch(const c2<T>* W, long long mstride, int n, int nbatch, const int* perm, long long perm_stride,
-                          const c2<T>* Linv, const c2<T>* Uinv, long long inv_stride, double2* X, long long xstride,
-                          int m, bool trans, const int* active, hipStream_t st) {
-  if (m > 32 || m < 1) return hipErrorInvalidValue;
+// the solve kernels for JN column groups of 8 right-hand sides
+template <typename T, int JN>
+static void solve_launch(const c2<T>* W, long long mstride, int n, int nbatch, const int* perm, long long perm_stride,
+                         const c2<T>* Linv, const c2<T>* Uinv, long long inv_stride, double2* X, long long xstride,
+                         int m, bool trans, const int* active, hipStream_t st) {
   if (trans) {
-    lu_solve_kernel<T, LU_NB, true><<<nbatch, 256, 0, st>>>(W, mstride, n, perm, perm_stride, Linv, Uinv, inv_stride, X, xstride, m, active);
+    lu_solve_kernel<T, LU_NB, true, JN><<<nbatch, 256, 0, st>>>(W, mstride, n, perm, perm_stride, Linv, Uinv, inv_stride, X, xstride, m, active);
   } else if (n < LU_SOLVE_SPLIT_N || m > LU_SOLVE_SPLIT_M) {
-    lu_solve_kernel<T, LU_NB, false><<<nbatch, 256, 0, st>>>(W, mstride, n, perm, perm_stride, Linv, Uinv, inv_stride, X, xstride, m, active);
+    lu_solve_kernel<T, LU_NB, false, JN><<<nbatch, 256, 0, st>>>(W, mstride, n, perm, perm_stride, Linv, Uinv, inv_stride, X, xstride, m, active);
   } else {
     constexpr int NB = LU_NB;
     const int nsteps = (n + NB - 1) / NB;
     for (int s = 0; s < nsteps; ++s) {
       const int k0 = s * NB, kend = min(n, k0 + NB);
-      solve_top_kernel<T, NB, true><<<nbatch, 256, 0, st>>>(W, mstride, n, s, perm, perm_stride, Linv, inv_stride,
+      solve_top_kernel<T, NB, true, JN><<<nbatch, 256, 0, st>>>(W, mstride, n, s, perm, perm_stride, Linv, inv_stride,
                                                             X, xstride, m, active);
       if (kend < n) {
         const int tiles = (n - kend + 63) / 64;
-        solve_rows_kernel<T, NB><<<dim3((unsigned)(nbatch * tiles)), 256, 0, st>>>(W, mstride, n, s, kend, n, tiles,
+        solve_rows_kernel<T, NB, JN><<<dim3((unsigned)(nbatch * tiles)), 256, 0, st>>>(W, mstride, n, s, kend, n, tiles,
                                                                                   X, xstride, m, active);
       }
     }
     for (int s = nsteps - 1; s >= 0; --s) {
       const int k0 = s * NB;
-      solve_top_kernel<T, NB, false><<<nbatch, 256, 0, st>>>(W, mstride, n, s, perm, perm_stride, Uinv, inv_stride,
+      solve_top_kernel<T, NB, false, JN><<<nbatch, 256, 0, st>>>(W, mstride, n, s, perm, perm_stride, Uinv, inv_stride,
                                                              X, xstride, m, active);
       if (k0 > 0) {
         const int tiles = (k0 + 63) / 64;
-        solve_rows_kernel<T, NB><<<dim3((unsigned)(nbatch * tiles)), 256, 0, st>>>(W, mstride, n, s, 0, k0, tiles,
+        solve_rows_kernel<T, NB, JN><<<dim3((unsigned)(nbatch * tiles)), 256, 0, st>>>(W, mstride, n, s, 0, k0, tiles,
                                                                                   X, xstride, m, active);
       }
     }
+  }
+}
+
+template <typename T>
+hipError_t lu_solve_batch(const c2<T>* W, long long mstride, int n, int nbatch, const int* perm, long long perm_stride,
+                          const c2<T>* Linv, const c2<T>* Uinv, long long inv_stride, double2* X, long long xstride,
+                          int m, bool trans, const int* active, hipStream_t st) {
+  if (m > 32 || m < 1) return hipErrorInvalidValue;
+  switch ((m + 7) / 8) {
+    case 1: solve_launch<T, 1>(W, mstride, n, nbatch, perm, perm_stride, Linv, Uinv, inv_stride, X, xstride, m, trans, active, st); break;
+    case 2: solve_launch<T, 2>(W, mstride, n, nbatch, perm, perm_stride, Linv, Uinv, inv_stride, X, xstride, m, trans, active, st); break;
+    case 3: solve_launch<T, 3>(W, mstride, n, nbatch, perm, perm_stride, Linv, Uinv, inv_stride, X, xstride, m, trans, active, st); break;
+    default: solve_launch<T, 4>(W, mstride, n, nbatch, perm, perm_stride, Linv, Uinv, inv_stride, X, xstride, m, trans, active, st); break;
   }
   return hipGetLastError();
 }
