@@ -29,8 +29,12 @@ struct DevBuf {
     if (p) { hipFree(p); p = nullptr; bytes = 0; }
     if (b == 0) return hipSuccess;
     hipError_t e = hipMalloc(&p, b);
-    if (e == hipSuccess) bytes = b;
-    else p = nullptr;
+    if (e == hipSuccess) {
+      bytes = b;
+    } else {
+      p = nullptr;
+      (void)hipGetLastError();   // the failure is returned here; do not leave it for the next launch check
+    }
     return e;
   }
   void release() {
@@ -221,12 +225,18 @@ static void reset_stats(nep_plan_t* p) {
   p->lut.gemm_flops = 0;
 }
 
+// Launches are checked with hipGetLastError, which also returns an error left by an
+// earlier, unrelated call of this thread (a caller's failed allocation, say): every
+// entry point that launches work starts from a clear state.
+static void clear_stale_error() { (void)hipGetLastError(); }
+
 // ---------------------------------------------------------------------------- plan
 extern "C" nep_status nep_plan(const nep_problem* probs, int nprob, const nep_region* regs,
                                const nep_options* opt, hipStream_t stream, nep_plan_t** out) {
   if (!out) return NEP_ERR_ARG;
   *out = nullptr;
   g_last_create_error.clear();
+  clear_stale_error();
   auto bad = [](const char* m) { g_last_create_error = m; return NEP_ERR_ARG; };
   if (!probs || nprob < 1 || !regs || !opt) return bad("null argument or nprob < 1");
   const nep_options& o = *opt;
@@ -760,6 +770,7 @@ static nep_status capture_sweep(nep_plan_t* P, const SweepCall& sc, const SweepL
 extern "C" nep_status nep_indicator(nep_plan_t* P, const void* const* F_dev, const void* const* V_dev, double* ind,
                                     uint8_t* flags, double* profiles) {
   if (!P) return NEP_ERR_ARG;
+  clear_stale_error();
   if (!F_dev || !ind || !flags) return fail(P, NEP_ERR_ARG, "F_dev, ind and flags are required");
   for (int p = 0; p < P->nprob; ++p)
     if (!F_dev[p] || (V_dev && P->opt.L > 0 && !V_dev[p])) return fail(P, NEP_ERR_ARG, "null probe block");
@@ -836,6 +847,7 @@ extern "C" nep_status nep_indicator(nep_plan_t* P, const void* const* F_dev, con
 extern "C" nep_status nep_beyn(nep_plan_t* P, const int32_t* disk_ids, int ndisks, const void* const* V_dev,
                                void* eig, int32_t* p, double* sv, uint8_t* keep, void* eigvec_dev) {
   if (!P) return NEP_ERR_ARG;
+  clear_stale_error();
   if (ndisks < 0 || (ndisks > 0 && (!disk_ids || !eig || !p || !sv))) return fail(P, NEP_ERR_ARG, "null output");
   const int L = P->opt.L;
   if (L < 1) return fail(P, NEP_ERR_ARG, "plan has L = 0");
@@ -1068,6 +1080,7 @@ static nep_status verify_refine(nep_plan_t* P, const int32_t* prob_ids, const do
 
 static nep_status check_candidates(nep_plan_t* P, const int32_t* prob_ids, const void* lam, int m, double* sigma_min,
                                    uint8_t* accepted) {
+  clear_stale_error();
   if (m < 0 || (m > 0 && (!prob_ids || !lam || !sigma_min || !accepted))) return fail(P, NEP_ERR_ARG, "null argument");
   for (int i = 0; i < m; ++i)
     if (prob_ids[i] < 0 || prob_ids[i] >= P->nprob) return fail(P, NEP_ERR_ARG, "problem id out of range");
