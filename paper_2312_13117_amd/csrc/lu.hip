@@ -855,7 +855,11 @@ __device__ inline unsigned long long rp_key(float m, int i) {
   return ((unsigned long long)__float_as_uint(m) << 16) | (unsigned long long)(4095 - i);
 }
 
-template <typename T, int RP_W, int RP_NT, int RPT>
+// PREV: the rank-W update of the previous leaf (q - 1) has not been applied to this
+// leaf's columns nor to the panel's top rows right of it; the leaf applies it to its own
+// rows on load and to its top rows before forming U (leaves then run in pairs with one
+// rank-2W update per pair for the columns right of both).
+template <typename T, int RP_W, int RP_NT, int RPT, bool PREV>
 __global__ __launch_bounds__(RP_NT) void rpanel_leaf_kernel(c2<T>* __restrict__ W, long long mstride, int n,
                                                             int k0, int q, int* __restrict__ sub,
                                                             int* __restrict__ info) {
@@ -875,6 +879,7 @@ __global__ __launch_bounds__(RP_NT) void rpanel_leaf_kernel(c2<T>* __restrict__ 
   __shared__ unsigned char s_top[RP_W];
   __shared__ c2<T> xbuf[2 * RP_W][OC];             // exchanged rows of the other panel columns
   __shared__ c2<T> Lqq[RP_W][RP_W + 1];
+  __shared__ c2<T> Up[PREV ? RP_W : 1][RP_W];      // U of the previous leaf in this leaf's columns
 
   c2<T> a[RPT][RP_W];
   int row[RPT];
@@ -886,6 +891,23 @@ __global__ __launch_bounds__(RP_NT) void rpanel_leaf_kernel(c2<T>* __restrict__ 
     chosen[p] = false;
 #pragma unroll
     for (int u = 0; u < RP_W; ++u) a[p][u] = (r < n) ? A[(long long)r * n + c0 + u] : czero<T>();
+  }
+  if constexpr (PREV) {
+    // a -= L[r, c0-W : c0] U[r0-W : r0, c0 : c0+W] (the previous leaf's multipliers and U rows)
+    for (int e = t; e < RP_W * RP_W; e += RP_NT)
+      Up[e / RP_W][e % RP_W] = A[(long long)(r0 - RP_W + e / RP_W) * n + c0 + e % RP_W];
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < RPT; ++p) {
+      if (row[p] < 0) continue;
+      const c2<T>* Lr = A + (long long)row[p] * n + c0 - RP_W;
+#pragma unroll
+      for (int kk = 0; kk < RP_W; ++kk) {
+        const c2<T> l = Lr[kk];
+#pragma unroll
+        for (int u = 0; u < RP_W; ++u) a[p][u] = cfms<T>(a[p][u], l, Up[kk][u]);
+      }
+    }
   }
   if (t == 0) s_sing = 0;
   if (t < RP_W) win[t] = -1;
@@ -1012,6 +1034,19 @@ __global__ __launch_bounds__(RP_NT) void rpanel_leaf_kernel(c2<T>* __restrict__ 
   // per thread, forward substitution out of LDS)
   if (t < wr) {
     const int cc = cright + t;                      // each thread owns one column of xbuf
+    if constexpr (PREV) {
+      // the previous leaf's update on the top rows: xbuf columns cright - W .. cright - 1
+      // hold their multipliers, its U rows sit at rows r0 - W .. r0 - 1
+      c2<T> up[RP_W];
+#pragma unroll
+      for (int kk = 0; kk < RP_W; ++kk) up[kk] = A[(long long)(r0 - RP_W + kk) * n + cr + t];
+      for (int i = 0; i < RP_W; ++i) {
+        c2<T> v = xbuf[i][cc];
+#pragma unroll
+        for (int kk = 0; kk < RP_W; ++kk) v = cfms<T>(v, xbuf[i][cright - RP_W + kk], up[kk]);
+        xbuf[i][cc] = v;
+      }
+    }
     for (int i = 0; i < RP_W; ++i) {
       c2<T> v = xbuf[i][cc];
       for (int l = 0; l < i; ++l) v = cfms<T>(v, Lqq[i][l], xbuf[l][cc]);
@@ -1893,16 +1928,27 @@ hipError_t lu_factor_batch(c2<T>* W, long long mstride, int n, int nbatch, void*
       constexpr int LW = sizeof(T) == 8 ? 8 : 16;          // leaf width
       for (int q = 0; q < NB / LW; ++q) {
         if constexpr (sizeof(T) == 8) {
-          rpanel_leaf_kernel<T, 8, 512, 2><<<nbatch, 512, 0, st>>>(W, mstride, n, k0, q, sub, info);
+          // leaves in pairs: the odd leaf applies the even one's update to itself, and one
+          // rank-16 update per pair serves the columns right of both
+          if (q & 1)
+            rpanel_leaf_kernel<T, 8, 512, 2, true><<<nbatch, 512, 0, st>>>(W, mstride, n, k0, q, sub, info);
+          else
+            rpanel_leaf_kernel<T, 8, 512, 2, false><<<nbatch, 512, 0, st>>>(W, mstride, n, k0, q, sub, info);
+          if ((q & 1) && q < NB / LW - 1) {
+            const int tiles = (n - (k0 + LW * (q - 1)) - 2 * LW + 63) / 64;
+            rpanel_update_kernel<T, 2 * LW><<<dim3((unsigned)(nbatch * tiles)), 256, 0, st>>>(W, mstride, n, k0,
+                                                                                            (q - 1) / 2, tiles);
+          }
         } else {
           if (rows > RP_NTMAX)
-            rpanel_leaf_kernel<T, 16, 1024, 2><<<nbatch, 1024, 0, st>>>(W, mstride, n, k0, q, sub, info);
+            rpanel_leaf_kernel<T, 16, 1024, 2, false><<<nbatch, 1024, 0, st>>>(W, mstride, n, k0, q, sub, info);
           else
-            rpanel_leaf_kernel<T, 16, 1024, 1><<<nbatch, 1024, 0, st>>>(W, mstride, n, k0, q, sub, info);
-        }
-        if (q < NB / LW - 1) {
-          const int tiles = (n - (k0 + LW * q) - LW + 63) / 64;
-          rpanel_update_kernel<T, LW><<<dim3((unsigned)(nbatch * tiles)), 256, 0, st>>>(W, mstride, n, k0, q, tiles);
+            rpanel_leaf_kernel<T, 16, 1024, 1, false><<<nbatch, 1024, 0, st>>>(W, mstride, n, k0, q, sub, info);
+          if (q < NB / LW - 1) {
+            const int tiles = (n - (k0 + LW * q) - LW + 63) / 64;
+            rpanel_update_kernel<T, LW><<<dim3((unsigned)(nbatch * tiles)), 256, 0, st>>>(W, mstride, n, k0, q,
+                                                                                           tiles);
+          }
         }
       }
       rpanel_finish_kernel<T, NB, LW><<<nbatch, 256, 0, st>>>(W, mstride, n, k0, s, sub, perm, perm_stride, Linv, Uinv,
