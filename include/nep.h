@@ -189,6 +189,8 @@ typedef struct nep_stats {
   double ms_gemm;            /* the paired trailing update alone (timed launches)      */
   int64_t gemm_launches;     /* its timed launches (the first 2048 of the call)       */
   double gemm_flops;         /* its algorithmic flops over those launches             */
+  double ms_gemm_busy;       /* the union of those launches' intervals: ms_gemm counts
+                                twice the time two worker streams' launches overlap   */
 } nep_stats;
 
 typedef struct nep_plan nep_plan_t;

@@ -206,13 +206,32 @@ static void finish_stats(nep_plan_t* p) {
   p->stats.ms_refine = tsum(p, PH_REFINE);
   p->stats.ms_sums = tsum(p, PH_SUMS);
   p->stats.ms_total = tsum(p, PH_TOTAL);
+  // Each timed launch as an interval against the first start event; launches of the
+  // worker streams may overlap, so the busy time is the length of their union.
   double g = 0;
+  std::vector<std::pair<float, float>> iv;
+  iv.reserve(p->lut.npairs);
   for (int i = 0; i < p->lut.npairs; ++i) {
-    float x = 0;
-    hipEventElapsedTime(&x, p->lut.ev[2 * i], p->lut.ev[2 * i + 1]);
-    g += x;
+    float a = 0, b = 0;
+    hipEventElapsedTime(&a, p->lut.ev[0], p->lut.ev[2 * i]);
+    hipEventElapsedTime(&b, p->lut.ev[0], p->lut.ev[2 * i + 1]);
+    g += b - a;
+    iv.push_back({a, b});
   }
+  std::sort(iv.begin(), iv.end());
+  double busy = 0, lo = 0, hi = 0;
+  for (size_t i = 0; i < iv.size(); ++i) {
+    if (i == 0 || iv[i].first > hi) {
+      busy += hi - lo;
+      lo = iv[i].first;
+      hi = iv[i].second;
+    } else if (iv[i].second > hi) {
+      hi = iv[i].second;
+    }
+  }
+  busy += hi - lo;
   p->stats.ms_gemm = g;
+  p->stats.ms_gemm_busy = busy;
   p->stats.gemm_launches = p->lut.gemm_launches;
   p->stats.gemm_flops = p->lut.gemm_flops;
 }

@@ -46,7 +46,7 @@ class nep_stats(C.Structure):
                 ("singular_nodes", C.c_int64), ("ms_total", C.c_double), ("ms_assemble", C.c_double),
                 ("ms_lu", C.c_double), ("ms_solve", C.c_double), ("ms_refine", C.c_double),
                 ("ms_sums", C.c_double), ("ms_gemm", C.c_double), ("gemm_launches", C.c_int64),
-                ("gemm_flops", C.c_double)]
+                ("gemm_flops", C.c_double), ("ms_gemm_busy", C.c_double)]
 
 
 _lib = None
