@@ -1925,11 +1925,11 @@ hipError_t lu_factor_batch(c2<T>* W, long long mstride, int n, int nbatch, void*
     } else if (pivot == LU_PIVOT_PARTIAL && rows <= (sizeof(T) == 4 ? 2 : 1) * RP_NTMAX) {
       // recursive panel: register leaves with rank-W updates between them
       int* sub = ipiv + (size_t)nbatch * n;
-      constexpr int LW = sizeof(T) == 8 ? 8 : 16;          // leaf width
-      for (int q = 0; q < NB / LW; ++q) {
-        if constexpr (sizeof(T) == 8) {
-          // leaves in pairs: the odd leaf applies the even one's update to itself, and one
-          // rank-16 update per pair serves the columns right of both
+      if (sizeof(T) == 8 || rows <= RP_NTMAX) {
+        // leaves of 8 columns in pairs: the odd leaf applies the even one's update to
+        // itself, and one rank-16 update per pair serves the columns right of both
+        constexpr int LW = 8;
+        for (int q = 0; q < NB / LW; ++q) {
           if (q & 1)
             rpanel_leaf_kernel<T, 8, 512, 2, true><<<nbatch, 512, 0, st>>>(W, mstride, n, k0, q, sub, info);
           else
@@ -1939,20 +1939,23 @@ hipError_t lu_factor_batch(c2<T>* W, long long mstride, int n, int nbatch, void*
             rpanel_update_kernel<T, 2 * LW><<<dim3((unsigned)(nbatch * tiles)), 256, 0, st>>>(W, mstride, n, k0,
                                                                                             (q - 1) / 2, tiles);
           }
-        } else {
-          if (rows > RP_NTMAX)
-            rpanel_leaf_kernel<T, 16, 1024, 2, false><<<nbatch, 1024, 0, st>>>(W, mstride, n, k0, q, sub, info);
-          else
-            rpanel_leaf_kernel<T, 16, 1024, 1, false><<<nbatch, 1024, 0, st>>>(W, mstride, n, k0, q, sub, info);
+        }
+        rpanel_finish_kernel<T, NB, LW><<<nbatch, 256, 0, st>>>(W, mstride, n, k0, s, sub, perm, perm_stride, Linv,
+                                                                Uinv, inv_stride);
+      } else if constexpr (sizeof(T) == 4) {
+        // complex64 panels of 1025..2048 rows: leaves of 16 columns, two rows per thread
+        constexpr int LW = 16;
+        for (int q = 0; q < NB / LW; ++q) {
+          rpanel_leaf_kernel<T, 16, 1024, 2, false><<<nbatch, 1024, 0, st>>>(W, mstride, n, k0, q, sub, info);
           if (q < NB / LW - 1) {
             const int tiles = (n - (k0 + LW * q) - LW + 63) / 64;
             rpanel_update_kernel<T, LW><<<dim3((unsigned)(nbatch * tiles)), 256, 0, st>>>(W, mstride, n, k0, q,
                                                                                            tiles);
           }
         }
+        rpanel_finish_kernel<T, NB, LW><<<nbatch, 256, 0, st>>>(W, mstride, n, k0, s, sub, perm, perm_stride, Linv,
+                                                                Uinv, inv_stride);
       }
-      rpanel_finish_kernel<T, NB, LW><<<nbatch, 256, 0, st>>>(W, mstride, n, k0, s, sub, perm, perm_stride, Linv, Uinv,
-                                                              inv_stride);
     } else if (pivot == LU_PIVOT_PARTIAL) {
       // panel rows n - k0 <= threads * rows-per-thread
       if (n <= 1024)
