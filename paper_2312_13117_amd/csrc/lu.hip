@@ -1083,8 +1083,12 @@ __global__ __launch_bounds__(256) void rpanel_update_kernel(c2<T>* __restrict__ 
   }
 }
 
-// the step's exchange (the four leaf exchanges composed, top rows first) and the
-// inverses of the factored 64 x 64 diagonal block
+// the step's exchange (the leaf exchanges composed, top rows first) and the inverses
+// of the factored 64 x 64 diagonal block.  The leaves' exchange records are staged in
+// LDS before one thread composes the step's record from them; the row map of that
+// phase shares its LDS with the diagonal block of the next (at most RP_ROWS rows: the
+// launcher sends only panels that fit the leaves), so two workgroups fit on a CU.
+constexpr int RP_ROWS = 2 * RP_NTMAX;
 template <typename T, int NB, int RP_W>
 __global__ __launch_bounds__(256) void rpanel_finish_kernel(const c2<T>* __restrict__ W, long long mstride, int n,
                                                             int k0, int step, const int* __restrict__ sub,
@@ -1092,18 +1096,22 @@ __global__ __launch_bounds__(256) void rpanel_finish_kernel(const c2<T>* __restr
                                                             c2<T>* __restrict__ Linv, c2<T>* __restrict__ Uinv,
                                                             long long inv_stride) {
   constexpr int NL = NB / RP_W, RP_EX = rp_ex(RP_W);
+  constexpr size_t TRI_BYTES = sizeof(c2<T>) * NB * (NB + 1), MAP_BYTES = (sizeof(int) + 1) * RP_ROWS;
   const int b = blockIdx.x, t = threadIdx.x;
   const c2<T>* A = W + (long long)b * mstride;
-  __shared__ c2<T> Mtri[NB][NB + 1];
+  __shared__ __align__(16) unsigned char shared_buf[TRI_BYTES > MAP_BYTES ? TRI_BYTES : MAP_BYTES];
   __shared__ c2<T> Stmp[TB][NB];
-  // srcmap[r - k0] = original row now at position r (rows k0 .. n-1, n <= 4096)
-  __shared__ int srcmap[4096];
+  __shared__ int rec[NL * RP_EX];
   __shared__ int nv[2 * RP_W];
-  __shared__ unsigned char emitted[4096];
+  auto Mtri = reinterpret_cast<c2<T> (*)[NB + 1]>(shared_buf);
+  // srcmap[r - k0] = original row now at position r (rows k0 .. n-1)
+  int* srcmap = reinterpret_cast<int*>(shared_buf);
+  unsigned char* emitted = shared_buf + sizeof(int) * RP_ROWS;
   for (int i = t; i < n - k0; i += 256) { srcmap[i] = k0 + i; emitted[i] = 0; }
+  for (int e = t; e < NL * RP_EX; e += 256) rec[e] = sub[(long long)b * NL * RP_EX + e];
   __syncthreads();
   for (int q = 0; q < NL; ++q) {
-    const int* R = sub + ((long long)b * NL + q) * RP_EX;
+    const int* R = rec + q * RP_EX;
     const int cnt = R[0];
     if (t < cnt) nv[t] = srcmap[R[1 + 2 * RP_W + t] - k0];   // sources before this leaf
     __syncthreads();
@@ -1116,7 +1124,7 @@ __global__ __launch_bounds__(256) void rpanel_finish_kernel(const c2<T>* __restr
     int cnt = 0;
     for (int k = 0; k < NB; ++k) { P[1 + cnt] = k0 + k; P[1 + 2 * NB + cnt] = srcmap[k]; ++cnt; }
     for (int q = 0; q < NL; ++q) {
-      const int* R = sub + ((long long)b * NL + q) * RP_EX;
+      const int* R = rec + q * RP_EX;
       for (int i = 0; i < R[0]; ++i) {
         const int pos = R[1 + i];
         if (pos >= k0 + NB && !emitted[pos - k0] && srcmap[pos - k0] != pos && cnt < 2 * NB) {
@@ -1130,6 +1138,7 @@ __global__ __launch_bounds__(256) void rpanel_finish_kernel(const c2<T>* __restr
     for (int e = cnt; e < 2 * NB; ++e) { P[1 + e] = -1; P[1 + 2 * NB + e] = -1; }
     P[0] = cnt;
   }
+  __syncthreads();                                   // the row map's LDS becomes the diagonal block
   for (int e = t; e < NB * NB; e += 256) Mtri[e / NB][e % NB] = A[(long long)(k0 + e / NB) * n + k0 + e % NB];
   __syncthreads();
   c2<T>* Li = Linv + (long long)b * inv_stride + (long long)step * NB * NB;
