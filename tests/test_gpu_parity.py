@@ -350,3 +350,30 @@ def test_results_do_not_depend_on_the_probes(N):
     assert max(np.min(np.abs(b - v)) for v in a) < 1e-5
     ra, rb = out[0][2], out[1][2]
     assert max(np.min(np.abs(rb - v)) / max(1, abs(v)) for v in ra) < 1e-12
+
+
+def test_update_timers(N):
+    # the paired update's event timers: on one stream the launches cannot overlap, so
+    # the union of their intervals is their sum; on two streams it lies between half
+    # the sum and the sum
+    n = 600
+    A = gen.gaussian(610, n)
+    prob = gen.qep(A + A.T, 0.1 * gen.gaussian(611, n), None)
+    reg = gen.Region(-1.0, 1.0, -1.0, 1.0, 2, 2)
+    F, V = gen.probes(612, n, 1), gen.probes(613, n, 4)
+    say("case update timers n=600, one and two streams")
+    for streams in (1, 2):
+        plan = N.nep_plan([prob], [reg], gen.Options(N=16, s=1, L=4, streams=streams, batch=16))
+        try:
+            N.nep_indicator(plan, [F], [V])
+            st = N.nep_get_stats(plan)
+        finally:
+            N.nep_destroy(plan)
+        # 64 node solves in 4 batches, 4 pairs of panels each (n = 600: k0 = 0, 128, 256, 384)
+        assert st["gemm_launches"] == 16 and st["gemm_flops"] > 0
+        tot, busy = st["ms_gemm"], st["ms_gemm_busy"]
+        assert 0 < busy <= tot * (1 + 1e-4) + 1e-3
+        if streams == 1:
+            assert busy >= tot * (1 - 1e-4) - 1e-3
+        else:
+            assert busy >= 0.5 * tot - 1e-3
