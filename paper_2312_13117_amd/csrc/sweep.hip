@@ -201,6 +201,10 @@ __global__ __launch_bounds__(256) void indicator_kernel(const double2* __restric
 // tiles of 64 over the concatenated columns of all tasks).  Column c of the product is
 // column c % m of task c / m; columns of converged tasks (active[t] == 0) are skipped.
 // Matrix cores, complex128; a real coefficient needs two of the four real products.
+// Operands go through LDS in chunks of 16 along the inner dimension (a 64 x 16 block
+// of A_k and the matching 16 x 64 block of X, each column scaled by its task's
+// phi_k(z)); the next chunk is loaded into registers while the current one is used.
+constexpr int RES_KC = 16;
 __global__ __launch_bounds__(256) void residual_kernel(ProblemDev pd, const double2* __restrict__ znode,
                                                        const double2* __restrict__ X, const double2* __restrict__ F,
                                                        int s, const double2* __restrict__ V, int L,
@@ -210,31 +214,26 @@ __global__ __launch_bounds__(256) void residual_kernel(ProblemDev pd, const doub
   const int ncol = nbatch * m;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int l16 = lane & 15, kq = lane >> 4;
-  const int rb = blockIdx.x * 64 + (wave >> 1) * 32;
-  const int cb = blockIdx.y * 64 + (wave & 1) * 32;
+  const int R0 = blockIdx.x * 64, C0 = blockIdx.y * 64;
+  const int rw = (wave >> 1) * 32, cw = (wave & 1) * 32;     // the wave's quarter of the tile
+  const int rb = R0 + rw, cb = C0 + cw;
   // skip tiles whose tasks have all converged
   if (active) {
     __shared__ int s_any;
     if (t == 0) s_any = 0;
     __syncthreads();
-    const int c = blockIdx.y * 64 + (t & 63);
+    const int c = C0 + (t & 63);
     if (t < 64 && c < ncol && active[c / m]) s_any = 1;
     __syncthreads();
     if (!s_any) return;
   }
-  int ctask[2], cq[2];
-  double2 ph[2][MAX_TERMS];
-#pragma unroll
-  for (int bj = 0; bj < 2; ++bj) {
-    const int c = cb + bj * 16 + l16;
-    const bool ok = c < ncol && (!active || active[c / m]);
-    ctask[bj] = ok ? c / m : -1;
-    cq[bj] = ok ? c % m : 0;
-#pragma unroll
-    for (int k = 0; k < MAX_TERMS; ++k)
-      ph[bj][k] = (ctask[bj] >= 0 && k < pd.nterms) ? phi_eval(pd.kind[k], pd.param[k], znode[ctask[bj]])
-                                                    : cmk<double>(0, 0);
-  }
+  // the column this thread stages into the X block (the same for every chunk)
+  const int sc = C0 + (t & 63);
+  const int stask = (sc < ncol && (!active || active[sc / m])) ? sc / m : -1;
+  const int sq = sc < ncol ? sc % m : 0;
+  __shared__ double2 As[64][RES_KC + 1];
+  __shared__ double2 Bs[RES_KC][64 + 1];
+  constexpr int QA = 64 * RES_KC / 256, QB = RES_KC * 64 / 256;
   d4 cre[2][2], cim[2][2];
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
@@ -246,58 +245,86 @@ __global__ __launch_bounds__(256) void residual_kernel(ProblemDev pd, const doub
     const double2* Ak = pd.A[k];
     if (!Ak) continue;
     const bool real = pd.real[k] != 0;
-    for (int kk = 0; kk < n; kk += 4) {
-      const int j = kk + kq;
-      double2 af[2], bf[2];
+    const double2 sph = stask >= 0 ? phi_eval(pd.kind[k], pd.param[k], znode[stask]) : cmk<double>(0, 0);
+    double2 pa[QA], pb[QB];
+    auto fetch = [&](int kk) {
 #pragma unroll
-      for (int bi = 0; bi < 2; ++bi) {
-        const int row = rb + bi * 16 + l16;
-        af[bi] = (row < n && j < n) ? Ak[(long long)row * n + j] : cmk<double>(0, 0);
+      for (int q = 0; q < QA; ++q) {
+        const int e = t + q * 256, row = R0 + e / RES_KC, col = kk + e % RES_KC;
+        pa[q] = (row < n && col < n) ? Ak[(long long)row * n + col] : cmk<double>(0, 0);
       }
 #pragma unroll
-      for (int bj = 0; bj < 2; ++bj) {
-        bf[bj] = (ctask[bj] >= 0 && j < n)
-                     ? cmul<double>(ph[bj][k], X[(long long)ctask[bj] * xstride + (long long)j * m + cq[bj]])
-                     : cmk<double>(0, 0);
+      for (int q = 0; q < QB; ++q) {
+        const int xr = kk + (t >> 6) + 4 * q;
+        pb[q] = (stask >= 0 && xr < n) ? X[(long long)stask * xstride + (long long)xr * m + sq] : cmk<double>(0, 0);
+      }
+    };
+    fetch(0);
+    for (int kk = 0; kk < n; kk += RES_KC) {
+      __syncthreads();                       // the previous chunk has been read
+#pragma unroll
+      for (int q = 0; q < QA; ++q) {
+        const int e = t + q * 256;
+        As[e / RES_KC][e % RES_KC] = pa[q];
       }
 #pragma unroll
-      for (int bi = 0; bi < 2; ++bi)
+      for (int q = 0; q < QB; ++q) Bs[(t >> 6) + 4 * q][t & 63] = cmul<double>(sph, pb[q]);
+      __syncthreads();
+      if (kk + RES_KC < n) fetch(kk + RES_KC);
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj) {
-          cre[bi][bj] = mfma16(af[bi].x, bf[bj].x, cre[bi][bj]);
-          cim[bi][bj] = mfma16(af[bi].x, bf[bj].y, cim[bi][bj]);
-        }
-      if (!real) {
+      for (int k4 = 0; k4 < RES_KC; k4 += 4) {
+        double2 af[2], bf[2];
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi) af[bi] = As[rw + bi * 16 + l16][k4 + kq];
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) bf[bj] = Bs[k4 + kq][cw + bj * 16 + l16];
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
           for (int bj = 0; bj < 2; ++bj) {
-            cre[bi][bj] = mfma16(-af[bi].y, bf[bj].y, cre[bi][bj]);
-            cim[bi][bj] = mfma16(af[bi].y, bf[bj].x, cim[bi][bj]);
+            cre[bi][bj] = mfma16(af[bi].x, bf[bj].x, cre[bi][bj]);
+            cim[bi][bj] = mfma16(af[bi].x, bf[bj].y, cim[bi][bj]);
           }
+        if (!real) {
+#pragma unroll
+          for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj) {
+              cre[bi][bj] = mfma16(-af[bi].y, bf[bj].y, cre[bi][bj]);
+              cim[bi][bj] = mfma16(af[bi].y, bf[bj].x, cim[bi][bj]);
+            }
+        }
       }
     }
   }
+  // epilogue: identity coefficients and R = B - T X for the wave's columns
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
+  for (int bj = 0; bj < 2; ++bj) {
+    const int c = cb + bj * 16 + l16;
+    const int ctask = (c < ncol && (!active || active[c / m])) ? c / m : -1;
+    if (ctask < 0) continue;
+    const int q = c % m;
+    double2 ph[MAX_TERMS];
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj) {
-      if (ctask[bj] < 0) continue;
+    for (int k = 0; k < MAX_TERMS; ++k)
+      ph[k] = (k < pd.nterms && !pd.A[k]) ? phi_eval(pd.kind[k], pd.param[k], znode[ctask]) : cmk<double>(0, 0);
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = rb + bi * 16 + acc_row<double>(lane, r);
         if (row >= n) continue;
-        const long long off = (long long)ctask[bj] * xstride + (long long)row * m + cq[bj];
+        const long long off = (long long)ctask * xstride + (long long)row * m + q;
         double2 tx = cmk<double>(cre[bi][bj][r], cim[bi][bj][r]);
         const double2 x = X[off];
 #pragma unroll
         for (int k = 0; k < MAX_TERMS; ++k)
-          if (k < pd.nterms && !pd.A[k]) tx = cfma<double>(tx, ph[bj][k], x);   // identity coefficient
-        const int q = cq[bj];
+          if (k < pd.nterms && !pd.A[k]) tx = cfma<double>(tx, ph[k], x);   // identity coefficient
         const double2 bv = (q < s) ? F[(long long)row * s + q] : V[(long long)row * L + (q - s)];
         R[off] = csub<double>(bv, tx);
       }
     }
+  }
 }
 
 // flags[k] = 1 if coefficient k has no nonzero imaginary part (identity: 1)
