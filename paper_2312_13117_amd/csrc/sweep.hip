@@ -205,7 +205,7 @@ __global__ __launch_bounds__(256) void indicator_kernel(const double2* __restric
 // of A_k and the matching 16 x 64 block of X, each column scaled by its task's
 // phi_k(z)); the next chunk is loaded into registers while the current one is used.
 constexpr int RES_KC = 16;
-__global__ __launch_bounds__(256) void residual_kernel(ProblemDev pd, const double2* __restrict__ znode,
+__global__ __launch_bounds__(256, 3) void residual_kernel(ProblemDev pd, const double2* __restrict__ znode,
                                                        const double2* __restrict__ X, const double2* __restrict__ F,
                                                        int s, const double2* __restrict__ V, int L,
                                                        long long xstride, int m, int nbatch,
