@@ -61,6 +61,22 @@ def refine_bound(prob, dk, Nn):
     return 4.0 * 2.0 ** -26 * 2.0 ** -24 * kappa
 
 
+def fp64_bound(prob, dk, Nn):
+    # two backward-stable complex128 solves differ by about kappa u64 (kappa = the node
+    # matrix's condition number, LAPACK's 1-norm estimate): eight times that at the
+    # worst node of the disk
+    from scipy.linalg import lapack
+    z, _ = oracle.nodes_weights(dk.c, dk.r, Nn)
+    kappa = 0.0
+    for zj in z:
+        T = oracle.assemble(prob, zj)
+        lu, _, info = lapack.zgetrf(T)
+        assert info == 0
+        rc, _ = lapack.zgecon(lu, np.linalg.norm(T, 1), norm="1")
+        kappa = max(kappa, 1.0 / rc)
+    return 8.0 * 2.0 ** -53 * kappa
+
+
 def check_sums(N, plan, prob, reg, opts, F, V, tol, disks=None):
     nd = plan.total_disks
     PfN, PfN2, C0, C1 = N.nep_copy_sums(plan, 0, nd)
@@ -81,9 +97,10 @@ def check_sums(N, plan, prob, reg, opts, F, V, tol, disks=None):
 
 # pivot 0 = partial pivoting, 1 = tournament (panels of > 128 rows go through the
 # chunk/merge tree: n = 300 and 700 take one and two merge levels).  Panel kernels by
-# rows: <= 256 in registers; <= 1024 (complex128) / 2048 (complex64, two rows per
-# thread above 1024) recursive leaves; more: the streaming panel (n = 1100,
-# complex128).  Orders >= 256 with <= 8 columns take the step-parallel solve.
+# rows: <= 256 in registers; <= 1024 recursive leaves of 8 columns in pairs; 1025 to
+# 2048 in complex64 leaves of 16 columns, two rows per thread; more: the streaming
+# panel (n = 1100, complex128; the largest orders below).  Orders >= 256 with <= 8
+# columns take the step-parallel solve.
 @pytest.mark.parametrize("n,Nn,s,L,prec,pivot", [(4, 8, 1, 2, 0, 0), (37, 8, 1, 4, 0, 0), (100, 16, 2, 6, 0, 0),
                                                  (200, 16, 1, 8, 0, 0), (200, 16, 1, 8, 1, 0),
                                                  (130, 12, 3, 5, 1, 0), (300, 8, 1, 4, 0, 0), (700, 8, 1, 4, 1, 0),
@@ -108,6 +125,29 @@ def test_sums_ragged_sizes(N, n, Nn, s, L, prec, pivot):
             I, Iq = oracle.indicator(sw.PfN, sw.PfN2, sw.scale)
             assert flags[d] == (I > opts.tol_ind)
             assert np.allclose(prof[d], sw.profile, rtol=1e-10 if prec == 0 else 1e-9)
+    finally:
+        N.nep_destroy(plan)
+
+
+@pytest.mark.parametrize("n,prec", [(2048, 0), (2048, 1), (3000, 1), (4096, 0)])
+def test_largest_orders_sampled(N, n, prec):
+    # up to the library's largest order: panels of more than 1024 (complex128) or 2048
+    # (complex64) rows take the streaming panel; one disk of four nodes
+    say(f"case largest orders n={n} precision={prec}")
+    A = gen.gaussian(100 + n, n)
+    B = gen.gaussian(200 + n, n)
+    prob = gen.qep(A + A.T, 0.1 * B, None)
+    reg = gen.Region(-1.0, 1.0, -0.5, 0.5, 1, 1)
+    opts = gen.Options(N=4, s=1, L=2, precision=prec)
+    F, V = gen.probes(1, n, 1), gen.probes(2, n, 2)
+    plan = N.nep_plan([prob], [reg], opts)
+    try:
+        _, _, _, st = N.nep_indicator(plan, [F], [V])
+        assert st in (0, 2)
+        # at these orders the rounding of either solver reaches the 1e-12 of the
+        # smaller cases: the bound follows the node matrices' conditioning
+        tol = max(1e-12, fp64_bound(prob, oracle.cover(reg)[0], opts.N)) if prec == 0 else 1e-11
+        check_sums(N, plan, prob, reg, opts, F, V, tol)
     finally:
         N.nep_destroy(plan)
 
