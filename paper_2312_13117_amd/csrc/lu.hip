@@ -841,9 +841,9 @@ __global__ __launch_bounds__(4 * R) void tslu_root_kernel(c2<T>* __restrict__ W,
 // the W rows of U to its right inside the panel.  A rank-W update of the rows below
 // follows as a launch of its own (many workgroups per matrix).  A finishing kernel
 // composes the leaves' exchanges into the step's one and forms inv(L11) and inv(U11).
-// Leaf shapes: complex128 uses 8-column leaves of 512 threads (two rows each), whose
-// registers leave room on the CU for a workgroup of the other stream's update;
-// complex64 uses 16-column leaves of 1024 threads (one or two rows each).
+// Leaf shapes: panels of up to 1024 rows use 8-column leaves of 256 threads (four rows
+// each; fewer waves per barrier) in pairs, in both precisions; complex64 panels of
+// 1025 to 2048 rows use 16-column leaves of 1024 threads (two rows each).
 constexpr int RP_NTMAX = 1024, RP_WMAX = 16;
 constexpr int rp_ex(int w) { return 1 + 4 * w; }   // leaf exchange record: cnt, pos[2W], src[2W]
 constexpr int RP_EXMAX = rp_ex(8) * 8;             // ints per matrix for the records of one step
@@ -1940,9 +1940,9 @@ hipError_t lu_factor_batch(c2<T>* W, long long mstride, int n, int nbatch, void*
         constexpr int LW = 8;
         for (int q = 0; q < NB / LW; ++q) {
           if (q & 1)
-            rpanel_leaf_kernel<T, 8, 512, 2, true><<<nbatch, 512, 0, st>>>(W, mstride, n, k0, q, sub, info);
+            rpanel_leaf_kernel<T, 8, 256, 4, true><<<nbatch, 256, 0, st>>>(W, mstride, n, k0, q, sub, info);
           else
-            rpanel_leaf_kernel<T, 8, 512, 2, false><<<nbatch, 512, 0, st>>>(W, mstride, n, k0, q, sub, info);
+            rpanel_leaf_kernel<T, 8, 256, 4, false><<<nbatch, 256, 0, st>>>(W, mstride, n, k0, q, sub, info);
           if ((q & 1) && q < NB / LW - 1) {
             const int tiles = (n - (k0 + LW * (q - 1)) - 2 * LW + 63) / 64;
             rpanel_update_kernel<T, 2 * LW><<<dim3((unsigned)(nbatch * tiles)), 256, 0, st>>>(W, mstride, n, k0,
