@@ -833,7 +833,7 @@ __global__ __launch_bounds__(4 * R) void tslu_root_kernel(c2<T>* __restrict__ W,
 }
 
 // ----------------------------------------------------------------------------- recursive panel
-// Panels of more than 256 rows under partial pivoting, as leaves of W columns.  A
+// Panels of more than 128 rows under partial pivoting, as leaves of W columns.  A
 // leaf holds rows r0 .. n-1 of its W columns in registers (RPT rows per thread, NT
 // threads), runs partial pivoting on them (one barrier per column; 64-bit keys hold
 // the magnitude's top bits and the row), writes the factored columns at their
@@ -1928,7 +1928,7 @@ hipError_t lu_factor_batch(c2<T>* W, long long mstride, int n, int nbatch, void*
       // the whole panel in registers (either pivot choice: this is partial pivoting)
       tslu_root_kernel<T, NB, 128, true><<<nbatch, 512, 0, st>>>(W, mstride, n, k0, nbk, s, 0, nullptr, perm,
                                                                   perm_stride, nullptr, Linv, Uinv, inv_stride, info);
-    } else if (rows <= 256) {
+    } else if (rows <= 256 && pivot != LU_PIVOT_PARTIAL) {
       tslu_root_kernel<T, NB, 256, true><<<nbatch, 1024, 0, st>>>(W, mstride, n, k0, nbk, s, 0, nullptr, perm,
                                                                    perm_stride, nullptr, Linv, Uinv, inv_stride, info);
     } else if (pivot == LU_PIVOT_PARTIAL && rows <= (sizeof(T) == 4 ? 2 : 1) * RP_NTMAX) {

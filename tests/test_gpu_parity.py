@@ -97,7 +97,8 @@ def check_sums(N, plan, prob, reg, opts, F, V, tol, disks=None):
 
 # pivot 0 = partial pivoting, 1 = tournament (panels of > 128 rows go through the
 # chunk/merge tree: n = 300 and 700 take one and two merge levels).  Panel kernels by
-# rows: <= 256 in registers; <= 1024 recursive leaves of 8 columns in pairs; 1025 to
+# rows: <= 128 in registers (<= 256 under tournament pivoting); <= 1024 recursive
+# leaves of 8 columns in pairs; 1025 to
 # 2048 in complex64 leaves of 16 columns, two rows per thread; more: the streaming
 # panel (n = 1100, complex128; the largest orders below).  Orders >= 256 with <= 8
 # columns take the step-parallel solve.
