@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -402,14 +403,26 @@ extern "C" nep_status nep_plan(const nep_problem* probs, int nprob, const nep_re
   PCHK(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming));
   for (int q = 0; q < nep_plan_t::MAX_WS; ++q) PCHK(hipEventCreateWithFlags(&P->ev_join[q], hipEventDisableTiming));
   {
+    // which coefficients are real; problems that share their coefficient buffers (the
+    // cells of one problem given as separate regions) are checked once
     DevBuf rf;
     PCHK(rf.alloc(sizeof(int) * MAX_TERMS));
+    std::map<std::vector<const void*>, int> seen;
     for (int p = 0; p < nprob; ++p) {
+      ProblemDev& d = P->pd[p];
+      if (d.nterms == 0) continue;
+      std::vector<const void*> key{reinterpret_cast<const void*>(static_cast<intptr_t>(d.n))};
+      for (int k = 0; k < d.nterms; ++k) key.push_back(d.A[k]);
+      auto it = seen.find(key);
+      if (it != seen.end()) {
+        for (int k = 0; k < d.nterms; ++k) d.real[k] = P->pd[it->second].real[k];
+        continue;
+      }
       int h[MAX_TERMS] = {0, 0, 0, 0};
-      if (P->pd[p].nterms == 0) continue;
-      PCHK(launch_is_real(P->pd[p], rf.as<int>(), P->st));
-      PCHK(hipMemcpy(h, rf.p, sizeof(int) * P->pd[p].nterms, hipMemcpyDeviceToHost));
-      for (int k = 0; k < P->pd[p].nterms; ++k) P->pd[p].real[k] = h[k];
+      PCHK(launch_is_real(d, rf.as<int>(), P->st));
+      PCHK(hipMemcpy(h, rf.p, sizeof(int) * d.nterms, hipMemcpyDeviceToHost));
+      for (int k = 0; k < d.nterms; ++k) d.real[k] = h[k];
+      seen.emplace(std::move(key), p);
     }
     rf.release();
   }
