@@ -180,6 +180,7 @@ def nep_plan(problems, regions, opts, stream=None) -> Plan:
     keep = []
     cp = (nep_problem * len(problems))()
     assembled = []
+    split_terms = {}
     for i, pr in enumerate(problems):
         if _is_circle(pr):
             assembled.append((i, None))
@@ -192,6 +193,9 @@ def nep_plan(problems, regions, opts, stream=None) -> Plan:
             assembled.append((i, ctx))
             cp[i] = nep_problem(pr.n, 0, None, None, None)
             continue
+        if id(pr) in split_terms:            # the same problem object again (one entry per cell)
+            cp[i] = split_terms[id(pr)]
+            continue
         devs = []
         for A in pr.coeffs:
             t = _dev_complex(A, torch)
@@ -200,8 +204,9 @@ def nep_plan(problems, regions, opts, stream=None) -> Plan:
         arr = (C.c_void_p * len(devs))(*devs)
         kinds = (C.c_int * len(devs))(*pr.phi_kind)
         pars = (C.c_double * len(devs))(*pr.phi_param)
-        keep += [arr, kinds, pars]
+        keep += [arr, kinds, pars, pr]
         cp[i] = nep_problem(pr.n, len(devs), arr, kinds, pars)
+        split_terms[id(pr)] = cp[i]
     cr = (nep_region * len(regions))()
     for i, r in enumerate(regions):
         cr[i] = nep_region(r.x0, r.x1, r.y0, r.y1, r.nx, r.ny)
