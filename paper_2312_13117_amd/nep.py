@@ -237,6 +237,18 @@ def nep_plan(problems, regions, opts, stream=None) -> Plan:
     return Plan(h, len(problems), [p.n for p in problems], opts.N, opts.s, opts.L, nd, keep)
 
 
+def _dev_list(xs, torch):
+    """_dev_complex over a per-entry list; an object given for many entries (the same
+    probe block for every cell) is converted once."""
+    done = {}
+    out = []
+    for x in xs:
+        if id(x) not in done:
+            done[id(x)] = _dev_complex(x, torch)
+        out.append(done[id(x)])
+    return out
+
+
 def _ptr_array(tensors):
     return (C.c_void_p * len(tensors))(*[t.data_ptr() for t in tensors])
 
@@ -246,8 +258,8 @@ def nep_indicator(plan: Plan, F, V=None, want_profiles: bool = False):
     Returns (ind [nd x s], flags [nd] bool, profiles [nd x N x s] or None, status)."""
     import torch
     L = lib()
-    Ft = [_dev_complex(f, torch) for f in F]
-    Vt = [_dev_complex(v, torch) for v in V] if V is not None else None
+    Ft = _dev_list(F, torch)
+    Vt = _dev_list(V, torch) if V is not None else None
     plan.keep_alive.append(Ft)            # the plan may re-sweep with F in nep_beyn
     nd = plan.total_disks
     ind = np.zeros(nd * plan.s)
@@ -274,7 +286,7 @@ def nep_beyn(plan: Plan, disk_ids: Sequence[int], V=None, want_vectors: bool = F
     vt = None
     if want_vectors and k > 0:
         vt = torch.zeros((k, max(plan.n), plan.L), dtype=torch.complex128, device="cuda")
-    Vt = [_dev_complex(v, torch) for v in V] if V is not None else None
+    Vt = _dev_list(V, torch) if V is not None else None
     st = L.nep_beyn(plan.handle, ids.ctypes.data_as(C.POINTER(C.c_int32)), k,
                     _ptr_array(Vt) if Vt is not None else None, _ptr(eig),
                     p.ctypes.data_as(C.POINTER(C.c_int32)), sv.ctypes.data_as(C.POINTER(C.c_double)),
