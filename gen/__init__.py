@@ -191,6 +191,13 @@ def workload_delay(count: int = 64, sizes: Sequence[int] = (128, 256, 512, 1024,
     return Workload("delay_uneven", probs, [reg] * len(probs), opts, F, [None] * len(probs))
 
 
+def delay_sampled_rectangles(p: int, count: int = 8, cells: int = 128) -> List[int]:
+    """The rectangles of delay problem p checked one by one when the problem is too
+    large to check whole: `count` distinct cover indices from default_rng(4000 + p)."""
+    rng = np.random.default_rng(4000 + p)
+    return sorted(int(i) for i in rng.choice(cells, size=count, replace=False))
+
+
 def elementwise_delay(n: int, seed: int, tau_lo: float = 0.5, tau_hi: float = 2.0) -> ElementwiseDelay:
     """A0 = G0, A1 = G1 (Gaussian / sqrt(n), seeds `seed`, `seed` + 1), tau_ij ~
     U[tau_lo, tau_hi] from rng(seed + 2)."""

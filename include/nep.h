@@ -215,11 +215,18 @@ nep_status nep_plan(const nep_problem* probs, int nprob, const nep_region* regs,
  *   F_dev[p]   device, complex128 n_p x s, the indicator probes (unit columns)
  *   V_dev      NULL, or V_dev[p] = device complex128 n_p x L (Beyn probes)
  *   ind        host double [total_disks * s]: I_q of eq (3.1) per probe column, read
- *              as || P f|_N ./ P f|_{N/2} ||_2 / sqrt(n) (elementwise ratio); a
- *              non-finite ratio is reported as +inf; a column whose half-rule sum is at
- *              most 1e-9 S_q, S_q = sum_j |w_j| ||x_j[:, q]||, is reported as 0 (both sums
- *              are then rounding noise, and so is their ratio)
- *   flags      host uint8 [total_disks]: 1 iff max_q I_q > tol_ind (or non-finite)
+ *              as || P f|_N ./ P f|_{N/2} ||_2 / sqrt(n) (elementwise ratio, each entry
+ *              and the norm scaled so that no square overflows or underflows); a
+ *              non-finite ratio is reported as +inf.  A column whose two sums are both
+ *              at most 2^-30 times their summand sizes, S_N = sum_j |w_j| ||x_j[:, q]||
+ *              and S_half = sum over the 1-based even nodes of 2 |w_j| ||x_j[:, q]||,
+ *              is reported as 0: both sums are then rounding noise (a normwise error
+ *              of n u kappa per node solution, with n <= 2^12 and kappa <= 2^10 far
+ *              from every eigenvalue, is at most 2^-31 of S), and so is their ratio
+ *   flags      host uint8 [total_disks]: 1 iff max_q I_q > tol_ind, or one of the
+ *              disk's nodes had an exact zero pivot (complex128 LU) or a non-finite
+ *              solution entry (the conservative flag of NEP_WARN_SINGULAR_NODE); in
+ *              mixed precision the complex128 re-solve decides a zero pivot
  *   profiles   host double [total_disks * N * s] or NULL: ||x_j[:, q]||_2 per node
  * The half rule uses the 1-based even nodes x_2, x_4, ..., x_N with weights 2 w_j.
  * Returns NEP_OK, NEP_WARN_SINGULAR_NODE or NEP_WARN_REFINE_FALLBACK, or an error. */

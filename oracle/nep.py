@@ -167,7 +167,16 @@ class DiskSweep:
     C0: Optional[np.ndarray]  # n x L : eq (3.2)
     C1: Optional[np.ndarray]  # n x L : eq (3.3)
     profile: np.ndarray      # N x s : ||x_j|| per node and probe column
-    scale: np.ndarray        # s : sum_j |w_j| ||x_j[:, q]||, the size of the summands
+    scale: np.ndarray        # s : sum_j |w_j| ||x_j[:, q]||, the size of the summands of P f|_N
+    scale_half: np.ndarray   # s : sum_{j even} 2 |w_j| ||x_j[:, q]||, the same for P f|_{N/2}
+
+    @property
+    def scales(self) -> Tuple[np.ndarray, np.ndarray]:
+        return self.scale, self.scale_half
+
+    def indicator(self) -> Tuple[float, np.ndarray]:
+        """eq (3.1) of this disk, with the rounding-noise floor (see ``indicator``)."""
+        return indicator(self.PfN, self.PfN2, self.scales)
 
 
 def sweep_disk(prob: Problem, c: complex, r: float, N: int, F: np.ndarray,
@@ -199,33 +208,59 @@ def sweep_disk(prob: Problem, c: complex, r: float, N: int, F: np.ndarray,
             XV = X[:, s:]
             C0 += w[j] * XV
             C1 += (w[j] * z[j]) * XV
-        profile[j] = np.linalg.norm(x, axis=0)
+        profile[j] = [norm2(x[:, q]) for q in range(s)]
     scale = (np.abs(w)[:, None] * profile).sum(axis=0)
-    return DiskSweep(PfN, PfN2, C0, C1, profile, scale)
+    scale_half = (2.0 * np.abs(w[1::2])[:, None] * profile[1::2]).sum(axis=0)
+    return DiskSweep(PfN, PfN2, C0, C1, profile, scale, scale_half)
 
 
-# A half-rule sum below this fraction of its summand scale is rounding noise.
-NOISE_FLOOR = 1e-9
+def norm2(v: np.ndarray) -> float:
+    """Euclidean norm of a vector, scaled by its largest modulus so that entries far
+    outside 1e+-154 neither overflow nor underflow when squared."""
+    a = np.abs(np.asarray(v).ravel())
+    m = float(a.max()) if a.size else 0.0
+    if m == 0.0 or not math.isfinite(m):
+        return m
+    return m * math.sqrt(float(np.sum((a / m) ** 2)))
 
 
-def indicator(PfN: np.ndarray, PfN2: np.ndarray, scale: Optional[np.ndarray] = None,
+# Rounding-noise floor of a quadrature sum relative to the size of its summands.
+# A sum of N node solutions, each with a normwise relative error eps, lies within
+# (eps + gamma_N) * S of the exact sum, S = sum_j |weight_j| ||x_j||.  A backward-stable
+# LU gives eps <= c n u kappa; with n <= 2^12, u = 2^-53 and kappa <= 2^10 (the floor
+# can only matter on disks far from every eigenvalue, where the node matrices are well
+# conditioned) n u kappa <= 2^-31, and the floor is twice that.
+NOISE_FLOOR = 2.0 ** -30
+
+
+def indicator(PfN: np.ndarray, PfN2: np.ndarray, scales=None,
               floor: float = NOISE_FLOOR) -> Tuple[float, np.ndarray]:
     """Ratio indicator of eq (3.1), read as in the appendix's indicator routine: the
     elementwise ratio P f|_N ./ P f|_{N/2}, its 2-norm, divided by sqrt(n).  With s > 1
     probe columns the disk's indicator is the maximum over columns.  A non-finite
     column (0/0 or x/0) gives +inf, which flags the disk.
 
-    Reading (floating point): for a disk far from every eigenvalue both sums fall below
-    the rounding level of their summands, and their ratio is noise of order one, which
-    contradicts the stated I ~ e^{-CN/2}.  A column whose half-rule sum is at most
-    floor * scale_q (scale_q = sum_j |w_j| ||x_j[:, q]||) therefore has I_q = 0."""
+    Reading (floating point): far from every eigenvalue both quadrature errors fall
+    below the rounding level of their summands and their ratio is noise of order one,
+    where the paper states I ~ e^{-CN/2}.  ``scales`` = (S_N, S_half) per column, the
+    summand sizes of the two rules (sum_j |w_j| ||x_j||, and over the 1-based even
+    nodes with weights 2|w_j|).  A column whose sums are both at most ``floor`` times
+    their own summand size, all four numbers finite, has I_q = 0.  A node next to an
+    eigenvalue outside the circle dominates its rule's summands and that rule's sum
+    alike, so it never brings a column under the floor."""
     n = PfN.shape[0]
-    with np.errstate(divide="ignore", invalid="ignore"):
-        ratio = PfN / PfN2
-        Iq = np.linalg.norm(ratio, axis=0) / math.sqrt(n)
-    Iq = np.where(np.isfinite(Iq), Iq, np.inf)
-    if scale is not None:
-        Iq = np.where(np.linalg.norm(PfN2, axis=0) <= floor * np.asarray(scale), 0.0, Iq)
+    s = PfN.shape[1]
+    Iq = np.empty(s)
+    for q in range(s):
+        with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
+            ratio = PfN[:, q] / PfN2[:, q]      # complex division, scaled by numpy
+        v = norm2(ratio) / math.sqrt(n) if np.all(np.isfinite(ratio)) else math.inf
+        Iq[q] = v if math.isfinite(v) else math.inf
+        if scales is not None:
+            SN, SH = float(scales[0][q]), float(scales[1][q])
+            a, b = norm2(PfN[:, q]), norm2(PfN2[:, q])
+            if all(math.isfinite(t) for t in (a, b, SN, SH)) and a <= floor * SN and b <= floor * SH:
+                Iq[q] = 0.0
     return float(np.max(Iq)), Iq
 
 
@@ -344,7 +379,7 @@ def pmcimb(prob: Problem, reg: Region, opts: Options, F: np.ndarray,
     for d in idx:
         dk = disks[d]
         sw = sweep_disk(prob, dk.c, dk.r, opts.N, F, V)
-        I, Iq = indicator(sw.PfN, sw.PfN2, sw.scale)
+        I, Iq = sw.indicator()
         sweeps.append(sw)
         ind.append(I)
         ind_cols.append(Iq)

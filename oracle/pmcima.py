@@ -32,7 +32,7 @@ from typing import List, Sequence, Tuple
 import numpy as np
 
 from gen import Problem, Region
-from .nep import assemble, cover, indicator, sweep_disk
+from .nep import assemble, cover, sweep_disk
 
 Cell = Tuple[float, float, float, float]          # x0, x1, y0, y1
 
@@ -103,7 +103,7 @@ def pmcima(prob: Problem, region: Region, F: np.ndarray, N: int = 16, tol_ind: f
         ind = np.zeros(len(disks))
         for i, (_, c, r) in enumerate(disks):
             sw = sweep_disk(prob, c, r, N, F, None)
-            ind[i] = indicator(sw.PfN, sw.PfN2, sw.scale)[0]
+            ind[i] = sw.indicator()[0]
         flags = ind > tol_ind
         all_disks.append(disks)
         all_ind.append(ind)
@@ -121,3 +121,28 @@ def pmcima(prob: Problem, region: Region, F: np.ndarray, N: int = 16, tol_ind: f
         res.vectors = np.asarray([v for v, _ in vs]).reshape(len(eigs), prob.n)
         res.sigma = np.asarray([s for _, s in vs])
     return res
+
+
+def sim_quadtree_labels(prob: Problem, root: Cell, depth: int, F: np.ndarray, N: int = 32,
+                        tol_ind: float = 0.1) -> List[Tuple[int, Cell, np.ndarray]]:
+    """The SIM recursion of Section 2.1 (Step 1.b of pmCIMa) over a quadtree below
+    `root`: every flagged cell is split into its four quadrants (cover order of a 2 x 2
+    split) and each quadrant's disk is screened with the indicator of eq (3.1), down to
+    `depth` levels below the root.  The root itself is always split: for a matrix
+    polynomial of degree >= 2 a circle around the whole spectrum gives P f = 0, so its
+    indicator says nothing.  Returns one record per split cell, level by level and in
+    cover order within a level: (level of the split cell, the cell, indicators of its
+    four quadrants); a quadrant is flagged iff its indicator exceeds tol_ind."""
+    out = []
+    parents = [root]
+    for level in range(depth):
+        nxt = []
+        for cell in parents:
+            ch = children(cell)
+            ind = np.array([sweep_disk(prob, c, r, N, F, None).indicator()[0] for _, c, r in ch])
+            fl = ind > tol_ind
+            out.append((level, cell, ind))
+            if level + 1 < depth:
+                nxt.extend(ch[k][0] for k in range(4) if fl[k])
+        parents = nxt
+    return out

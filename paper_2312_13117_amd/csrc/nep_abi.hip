@@ -112,7 +112,8 @@ struct nep_plan {
   Workspace ws[MAX_WS];
   Workspace w64;
   hipEvent_t ev_fork = nullptr, ev_join[MAX_WS] = {nullptr, nullptr, nullptr};
-  DevBuf sing;
+  DevBuf sing;                        // per task: exact zero pivot of the complex128 LU
+  DevBuf nonfin;                      // per task: non-finite solution entry (set by the sums)
   DevBuf bscr, beig, bp, bsv, bkeep, bstat, bvec, bids;
   DevBuf vest;
   int batch = 0;
@@ -373,6 +374,7 @@ extern "C" nep_status nep_plan(const nep_problem* probs, int nprob, const nep_re
   PCHK(P->tnode.alloc(sizeof(double2) * (size_t)nd * N));
   PCHK(P->fbflag.alloc(sizeof(int) * (size_t)nd * N));
   PCHK(P->sing.alloc(sizeof(int) * (size_t)nd * N));
+  PCHK(P->nonfin.alloc(sizeof(int) * (size_t)nd * N));
   // factor workspace
   int ntask_max = 0;
   for (int p = 0; p < nprob; ++p) ntask_max = std::max(ntask_max, (regs[p].nx * regs[p].ny) * N);
@@ -442,7 +444,7 @@ extern "C" void nep_destroy(nep_plan_t* P) {
   for (auto& w : P->ws) if (w.st) hipStreamSynchronize(w.st);
   DevBuf* bufs[] = {&P->dev_dn, &P->dev_ix, &P->dev_iy, &P->dev_soff, &P->dev_w, &P->dev_z, &P->dev_r, &P->PfN, &P->PfN2,
                     &P->C0, &P->C1, &P->prof, &P->ind, &P->flags, &P->X, &P->xoff, &P->tnode, &P->dlist,
-                    &P->sing, &P->bscr, &P->beig, &P->bp, &P->bsv, &P->bkeep, &P->bstat, &P->bvec, &P->bids,
+                    &P->sing, &P->nonfin, &P->bscr, &P->beig, &P->bp, &P->bsv, &P->bkeep, &P->bstat, &P->bvec, &P->bids,
                     &P->vest};
   for (DevBuf* b : bufs) b->release();
   for (auto& w : P->ws) w.release();
@@ -535,6 +537,7 @@ static nep_status ensure_fp64_ws(nep_plan_t* P, int n, int B) {
 struct FbTask {
   const double2* z;   // device: the node
   double2* x;         // device: the node's n x m solution slot
+  int* sing;          // device: the node's singular flag
 };
 
 static nep_status fallback_solves(nep_plan_t* P, int prob, const SweepCall& sc, const std::vector<FbTask>& tasks) {
@@ -563,6 +566,14 @@ static nep_status fallback_solves(nep_plan_t* P, int prob, const SweepCall& sc, 
     for (int i = 0; i < c; ++i)
       HIPCHK(P, hipMemcpyAsync(tasks[c0 + i].x, xb + (size_t)i * n * m, sizeof(double2) * (size_t)n * m,
                                hipMemcpyDeviceToDevice, st));
+    // an exact zero pivot of the complex128 LU marks the node singular, as in a
+    // complex128 sweep (its disk is then flagged)
+    std::vector<int> info(c);
+    HIPCHK(P, hipMemcpyAsync(info.data(), P->w64.info.p, sizeof(int) * c, hipMemcpyDeviceToHost, st));
+    HIPCHK(P, hipStreamSynchronize(st));
+    static const int one = 1;
+    for (int i = 0; i < c; ++i)
+      if (info[i]) HIPCHK(P, hipMemcpy(tasks[c0 + i].sing, &one, sizeof(int), hipMemcpyHostToDevice));
     P->stats.refine_fallbacks += c;
   }
   HIPCHK(P, hipStreamSynchronize(st));
@@ -599,8 +610,10 @@ static nep_status sweep_batch(nep_plan_t* P, Workspace& w, int prob, const doubl
   const double tol = std::ldexp(1.0, -26);
   double2* Rb = w.R.as<double2>();
   tmark(P, PH_REFINE, true, w.st);
-  HIPCHK(P, launch_fill_int(w.active.as<int>(), 1, nb, w.st));
-  HIPCHK(P, launch_fill_int(w.active.as<int>() + nb, 0, nb, w.st));   // diverged flags
+  // a node whose complex64 LU met an exact zero pivot is not refined (the correction
+  // solves cannot reduce its residual) but re-solved in complex128, whose LU decides
+  // whether the node is singular
+  HIPCHK(P, launch_refine_init(w.info.as<int>(), nb, w.active.as<int>(), w.active.as<int>() + nb, w.st));
   // every sweep is issued (tasks that have converged are masked off inside the
   // kernels) and no decision waits for the host, so the other worker stream never
   // runs dry; the tasks needing a complex128 re-solve are listed in fb_out and
@@ -667,12 +680,15 @@ static nep_status run_sums(nep_plan_t* P, const SweepCall& sc, const SweepLayout
   const int N = P->opt.N, s = sc.s, L = sc.L, m = s + L;
   double2* X = P->X.as<double2>();
   tmark(P, PH_SUMS, true, P->st);
+  // non-finite solutions are found again by every pass of the sums (complex128
+  // re-solves after a mixed-precision sweep replace the entries that were)
+  HIPCHK(P, launch_fill_int(P->nonfin.as<int>(), 0, (int)sc.disks.size() * N, P->st));
   for (const auto& g : lay.groups) {
     const int n = g.n;
     HIPCHK(P, launch_sums(X + lay.xoff[g.li], (long long)n * m, P->dev_w.as<double2>(), P->dev_z.as<double2>(), N,
                           n, s, L, P->PfN.as<double2>(), P->PfN2.as<double2>(), P->C0.as<double2>(),
                           P->C1.as<double2>(), P->dlist.as<int>() + g.li, g.lj - g.li, P->dev_soff.as<long long>(),
-                          P->st));
+                          P->nonfin.as<int>() + (long long)g.li * N, P->st));
     if (s > 0 && sc.s == P->opt.s)
       HIPCHK(P, launch_profile(X + lay.xoff[g.li], (long long)n * m, N, n, s, m, P->prof.as<double>(),
                                P->dlist.as<int>() + g.li, g.lj - g.li, P->st));
@@ -733,7 +749,8 @@ static nep_status resolve_fallbacks(nep_plan_t* P, const SweepCall& sc, const Sw
     for (int li = g.li; li < g.lj; ++li)
       for (int j = 0; j < N; ++j)
         if (fb[(size_t)li * N + j])
-          tasks.push_back({tn + (size_t)li * N + j, X + lay.xoff[li] + (long long)j * g.n * m});
+          tasks.push_back({tn + (size_t)li * N + j, X + lay.xoff[li] + (long long)j * g.n * m,
+                           P->sing.as<int>() + (size_t)li * N + j});
     nep_status e = fallback_solves(P, P->d_prob[sc.disks[g.li]], sc, tasks);
     if (e != NEP_OK) return e;
     *count += (int)tasks.size();
@@ -752,6 +769,14 @@ static nep_status run_sweep(nep_plan_t* P, const SweepCall& sc, bool* fallback) 
   r = resolve_fallbacks(P, sc, lay, &cnt);
   if (cnt > 0) *fallback = true;
   return r;
+}
+
+// eq (3.1) over every disk of the plan, on the plan stream
+static hipError_t launch_plan_indicator(nep_plan_t* P) {
+  return launch_indicator(P->PfN.as<double2>(), P->PfN2.as<double2>(), P->dev_dn.as<int>(),
+                          P->dev_soff.as<long long>(), P->opt.s, P->opt.tol_ind, P->ind.as<double>(),
+                          P->flags.as<unsigned char>(), P->sing.as<int>(), P->nonfin.as<int>(), P->opt.N,
+                          P->prof.as<double>(), P->dev_r.as<double>(), INDICATOR_NOISE_FLOOR, P->nd, P->st);
 }
 
 // Graph mode: capture the device work of the full sweep (every disk) and the
@@ -774,11 +799,7 @@ static nep_status capture_sweep(nep_plan_t* P, const SweepCall& sc, const SweepL
   if (e == hipSuccess) {
     r = run_sweep_device(P, sc, lay);
     if (r == NEP_OK)
-      r = (launch_indicator(P->PfN.as<double2>(), P->PfN2.as<double2>(), P->dev_dn.as<int>(),
-                            P->dev_soff.as<long long>(), P->opt.s, P->opt.tol_ind, P->ind.as<double>(),
-                            P->flags.as<unsigned char>(), P->sing.as<int>(), P->opt.N, P->prof.as<double>(),
-                            P->dev_r.as<double>(), INDICATOR_NOISE_FLOOR, P->nd, P->st) == hipSuccess)
-              ? NEP_OK : NEP_ERR_HIP;
+      r = launch_plan_indicator(P) == hipSuccess ? NEP_OK : NEP_ERR_HIP;
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(P->st, &g);
     if (r == NEP_OK && e2 != hipSuccess) r = fail(P, NEP_ERR_HIP, "graph capture: %s", hipGetErrorString(e2));
@@ -840,20 +861,14 @@ extern "C" nep_status nep_indicator(nep_plan_t* P, const void* const* F_dev, con
       if (r != NEP_OK) return r;
       if (cnt > 0) {
         fb = true;
-        HIPCHK(P, launch_indicator(P->PfN.as<double2>(), P->PfN2.as<double2>(), P->dev_dn.as<int>(),
-                                   P->dev_soff.as<long long>(), P->opt.s, P->opt.tol_ind, P->ind.as<double>(),
-                                   P->flags.as<unsigned char>(), P->sing.as<int>(), P->opt.N, P->prof.as<double>(),
-                                   P->dev_r.as<double>(), INDICATOR_NOISE_FLOOR, P->nd, P->st));
+        HIPCHK(P, launch_plan_indicator(P));
       }
     }
   } else {
     tmark(P, PH_TOTAL, true, P->st);
     nep_status r = run_sweep(P, sc, &fb);
     if (r != NEP_OK) return r;
-    HIPCHK(P, launch_indicator(P->PfN.as<double2>(), P->PfN2.as<double2>(), P->dev_dn.as<int>(),
-                               P->dev_soff.as<long long>(), P->opt.s, P->opt.tol_ind, P->ind.as<double>(),
-                               P->flags.as<unsigned char>(), P->sing.as<int>(), P->opt.N, P->prof.as<double>(),
-                               P->dev_r.as<double>(), INDICATOR_NOISE_FLOOR, P->nd, P->st));
+    HIPCHK(P, launch_plan_indicator(P));
   }
   tmark(P, PH_TOTAL, false, P->st);
   HIPCHK(P, hipMemcpyAsync(ind, P->ind.p, sizeof(double) * P->nd * P->opt.s, hipMemcpyDeviceToHost, P->st));
@@ -867,9 +882,11 @@ extern "C" nep_status nep_indicator(nep_plan_t* P, const void* const* F_dev, con
   P->swept_with_V = sc.L > 0;
   P->last_F.assign(F_dev, F_dev + P->nprob);
   {
-    std::vector<int> hs((size_t)P->nd * P->opt.N);
+    std::vector<int> hs((size_t)P->nd * P->opt.N), hn(hs.size());
     HIPCHK(P, hipMemcpy(hs.data(), P->sing.p, sizeof(int) * hs.size(), hipMemcpyDeviceToHost));
-    for (int v : hs) if (v) { sing = true; P->stats.singular_nodes++; }
+    HIPCHK(P, hipMemcpy(hn.data(), P->nonfin.p, sizeof(int) * hn.size(), hipMemcpyDeviceToHost));
+    for (size_t t = 0; t < hs.size(); ++t)
+      if (hs[t] || hn[t]) { sing = true; P->stats.singular_nodes++; }
   }
   if (sing) return NEP_WARN_SINGULAR_NODE;   // the disks holding such nodes are flagged
   return fb ? NEP_WARN_REFINE_FALLBACK : NEP_OK;

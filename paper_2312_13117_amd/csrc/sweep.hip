@@ -6,7 +6,8 @@
 //                     C0 = sum w_j X_j^V, C1 = sum w_j z_j X_j^V (eqs (2.3), (3.2)-(3.3)),
 //                     accumulated in complex128 in node order
 //   profile_kernel    ||x_j[:, q]||_2 per node and probe column
-//   indicator_kernel  I_q = || P f|_N ./ P f|_{N/2} ||_2 / sqrt(n)   (eq (3.1))
+//   indicator_kernel  I_q = || P f|_N ./ P f|_{N/2} ||_2 / sqrt(n)   (eq (3.1)), with the
+//                     rounding-noise floor of the two rules' sums
 //   residual_kernel   R_t = B_t - T(z_t) X_t in complex128 (mixed-precision refinement)
 #include "common.h"
 #include "sweep.h"
@@ -87,13 +88,15 @@ __global__ __launch_bounds__(256) void rhs_kernel(const double2* __restrict__ F,
 }
 
 // grid (ceil(n*m/256), ndisks).  Node j of list entry dl has its solution at
-// X + (dl*N + j)*xstride (n x m); dl maps to the global disk disk_ids[dl].  Sums run over j = 1..N in order (fixed rounding order).
+// X + (dl*N + j)*xstride (n x m); dl maps to the global disk disk_ids[dl].  Sums run
+// over j = 1..N in order (fixed rounding order).  A non-finite solution entry sets
+// nonfin[dl*N + j] (every writer stores 1).
 __global__ __launch_bounds__(256) void sums_kernel(const double2* __restrict__ X, long long xstride,
                                                    const double2* __restrict__ wts, const double2* __restrict__ zn,
                                                    int N, int n, int s, int L, double2* __restrict__ PfN,
                                                    double2* __restrict__ PfN2, double2* __restrict__ C0,
                                                    double2* __restrict__ C1, const int* __restrict__ disk_ids,
-                                                   const long long* __restrict__ soff) {
+                                                   const long long* __restrict__ soff, int* __restrict__ nonfin) {
   const int dl = blockIdx.y;
   const int d = disk_ids ? disk_ids[dl] : dl;
   const int m = s + L;
@@ -106,6 +109,7 @@ __global__ __launch_bounds__(256) void sums_kernel(const double2* __restrict__ X
   double2 a0 = cmk<double>(0, 0), a1 = cmk<double>(0, 0);
   for (int j = 0; j < N; ++j) {
     const double2 x = X[(t0 + j) * xstride + e];
+    if (nonfin && !(fabs(x.x) <= 1.7976931348623157e308 && fabs(x.y) <= 1.7976931348623157e308)) nonfin[t0 + j] = 1;
     if (q < s) {
       a0 = cfma<double>(a0, w[j], x);
       if (j & 1) a1 = cfma<double>(a1, cscale<double>(w[j], 2.0), x);   // 1-based even node
@@ -124,75 +128,132 @@ __global__ __launch_bounds__(256) void sums_kernel(const double2* __restrict__ X
   }
 }
 
+// |a| without overflow or underflow of the squares
+NEP_DEV double cabs_safe(double2 a) { return hypot(a.x, a.y); }
+
+// Block-wide (256 threads) max and sum of three values; every thread gets the result.
+NEP_DEV void block_max3(double* v, double (*red)[3]) {
+  for (int k = 0; k < 3; ++k)
+    for (int o = 32; o > 0; o >>= 1) {
+      const double u = __shfl_xor(v[k], o, 64);
+      v[k] = (u > v[k] || u != u) ? u : v[k];     // NaN wins
+    }
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0)
+    for (int k = 0; k < 3; ++k) red[threadIdx.x >> 6][k] = v[k];
+  __syncthreads();
+  for (int k = 0; k < 3; ++k) {
+    double r = red[0][k];
+    for (int w = 1; w < 4; ++w) r = (red[w][k] > r || red[w][k] != red[w][k]) ? red[w][k] : r;
+    v[k] = r;
+  }
+}
+NEP_DEV void block_sum3(double* v, double (*red)[3]) {
+  for (int k = 0; k < 3; ++k) v[k] = wave_sum(v[k]);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0)
+    for (int k = 0; k < 3; ++k) red[threadIdx.x >> 6][k] = v[k];
+  __syncthreads();
+  for (int k = 0; k < 3; ++k) v[k] = red[0][k] + red[1][k] + red[2][k] + red[3][k];
+}
+
+// 2-norm as max * sqrt(sum (|v_i| / max)^2): entries far outside 1e+-154 neither
+// overflow nor underflow when squared
+NEP_DEV double scaled_norm(double mx, double ssq) { return (mx > 0.0 && mx <= 1.7976931348623157e308) ? mx * sqrt(ssq) : mx; }
+
 // grid (N, ndisks), 256 threads: profile[d][j][q] = ||x_j[:, q]||_2, q < s
 __global__ __launch_bounds__(256) void profile_kernel(const double2* __restrict__ X, long long xstride, int N,
                                                       int n, int s, int m, double* __restrict__ prof,
                                                       const int* __restrict__ disk_ids) {
   const int j = blockIdx.x, dl = blockIdx.y, d = disk_ids[dl];
   const double2* x = X + ((long long)dl * N + j) * xstride;
-  __shared__ double red[4][8];
-  double acc[8];
-  for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256)
-    for (int q = 0; q < s; ++q) acc[q] += cabs2<double>(x[(long long)i * m + q]);
+  __shared__ double red[4][3];
   for (int q = 0; q < s; ++q) {
-    const double v = wave_sum(acc[q]);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][q] = v;
-  }
-  __syncthreads();
-  if (threadIdx.x < s) {
-    const int q = threadIdx.x;
-    prof[((long long)d * N + j) * s + q] = sqrt(red[0][q] + red[1][q] + red[2][q] + red[3][q]);
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < n; i += 256) {
+      const double a = cabs_safe(x[(long long)i * m + q]);
+      v[0] = (a > v[0] || a != a) ? a : v[0];
+    }
+    block_max3(v, red);
+    const double mx = v[0];
+    double t[3] = {0.0, 0.0, 0.0};
+    if (mx > 0.0 && mx <= 1.7976931348623157e308)
+      for (int i = threadIdx.x; i < n; i += 256) {
+        const double a = cabs_safe(x[(long long)i * m + q]) / mx;
+        t[0] += a * a;
+      }
+    block_sum3(t, red);
+    if (threadIdx.x == 0) prof[((long long)d * N + j) * s + q] = scaled_norm(mx, t[0]);
   }
 }
 
-// one workgroup per disk: I_q = ||PfN[:,q] ./ PfN2[:,q]||_2 / sqrt(n); +inf if not
-// finite; 0 when ||PfN2[:,q]|| <= floor * S_q with S_q = (r/N) sum_j ||x_j[:,q]|| the size
-// of the summands (both sums are then rounding noise and their ratio carries no
-// information about eigenvalues inside)
+// one workgroup per disk, per probe column q:
+//   I_q = ||P f|_N[:, q] ./ P f|_{N/2}[:, q]||_2 / sqrt(n), +inf if not finite;
+//   I_q = 0 when ||P f|_N[:, q]|| <= floor * S_N and ||P f|_{N/2}[:, q]|| <= floor * S_half
+//   (all four finite), S_N = (r/N) sum_j ||x_j[:, q]|| and S_half = (2r/N) sum over the
+//   1-based even nodes, the summand sizes of the two rules: both sums are then rounding
+//   noise and so is their ratio.
+// The disk is flagged if some I_q > tol or one of its nodes is singular or non-finite.
 __global__ __launch_bounds__(256) void indicator_kernel(const double2* __restrict__ PfN,
                                                         const double2* __restrict__ PfN2, const int* __restrict__ dn,
                                                         const long long* __restrict__ soff, int s, double tol,
                                                         double* __restrict__ ind, unsigned char* __restrict__ flags,
-                                                        const int* __restrict__ sing, int N,
-                                                        const double* __restrict__ prof,
+                                                        const int* __restrict__ sing, const int* __restrict__ nonfin,
+                                                        int N, const double* __restrict__ prof,
                                                         const double* __restrict__ rad, double floor) {
   const int d = blockIdx.x;
   const int n = dn[d];
-  const double2* a = PfN + soff[d] * s;
-  const double2* b = PfN2 + soff[d] * s;
-  __shared__ double red[4][16];
-  double acc[8], den[8];
-  for (int q = 0; q < 8; ++q) { acc[q] = 0.0; den[q] = 0.0; }
-  for (int i = threadIdx.x; i < n; i += 256)
-    for (int q = 0; q < s; ++q) {
-      const double2 num = a[(long long)i * s + q], dd = b[(long long)i * s + q];
-      // |num / den|^2 = |num|^2 / |den|^2 (0/0 and x/0 give NaN / inf, caught below)
-      acc[q] += cabs2<double>(num) / cabs2<double>(dd);
-      den[q] += cabs2<double>(dd);
-    }
+  const double2* A = PfN + soff[d] * s;
+  const double2* B = PfN2 + soff[d] * s;
+  __shared__ double red[4][3];
+  bool flag = false;
   for (int q = 0; q < s; ++q) {
-    const double v = wave_sum(acc[q]), w = wave_sum(den[q]);
-    if ((threadIdx.x & 63) == 0) { red[threadIdx.x >> 6][q] = v; red[threadIdx.x >> 6][8 + q] = w; }
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    bool flag = false;
-    for (int q = 0; q < s; ++q) {
-      double v = sqrt((red[0][q] + red[1][q] + red[2][q] + red[3][q]) / (double)n);
-      if (!(v <= 1.7976931348623157e308)) v = __builtin_inf();
-      if (prof) {
-        double S = 0.0;
-        for (int j = 0; j < N; ++j) S += prof[((long long)d * N + j) * s + q];
-        S *= rad[d] / N;
-        const double nb = sqrt(red[0][8 + q] + red[1][8 + q] + red[2][8 + q] + red[3][8 + q]);
-        if (nb <= floor * S) v = 0.0;
-      }
-      ind[(long long)d * s + q] = v;
-      if (v > tol) flag = true;
+    // pass 1: largest |ratio|, |PfN|, |PfN2| (NaN propagates)
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < n; i += 256) {
+      const double a = cabs_safe(A[(long long)i * s + q]), b = cabs_safe(B[(long long)i * s + q]);
+      const double r = a / b;   // 0/0 -> NaN, x/0 -> inf
+      const double c[3] = {r, a, b};
+      for (int k = 0; k < 3; ++k) v[k] = (c[k] > v[k] || c[k] != c[k]) ? c[k] : v[k];
     }
-    if (sing)
-      for (int j = 0; j < N; ++j) flag = flag || sing[(long long)d * N + j] != 0;
+    block_max3(v, red);
+    // pass 2: sums of squares scaled by those maxima
+    double t[3] = {0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < n; i += 256) {
+      const double a = cabs_safe(A[(long long)i * s + q]), b = cabs_safe(B[(long long)i * s + q]);
+      const double c[3] = {a / b, a, b};
+      for (int k = 0; k < 3; ++k)
+        if (v[k] > 0.0 && v[k] <= 1.7976931348623157e308) {
+          const double u = c[k] / v[k];
+          t[k] += u * u;
+        }
+    }
+    block_sum3(t, red);
+    if (threadIdx.x == 0) {
+      double I = scaled_norm(v[0], t[0]) / sqrt((double)n);
+      if (!(I <= 1.7976931348623157e308)) I = __builtin_inf();
+      if (prof) {
+        double SN = 0.0, SH = 0.0;
+        for (int j = 0; j < N; ++j) {
+          const double p = prof[((long long)d * N + j) * s + q];
+          SN += p;
+          if (j & 1) SH += p;
+        }
+        SN *= rad[d] / N;
+        SH *= 2.0 * rad[d] / N;
+        const double na = scaled_norm(v[1], t[1]), nb = scaled_norm(v[2], t[2]);
+        const double big = 1.7976931348623157e308;
+        if (na <= big && nb <= big && SN <= big && SH <= big && na <= floor * SN && nb <= floor * SH) I = 0.0;
+      }
+      ind[(long long)d * s + q] = I;
+      if (I > tol) flag = true;
+    }
+  }
+  if (threadIdx.x == 0) {
+    for (int j = 0; j < N; ++j) {
+      if (sing) flag = flag || sing[(long long)d * N + j] != 0;
+      if (nonfin) flag = flag || nonfin[(long long)d * N + j] != 0;
+    }
     flags[d] = flag ? 1 : 0;
   }
 }
@@ -431,6 +492,23 @@ hipError_t launch_mark_singular(const int* info, int nb, int* sing, hipStream_t 
   return hipGetLastError();
 }
 
+// refinement state of a batch: active = 1 and diverged = 0, except for tasks whose
+// LU met an exact zero pivot (info != 0), which are set diverged and inactive
+__global__ void refine_init_kernel(const int* __restrict__ info, int nb, int* __restrict__ active,
+                                   int* __restrict__ diverged) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < nb) {
+    const int z = info[b] != 0;
+    active[b] = 1 - z;
+    diverged[b] = z;
+  }
+}
+
+hipError_t launch_refine_init(const int* info, int nb, int* active, int* diverged, hipStream_t st) {
+  refine_init_kernel<<<(nb + 255) / 256, 256, 0, st>>>(info, nb, active, diverged);
+  return hipGetLastError();
+}
+
 // out[b] = a[b] | c[b]: the tasks still unconverged or diverged after refinement
 __global__ void or_flags_kernel(const int* __restrict__ a, const int* __restrict__ c, int nb, int* __restrict__ out) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -600,9 +678,9 @@ hipError_t launch_rhs(const double2* F, int s, const double2* V, int L, int n, d
 
 hipError_t launch_sums(const double2* X, long long xstride, const double2* wts, const double2* zn, int N, int n,
                        int s, int L, double2* PfN, double2* PfN2, double2* C0, double2* C1, const int* disk_ids,
-                       int ndisks, const long long* soff, hipStream_t st) {
+                       int ndisks, const long long* soff, int* nonfin, hipStream_t st) {
   dim3 grid((unsigned)((n * (s + L) + 255) / 256), (unsigned)ndisks);
-  sums_kernel<<<grid, 256, 0, st>>>(X, xstride, wts, zn, N, n, s, L, PfN, PfN2, C0, C1, disk_ids, soff);
+  sums_kernel<<<grid, 256, 0, st>>>(X, xstride, wts, zn, N, n, s, L, PfN, PfN2, C0, C1, disk_ids, soff, nonfin);
   return hipGetLastError();
 }
 
@@ -613,9 +691,10 @@ hipError_t launch_profile(const double2* X, long long xstride, int N, int n, int
 }
 
 hipError_t launch_indicator(const double2* PfN, const double2* PfN2, const int* dn, const long long* soff, int s,
-                            double tol, double* ind, unsigned char* flags, const int* sing, int N,
-                            const double* prof, const double* rad, double floor, int ndisks, hipStream_t st) {
-  indicator_kernel<<<ndisks, 256, 0, st>>>(PfN, PfN2, dn, soff, s, tol, ind, flags, sing, N, prof, rad, floor);
+                            double tol, double* ind, unsigned char* flags, const int* sing, const int* nonfin,
+                            int N, const double* prof, const double* rad, double floor, int ndisks, hipStream_t st) {
+  indicator_kernel<<<ndisks, 256, 0, st>>>(PfN, PfN2, dn, soff, s, tol, ind, flags, sing, nonfin, N, prof, rad,
+                                           floor);
   return hipGetLastError();
 }
 

@@ -74,6 +74,7 @@ class Dataset:
     labels: np.ndarray     # child flags [rows, 4]
     sweeps: int            # disks swept
     seconds: float
+    cell: np.ndarray = None  # parent cell (x0, x1, y0, y1) [rows, 4]
 
 
 def build_dataset(problems, depth: int = 3, root: Rect = Rect(-4, 4, -4, 4), N_nodes: int = 32,
@@ -85,7 +86,7 @@ def build_dataset(problems, depth: int = 3, root: Rect = Rect(-4, 4, -4, 4), N_n
     devp = [N.upload_problem(p) for p in problems]
     F = [N._dev_complex(gen.probes(probe_seed, p.n, 1), torch) for p in problems]
     t0 = time.perf_counter()
-    rows_p, rows_l, rows_prof, rows_lab = [], [], [], []
+    rows_p, rows_l, rows_prof, rows_lab, rows_cell = [], [], [], [], []
     sweeps = 0
     # level 0: the root disk of every problem (for its profile)
     ent = [(p, root) for p in range(len(problems))]
@@ -118,6 +119,7 @@ def build_dataset(problems, depth: int = 3, root: Rect = Rect(-4, 4, -4, 4), N_n
             rows_l.append(level - 1)
             rows_prof.append(pprof)
             rows_lab.append(flags[i].astype(np.float32))
+            rows_cell.append((r.x0, r.x1, r.y0, r.y1))
             if level < depth:
                 for k, cr in enumerate(_children(r)):
                     if flags[i, k]:
@@ -125,7 +127,7 @@ def build_dataset(problems, depth: int = 3, root: Rect = Rect(-4, 4, -4, 4), N_n
         log(f"level {level}: {len(parents)} parents, {int(flags.sum())} positive children")
         parents = nxt
     return Dataset(np.asarray(rows_p), np.asarray(rows_l), np.asarray(rows_prof), np.asarray(rows_lab), sweeps,
-                   time.perf_counter() - t0)
+                   time.perf_counter() - t0, np.asarray(rows_cell))
 
 
 def train(ds: Dataset, train_mask: np.ndarray, epochs: int = 200, batch: int = 256, lr: float = 1e-3,

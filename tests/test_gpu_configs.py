@@ -1,0 +1,197 @@
+"""Oracle parity at the full sizes of the workloads, in the launch configuration the
+benchmark uses (the library's default batch and worker streams).
+
+* dense n = 1024 QEP (256 disks x 32 nodes, s = 4, L = 16), complex128 and complex64 +
+  complex128 refinement: all 256 flags identical to the oracle's stored sweep
+  (tests/golden/dense_qep_n1024_indicators.txt), every resolved indicator column within
+  1e-6 relative, and the quadrature sums of 8 disks (4 flagged, 4 empty) computed by
+  the oracle here, one by one;
+* uneven delay family (64 problems, n 128..2048, 8 x 16 rectangles x 48 nodes,
+  complex64 + refinement): flags and indicators of every rectangle of the problems with
+  n <= 512 and of 8 seeded rectangles of each larger problem
+  (tests/golden/delay_uneven_indicators.txt);
+* screener family, n = 256: the SIM quadtree labels of 16 held-out problems
+  (tests/golden/screener_labels_n256.txt).
+
+Indicator tolerance: columns whose two sums are both at least 1e-5 of their summand
+sizes agree to 1e-6 relative; smaller sums (close to the quadrature error of an empty
+disk) to the rounding bound of their ratio (see _indicator_parity); a column the oracle
+puts under the noise floor must be 0 on the GPU too, unless either sum lies within 10%
+of the floor (counted and printed).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from test_gpu_parity import GOLD, say
+
+pytestmark = pytest.mark.gpu
+
+TAU = oracle.NOISE_FLOOR
+
+
+@pytest.fixture(scope="module")
+def N():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2312_13117_amd import nep
+    nep.lib()
+    return nep
+
+
+def _indicator_parity(ind, flags, g_flag, g_I, g_rn, g_rh, tol_ind, label, eps):
+    """Flags identical; indicator columns within their rounding bound; floored columns 0.
+
+    The GPU sums carry an absolute error of at most eps * S (eps = 1e-12 for complex128,
+    1e-10 after complex64 refinement: the sum tolerances of the parity tests), so the
+    indicator of a column whose sums have relative sizes rn = |P f|_N| / S_N and
+    rh = |P f|_{N/2}| / S_half is good to 2 eps (1/rn + 1/rh) relative; columns with both
+    sizes >= 1e-5 are held to 1e-6 relative."""
+    band_tol = np.abs(g_I.max(axis=1) - tol_ind) <= 1e-6 * tol_ind
+    assert not band_tol.any(), f"{label}: indicator within 1e-6 of tol_ind"
+    bad = np.nonzero(flags.astype(bool) != g_flag.astype(bool))[0]
+    assert len(bad) == 0, f"{label}: flags differ at {bad[:10]}"
+    near_floor = ((np.abs(g_rn / TAU - 1) <= 0.1) | (np.abs(g_rh / TAU - 1) <= 0.1))
+    floored = (g_rn <= TAU) & (g_rh <= TAU)
+    live = (~floored) & np.isfinite(g_I) & (g_I > 0)
+    small = np.minimum(g_rn, g_rh)
+    tol = np.where(small >= 1e-5, 1e-6, 2 * eps * (1 / g_rn + 1 / g_rh) + 1e-9)
+    rel = np.abs(ind - g_I) / np.where(g_I > 0, g_I, 1.0)
+    tight = live & (small >= 1e-5)
+    loose = live & (small < 1e-5)
+    w_t = float(rel[tight].max()) if tight.any() else 0.0
+    w_l = float((rel[loose] / tol[loose]).max()) if loose.any() else 0.0
+    say(f"  {label}: {int(g_flag.sum())} flagged of {len(g_flag)}; {int(tight.sum())} columns with both sums "
+        f">= 1e-5 of their summands: worst relative indicator difference {w_t:.2e}; {int(loose.sum())} columns "
+        f"with smaller sums: worst difference {w_l:.2f} of their bound; {int(floored.sum())} floored, "
+        f"{int(near_floor.sum())} within 10% of the floor")
+    assert w_t <= 1e-6 and w_l <= 1.0, label
+    chk = floored & ~near_floor
+    assert np.all(ind[chk] == 0.0), f"{label}: a column under the floor is not 0"
+
+
+# ------------------------------------------------------------------------ dense n = 1024
+def _oracle_disk(prob, F, V, Nn, c, r):
+    """The oracle's sums of one disk, the summand size S = sum_j |w_j| max(1, |z_j|) ||X_j||
+    and the propagated rounding bound sum_j |w_j| max(1, |z_j|) kappa_j ||X_j|| (kappa_j
+    LAPACK's 1-norm condition estimate of the node matrix)."""
+    from scipy.linalg import lapack
+    import scipy.linalg as sla
+    sw = oracle.sweep_disk(prob, c, r, Nn, F, V)
+    z, w = oracle.nodes_weights(c, r, Nn)
+    B = np.concatenate([F, V], axis=1)
+    S = Kb = 0.0
+    for j in range(Nn):
+        T = oracle.assemble(prob, z[j])
+        lu, piv = sla.lu_factor(T)
+        rc, _ = lapack.zgecon(lu, np.linalg.norm(T, 1), norm="1")
+        X = sla.lu_solve((lu, piv), B)
+        a = abs(w[j]) * max(1.0, abs(z[j])) * np.linalg.norm(X)
+        S += a
+        Kb += a / rc
+    return sw.PfN, sw.PfN2, sw.C0, sw.C1, S, Kb
+
+
+_DENSE_SAMPLE = {}
+
+
+def _dense_gold():
+    a = np.loadtxt(os.path.join(GOLD, "dense_qep_n1024_indicators.txt"))
+    return a[:, 1], a[:, 2:6], a[:, 6:10], a[:, 10:14]
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec", [0, 1])
+def test_dense_workload_full(N, prec):
+    w = gen.workload_dense_qep(1024, precision=prec)
+    say(f"case dense workload full size, precision={prec}: 256 disks x 32 nodes, s=4, L=16")
+    g_flag, g_I, g_rn, g_rh = _dense_gold()
+    plan = N.nep_plan(w.problems, w.regions, w.opts)
+    try:
+        ind, flags, _, st = N.nep_indicator(plan, w.F, w.V)
+        assert st in (0, 2)
+        PfN, PfN2, C0, C1 = N.nep_copy_sums(plan, 0, plan.total_disks)
+    finally:
+        N.nep_destroy(plan)
+    _indicator_parity(ind.reshape(256, 4), flags, g_flag, g_I, g_rn, g_rh, w.opts.tol_ind,
+                      f"dense n=1024 precision={prec}", 1e-12 if prec == 0 else 1e-10)
+    # sums of 8 disks: four flagged (by the stored sweep) and four empty ones, near and far
+    fl = np.nonzero(g_flag)[0]
+    em = np.nonzero(g_flag == 0)[0]
+    disks = [int(fl[0]), int(fl[len(fl) // 3]), int(fl[2 * len(fl) // 3]), int(fl[-1]),
+             0, 255, int(em[len(em) // 2]), int(em[np.argmin(np.abs(em - fl[0]))])]
+    if not _DENSE_SAMPLE:
+        say("  oracle sums of 8 disks (256 node solves on the host)")
+        cov = oracle.cover(w.regions[0])
+        for d in disks:
+            _DENSE_SAMPLE[d] = _oracle_disk(w.problems[0], w.F[0], w.V[0], w.opts.N, cov[d].c, cov[d].r)
+    u64, u32 = 2.0 ** -53, 2.0 ** -24
+    for d in disks:
+        oPfN, oPfN2, oC0, oC1, S, Kb = _DENSE_SAMPLE[d]
+        # complex128: 8 u kappa propagated over the nodes (two backward-stable solvers);
+        # mixed: the refinement stopping rule leaves 2^-26 kappa u32 per node, four times
+        tol = max(1e-12 * S, 8 * u64 * Kb) if prec == 0 else max(1e-11 * S, 4 * 2.0 ** -26 * u32 * Kb)
+        errs = [np.linalg.norm(a - b) for a, b in ((PfN[d], oPfN), (PfN2[d], oPfN2), (C0[d], oC0), (C1[d], oC1))]
+        rel = [e / max(np.linalg.norm(b), 1e-300) for e, b in zip(errs, (oPfN, oPfN2, oC0, oC1))]
+        say(f"  disk {d} flag {int(g_flag[d])}: |dC0|/|C0| {rel[2]:.2e} |dC1|/|C1| {rel[3]:.2e} "
+            f"|dPfN|/S {errs[0] / S:.2e} (bound {tol / S:.2e})")
+        assert max(errs) <= tol, d
+        if g_flag[d]:
+            # flagged disks: the moments do not cancel, so they are also compared with
+            # their own size: 1e-12 (complex128) / 1e-10 (mixed), or the propagated bound
+            # relative to that size where it is larger
+            base = 1e-12 if prec == 0 else 1e-10
+            for k, ref in ((2, oC0), (3, oC1)):
+                assert rel[k] <= max(base, tol / np.linalg.norm(ref)), (d, k)
+
+
+# ------------------------------------------------------------------------ delay family
+@pytest.mark.timeout(900)
+def test_delay_family_full(N):
+    path = os.path.join(GOLD, "delay_uneven_indicators.txt")
+    if not os.path.exists(path):
+        pytest.skip("stored delay indicators not written")
+    g = np.loadtxt(path)
+    w = gen.workload_delay(64)
+    say("case delay family full size: 64 problems, 8 x 16 rectangles x 48 nodes, complex64 + refinement")
+    plan = N.nep_plan(w.problems, w.regions, w.opts)
+    try:
+        ind, flags, _, st = N.nep_indicator(plan, w.F, None)
+        assert st in (0, 2)
+        offs = [N.lib().nep_disk_offset(plan.handle, p) for p in range(len(w.problems))]
+        stats = N.nep_get_stats(plan)
+    finally:
+        N.nep_destroy(plan)
+    say(f"  sweep {stats['ms_total']:.0f} ms, {stats['refine_fallbacks']} complex128 re-solves")
+    p, n, rect = g[:, 0].astype(int), g[:, 1].astype(int), g[:, 2].astype(int)
+    idx = np.array([offs[a] + b for a, b in zip(p, rect)])
+    _indicator_parity(ind[idx][:, None], flags[idx], g[:, 3], g[:, 4:5], g[:, 5:6], g[:, 6:7], w.opts.tol_ind,
+                      f"delay family ({len(idx)} rectangles: all of n <= 512, 8 of each larger problem)", 1e-10)
+    for size in (128, 256, 512, 1024, 2048):
+        mk = n == size
+        say(f"    n={size}: {int(mk.sum())} rectangles, {int(g[mk, 3].sum())} flagged")
+
+
+# ------------------------------------------------------------------------ screener family
+@pytest.mark.timeout(600)
+def test_screener_labels_full_size(N):
+    from paper_2312_13117_amd import screener
+    g = np.loadtxt(os.path.join(GOLD, "screener_labels_n256.txt"))
+    probs = sorted(set(g[:, 0].astype(int).tolist()))
+    say(f"case screener labels: {len(probs)} held-out problems at n=256, three levels")
+    ds = screener.build_dataset([gen.screener_problem(p, 256) for p in probs], depth=3, log=lambda *a: None)
+    got = {}
+    for i in range(len(ds.labels)):
+        got[(probs[ds.problem[i]], int(ds.level[i])) + tuple(np.round(ds.cell[i], 12))] = ds.labels[i] > 0.5
+    want = {}
+    for row in g:
+        key = (int(row[0]), int(row[1])) + tuple(np.round(row[2:6], 12))
+        want[key] = row[6:10] > 0.1
+        assert np.all(np.abs(row[6:10] - 0.1) > 1e-6 * 0.1), key
+    assert set(got) == set(want)
+    for k in want:
+        assert np.array_equal(got[k], want[k]), k
+    say(f"  {len(want)} split cells, {int(sum(v.sum() for v in want.values()))} positive children: identical")

@@ -123,7 +123,7 @@ def test_sums_ragged_sizes(N, n, Nn, s, L, prec, pivot):
         check_sums(N, plan, prob, reg, opts, F, V, 1e-12 if prec == 0 else 1e-11)
         for d, dk in enumerate(oracle.cover(reg)):
             sw = oracle.sweep_disk(prob, dk.c, dk.r, Nn, F, None)
-            I, Iq = oracle.indicator(sw.PfN, sw.PfN2, sw.scale)
+            I, Iq = sw.indicator()
             assert flags[d] == (I > opts.tol_ind)
             assert np.allclose(prof[d], sw.profile, rtol=1e-10 if prec == 0 else 1e-9)
     finally:
@@ -302,14 +302,17 @@ def test_uneven_delay_plan(N):
         N.nep_destroy(plan)
 
 
-def test_singular_node_flags_disk(N):
+@pytest.mark.parametrize("prec", [0, 1])
+def test_singular_node_flags_disk(N, prec):
     # unrotated diagonal problem with a root exactly on node 1 of disk 0: exact zero pivot
+    # (in complex64 too: the node and the root are the same double, so the assembled
+    # entry is 0 before rounding; the complex128 re-solve meets the same zero pivot)
     n = 8
     r = float(np.hypot(1.0, 1.0))            # radius of the disk of the cell [-1,1]^2
     roots = np.array([r, 2.5, 3.0, 3.5, 4.0, 4.5, 5.0, 5.5], np.complex128)
     prob = gen.Problem(n, [np.ascontiguousarray(np.diag(-roots)), None], [gen.PHI_ONE, gen.PHI_Z])
-    say("case singular node")
-    opts = gen.Options(N=8, s=1, L=2)
+    say(f"case singular node precision={prec}")
+    opts = gen.Options(N=8, s=1, L=2, precision=prec)
     # disk 0: centre 0, radius sqrt(2) -> node 1 (theta = 0) at z = sqrt(2) hits the root
     reg = gen.Region(-1.0, 1.0, -1.0, 1.0, 1, 1)
     plan = N.nep_plan([prob], [reg], opts)
@@ -317,8 +320,41 @@ def test_singular_node_flags_disk(N):
         ind, flags, _, st = N.nep_indicator(plan, [gen.probes(1, n, 1)], [gen.probes(2, n, 2)])
         assert st == N.NEP_WARN_SINGULAR_NODE
         assert flags[0]
+        assert N.nep_get_stats(plan)["singular_nodes"] >= 1
     finally:
         N.nep_destroy(plan)
+
+
+@pytest.mark.parametrize("scale", [1e160, 1e-160])
+def test_scaled_coefficients(N, scale):
+    # T scaled by 1e+-160 scales every solution and sum by the inverse; the indicator is a
+    # ratio and must not change, although squares of the entries leave the double range
+    n = 48
+    A = gen.gaussian(120, n)
+    base = gen.qep(A + A.T, 0.1 * gen.gaussian(121, n), None)
+    reg = gen.Region(-4.0, 4.0, -3.0, 3.0, 4, 3)          # 8 flagged disks, 4 empty (I ~ 0.01)
+    opts = gen.Options(N=16, s=2, L=0)
+    F = gen.probes(122, n, 2)
+    say(f"case coefficients scaled by {scale:g}")
+    out = []
+    for f in (1.0, scale):
+        M = np.ascontiguousarray(f * np.eye(n, dtype=np.complex128))
+        prob = gen.Problem(n, [f * base.coeffs[0], f * base.coeffs[1], M], base.phi_kind)
+        plan = N.nep_plan([prob], [reg], opts)
+        try:
+            ind, flags, prof, st = N.nep_indicator(plan, [F], None, want_profiles=True)
+            assert st == 0
+            out.append((ind.copy(), flags.copy(), prof.copy()))
+        finally:
+            N.nep_destroy(plan)
+    assert np.array_equal(out[0][1], out[1][1]) and out[0][1].any() and not out[0][1].all()
+    # indicators: unchanged where resolved (empty disks under the floor report 0 both times)
+    assert np.allclose(out[1][0], out[0][0], rtol=1e-9, atol=0)
+    assert np.allclose(out[1][2] * scale, out[0][2], rtol=1e-10, atol=0)
+    cov = oracle.cover(reg)
+    for d in range(len(cov)):
+        I, _ = oracle.sweep_disk(prob, cov[d].c, cov[d].r, opts.N, F, None).indicator()
+        assert bool(out[1][1][d]) == (I > opts.tol_ind)
 
 
 def test_sweep_is_deterministic(N):
@@ -362,7 +398,7 @@ def test_dense_workload_sampled(N):
         cov = oracle.cover(w.regions[0])
         for d in sample:
             sw = oracle.sweep_disk(w.problems[0], cov[d].c, cov[d].r, 32, w.F[0], None)
-            I, _ = oracle.indicator(sw.PfN, sw.PfN2, sw.scale)
+            I, _ = sw.indicator()
             assert flags[d] == (I > 0.1)
     finally:
         N.nep_destroy(plan)

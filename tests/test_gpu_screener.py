@@ -99,7 +99,7 @@ def test_screener_labels_training_and_gain(N):
                 dk = oracle.Disk(0, 0, 0.5 * (r.x0 + r.x1), 0.5 * (r.y0 + r.y1), 0.5 * (r.x1 - r.x0),
                                  0.5 * (r.y1 - r.y0))
                 sw = oracle.sweep_disk(problems[p], dk.c, dk.r, 32, F, None)
-                I, _ = oracle.indicator(sw.PfN, sw.PfN2, sw.scale)
+                I, _ = sw.indicator()
                 assert bool(ds.labels[row, k]) == (I > 0.1)
             checked += 1
     assert checked >= 1

@@ -144,6 +144,110 @@ def test_cover_geometry():
     assert d[17].cx == pytest.approx(-3 + 0.75) and d[17].cy == pytest.approx(-6 + 0.375 * 3)
 
 
+def _rotated(n, roots, seed):
+    """The generator's rotated diagonal problem Q diag(z - a_i) Q^H and its unitary Q
+    (rebuilt here from the same seed for the closed forms)."""
+    prob = gen.rotated_diagonal(roots, seed)
+    r2 = np.random.default_rng(seed)
+    Z = r2.standard_normal((n, n)) + 1j * r2.standard_normal((n, n))
+    Q, R = np.linalg.qr(Z)
+    return prob, Q * (np.diag(R) / np.abs(np.diag(R)))
+
+
+def test_summand_scales_closed_form():
+    # x_j = Q diag(1/(z_j - a_i)) Q^H f, so ||x_j||^2 = sum_i |g_i|^2 / |z_j - a_i|^2 with
+    # g = Q^H f (Q unitary): S_N = sum_j (r/N) ||x_j||, S_half = sum_{j even} 2 (r/N) ||x_j||
+    n = 10
+    rng = np.random.default_rng(12)
+    roots = 2.0 * (rng.uniform(-1, 1, n) + 1j * rng.uniform(-1, 1, n))
+    prob, Q = _rotated(n, roots, 13)
+    F = gen.probes(14, n, 3)
+    c, r, N = 0.2 - 0.1j, 0.7, 16
+    sw = oracle.sweep_disk(prob, c, r, N, F, None)
+    theta = 2.0 * np.pi * np.arange(N) / N
+    z = c + r * np.exp(1j * theta)
+    g = Q.conj().T @ F
+    xn = np.sqrt((np.abs(g)[None, :, :] ** 2 / np.abs(z[:, None, None] - roots[None, :, None]) ** 2).sum(axis=1))
+    SN = (r / N) * xn.sum(axis=0)
+    SH = 2.0 * (r / N) * xn[1::2].sum(axis=0)          # 1-based even nodes 2, 4, ..., N
+    assert np.allclose(sw.profile, xn, rtol=1e-12, atol=0)
+    assert np.allclose(sw.scale, SN, rtol=1e-12, atol=0)
+    assert np.allclose(sw.scale_half, SH, rtol=1e-12, atol=0)
+
+
+def test_noise_floor_is_above_the_rounding_of_an_empty_disk():
+    # poles far outside (q = 0.25 / 4 -> q^{N/2} ~ 1e-19): both computed sums are
+    # rounding noise, far below the floor times their summand sizes
+    n = 12
+    roots = 4.0 + 0.3 * np.arange(n) + 0.1j
+    prob, _ = _rotated(n, roots, 5)
+    sw = oracle.sweep_disk(prob, 0j, 0.25, 32, gen.probes(6, n, 2), None)
+    a = np.array([oracle.norm2(sw.PfN[:, q]) for q in range(2)]) / sw.scale
+    b = np.array([oracle.norm2(sw.PfN2[:, q]) for q in range(2)]) / sw.scale_half
+    assert np.all(a < 1e-3 * oracle.NOISE_FLOOR) and np.all(b < 1e-3 * oracle.NOISE_FLOOR)
+
+
+@pytest.mark.parametrize("dist", [0.6, 0.75])
+def test_indicator_above_the_floor_matches_closed_form(dist):
+    # every pole outside at |a - c| = r / q with q^{N/2} ~ 1e-4 .. 1e-2: the half-rule sum
+    # is far above the floor, so the indicator is the ratio of the exact closed-form
+    # vectors, q^{N/2}-small and unflagged
+    n, N = 8, 32
+    c, r = 0.1 + 0.1j, 0.5
+    ang = 2.0 * np.pi * np.arange(n) / n + 0.3
+    roots = c + (r / dist) * np.exp(1j * ang) * (1.0 + 0.05 * np.arange(n))
+    prob, Q = _rotated(n, roots, 21)
+    F = gen.probes(22, n, 1)
+    sw = oracle.sweep_disk(prob, c, r, N, F, None)
+    delta = (roots - c) / r
+    gN = np.array([brute.trapezoid_pole_full(d, N) for d in delta])
+    gH = np.array([brute.trapezoid_pole_half(d, N) for d in delta])
+    ex = Q @ np.diag(gN) @ Q.conj().T @ F
+    eh = Q @ np.diag(gH) @ Q.conj().T @ F
+    exact = np.linalg.norm(ex / eh) / np.sqrt(n)
+    assert oracle.norm2(sw.PfN2[:, 0]) > 1e3 * oracle.NOISE_FLOOR * sw.scale_half[0]
+    I, _ = sw.indicator()
+    assert abs(I - exact) <= 1e-6 * exact
+    assert 0 < I < 0.1
+
+
+@pytest.mark.parametrize("node", [0, 1, 6, 7])
+@pytest.mark.parametrize("delta", [1e-8, 1e-12])
+def test_outside_eigenvalue_next_to_a_node_keeps_the_disk_flagged(node, delta):
+    # an eigenvalue inside the disk and one just outside the circle, delta * r from node
+    # `node` (0-based; odd and even nodes of the half rule): that node's solution
+    # dominates the summands of its rule(s) and P f|_N alike, so neither rule's sum can
+    # fall under the noise floor and the disk stays flagged
+    n, N = 12, 16
+    c, r = 0.0j, 1.0
+    zk = c + r * np.exp(2j * np.pi * node / N)
+    roots = np.concatenate([[0.3 * np.exp(0.7j), zk + delta * r * (zk - c) / r], 5.0 + 0.5 * np.arange(n - 2)])
+    prob, _ = _rotated(n, roots, 31)
+    sw = oracle.sweep_disk(prob, c, r, N, gen.probes(32, n, 1), None)
+    I, _ = sw.indicator()
+    assert I > 0.1
+    # the disk with the inside eigenvalue alone is flagged too, with I ~ 1
+    roots2 = roots.copy()
+    roots2[1] = 7.0
+    prob2, _ = _rotated(n, roots2, 31)
+    I2, _ = oracle.sweep_disk(prob2, c, r, N, gen.probes(32, n, 1), None).indicator()
+    assert 0.5 < I2 < 2.0
+
+
+def test_indicator_is_scale_invariant():
+    # T scaled by 1e+-160 scales every sum by the inverse; the ratio is unchanged and no
+    # square of an entry may overflow or underflow
+    n = 16
+    roots = np.concatenate([[0.05 + 0.02j], 0.4 + 0.1j * np.arange(n - 1)])
+    prob, _ = _rotated(n, roots, 41)
+    F = gen.probes(42, n, 1)
+    sw = oracle.sweep_disk(prob, 0j, 0.5, 32, F, None)
+    I0, _ = sw.indicator()
+    for f in (1e-160, 1e160):
+        I, _ = oracle.indicator(f * sw.PfN, f * sw.PfN2, (f * sw.scale, f * sw.scale_half))
+        assert I == pytest.approx(I0, rel=1e-13)
+
+
 def test_indicator_noise_floor():
     # all roots far outside: both sums sink below the rounding level of the summands
     # (q^N ~ 1e-40), their raw ratio is noise of order one, the floor reports 0; a disk
@@ -153,14 +257,14 @@ def test_indicator_noise_floor():
     prob = gen.rotated_diagonal(roots, 5)
     F = gen.probes(6, n, 2)
     sw = oracle.sweep_disk(prob, 0j, 0.25, 32, F, None)
-    assert np.all(np.linalg.norm(sw.PfN2, axis=0) < 1e-12 * sw.scale)
-    I_raw, _ = oracle.indicator(sw.PfN, sw.PfN2)
-    I, Iq = oracle.indicator(sw.PfN, sw.PfN2, sw.scale)
+    assert np.all(np.linalg.norm(sw.PfN2, axis=0) < 1e-12 * sw.scale_half)
+    assert np.all(np.linalg.norm(sw.PfN, axis=0) < 1e-12 * sw.scale)
+    I, Iq = sw.indicator()
     assert I == 0.0 and np.all(Iq == 0.0)
     roots2 = roots.copy()
     roots2[0] = 0.05 - 0.02j
     prob2 = gen.rotated_diagonal(roots2, 5)
     sw2 = oracle.sweep_disk(prob2, 0j, 0.25, 32, F, None)
     a, _ = oracle.indicator(sw2.PfN, sw2.PfN2)
-    b, _ = oracle.indicator(sw2.PfN, sw2.PfN2, sw2.scale)
+    b, _ = sw2.indicator()
     assert a == b and b > 0.1
