@@ -168,7 +168,7 @@ def test_delay_family_full(N):
     say(f"  sweep {stats['ms_total']:.0f} ms, {stats['refine_fallbacks']} complex128 re-solves")
     p, n, rect = g[:, 0].astype(int), g[:, 1].astype(int), g[:, 2].astype(int)
     idx = np.array([offs[a] + b for a, b in zip(p, rect)])
-    _indicator_parity(ind[idx][:, None], flags[idx], g[:, 3], g[:, 4:5], g[:, 5:6], g[:, 6:7], w.opts.tol_ind,
+    _indicator_parity(ind.reshape(-1, 1)[idx], flags[idx], g[:, 3], g[:, 4:5], g[:, 5:6], g[:, 6:7], w.opts.tol_ind,
                       f"delay family ({len(idx)} rectangles: all of n <= 512, 8 of each larger problem)", 1e-10)
     for size in (128, 256, 512, 1024, 2048):
         mk = n == size
