@@ -351,6 +351,17 @@ size_t nep_mlp_workspace_floats(int B);
 /* probs (device, B x 4) = sigmoid(network(X[idx]))                                    */
 nep_status nep_mlp_forward(const float* params_dev, const float* X_dev, const int32_t* idx_dev, int B,
                            float* probs_dev, float* work_dev, hipStream_t stream);
+/* nep_mlp_forward_noalloc -- nep_mlp_forward for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same kernels, with the activations in a library-owned device array
+ * of NEP_MLP_NOALLOC_MAX_B x 260 floats (4.3 MB) per GPU, kept until the process ends.
+ * No allocation happens in the call.  All calls on one GPU share that array: calls that
+ * overlap in time on one GPU (other streams or threads) race and must be serialised by
+ * the caller.  Errors: NEP_ERR_ARG, NEP_ERR_CAPACITY (B > NEP_MLP_NOALLOC_MAX_B),
+ * NEP_ERR_HIP.                                                                       */
+#define NEP_MLP_NOALLOC_MAX_B 4096
+nep_status nep_mlp_forward_noalloc(const float* params_dev, const float* X_dev, const int32_t* idx_dev, int B,
+                                   float* probs_dev, hipStream_t stream);
 /* grad (device, 21252) = gradient of the mean binary cross-entropy over the batch and
  * the 4 outputs; *loss (host, or NULL) receives that mean (the call then synchronises) */
 nep_status nep_mlp_grad(const float* params_dev, const float* X_dev, const float* Y_dev, const int32_t* idx_dev,

@@ -3,6 +3,8 @@
 // orders the screening of child subregions; it never decides a flag.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "../../include/nep.h"
 #include "common.h"
 
@@ -171,6 +173,47 @@ extern "C" nep_status nep_mlp_forward(const float* params, const float* X, const
   if (r != NEP_OK) return r;
   const float* Z3 = work + (size_t)2 * B * MH;
   sigmoid_kernel<<<(B * MOUT + 255) / 256, 256, 0, st>>>(Z3, probs, B * MOUT);
+  return hipGetLastError() == hipSuccess ? NEP_OK : NEP_ERR_HIP;
+}
+
+// ---------------------------------------------------------------- forward without allocation
+// The activations of nep_mlp_forward_noalloc live in a file-scope device array (one copy
+// per GPU, held until the process ends).  Host code never uses the array's name as an
+// address: its device address is looked up once per device with hipGetSymbolAddress and
+// that pointer is what the kernels receive.
+static __device__ __align__(256) float scratch[(size_t)NEP_MLP_NOALLOC_MAX_B * (2 * MH + MOUT)];
+
+static constexpr int MAX_DEVICES = 64;
+static float* g_scratch[MAX_DEVICES];
+static std::mutex g_scratch_mu;
+
+static nep_status scratch_of_current_device(float** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return NEP_ERR_HIP;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return NEP_ERR_HIP;
+    }
+    g_scratch[dev] = static_cast<float*>(p);
+  }
+  *out = g_scratch[dev];
+  return NEP_OK;
+}
+
+extern "C" nep_status nep_mlp_forward_noalloc(const float* params, const float* X, const int32_t* idx, int B,
+                                              float* probs, hipStream_t st) {
+  if (!params || !X || !probs || B < 1) return NEP_ERR_ARG;
+  if (B > NEP_MLP_NOALLOC_MAX_B) return NEP_ERR_CAPACITY;
+  float* w = nullptr;
+  nep_status r = scratch_of_current_device(&w);
+  if (r != NEP_OK) return r;
+  // every activation is written before it is read: nothing in the array needs clearing
+  r = fwd(params, X, idx, B, w, st);
+  if (r != NEP_OK) return r;
+  sigmoid_kernel<<<(B * MOUT + 255) / 256, 256, 0, st>>>(w + (size_t)2 * B * MH, probs, B * MOUT);
   return hipGetLastError() == hipSuccess ? NEP_OK : NEP_ERR_HIP;
 }
 
