@@ -31,7 +31,13 @@ Prints ONE JSON line.
   durations come from the library's own HIP events recorded on the stream the
   kernel runs on; the average launch duration is the union of the launches'
   intervals over their number (launches of the two worker streams may overlap).
-- `cpu_baseline` = the FP64 CPU oracle on a bounded sample of the same workload.
+- `delay_family` = the uneven delay family in full (64 problems, n 128..2048, 393,216
+  node systems in one plan, complex64 + refinement): one pass.
+- `screener` = the learned screener on the n = 256 family (2000 problems): miss rate,
+  solves a skip policy would save, ordering gain.
+- `peak_measured` = the matrix-core rate of the update's MFMA shape on this device.
+- `cpu_baseline` = the FP64 CPU oracle on a bounded sample of the same workload, one
+  single-threaded LAPACK worker per host core over disks.
 """
 from __future__ import annotations
 
@@ -136,6 +142,11 @@ def _log(msg):
         print(msg, file=sys.stderr, flush=True)
 
 
+def _progress(msg):
+    """One stderr line per block of the benchmark (stdout carries only the JSON line)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def timed(runner, steps: int, warmup: int):
     import torch
     for i in range(warmup):
@@ -157,23 +168,62 @@ def timed(runner, steps: int, warmup: int):
     return float(np.median(times)), outs[k]
 
 
-def cpu_baseline(w, max_disks: int):
-    """FP64 CPU oracle on a bounded sample: `max_disks` disks spread over problem 0."""
+_CPU_JOB = {}
+
+
+def _cpu_worker_init():
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except ImportError:
+        pass
+
+
+def _cpu_disk(d):
     import oracle
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    prob, reg = w.problems[0], w.regions[0]
-    disks = oracle.cover(reg)
-    idx = np.linspace(0, len(disks) - 1, max_disks).round().astype(int)
+    prob, reg, opts, F, V = _CPU_JOB["w"]
+    dk = oracle.cover(reg)[d]
     t0 = time.perf_counter()
-    for d in idx:
-        dk = disks[d]
-        oracle.sweep_disk(prob, dk.c, dk.r, w.opts.N, w.F[0], w.V[0])
-    dt = time.perf_counter() - t0
+    oracle.sweep_disk(prob, dk.c, dk.r, opts.N, F, V)
+    return time.perf_counter() - t0
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, disks_per_worker: int = 2):
+    """The FP64 CPU oracle on a bounded sample of the same workload, the analogue of the
+    paper's parfor over disks: one single-threaded LAPACK worker process per host core
+    (the GPU machine's CPU share: OMP_NUM_THREADS, at most 16), each sweeping whole disks of
+    problem 0.  Runs before the GPU is touched (the workers are forked)."""
+    import multiprocessing as mp
+    import oracle  # noqa: F401  (imported before the fork: the workers must not import scipy themselves)
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or min(16, os.cpu_count() or 1)
+    cores = max(1, min(cores, 16, os.cpu_count() or 1))
+    prob, reg = w.problems[0], w.regions[0]
+    _CPU_JOB["w"] = (prob, reg, w.opts, w.F[0], w.V[0])
+    nd = reg.nx * reg.ny
+    idx = np.linspace(0, nd - 1, min(nd, cores * disks_per_worker)).round().astype(int).tolist()
+    ctx = mp.get_context("fork")
+    with ctx.Pool(cores, initializer=_cpu_worker_init) as pool:
+        pool.map(_cpu_disk, idx[:cores], chunksize=1)          # page in, start the pool
+        t0 = time.perf_counter()
+        per = pool.map(_cpu_disk, idx, chunksize=1)
+        dt = time.perf_counter() - t0
     solves = len(idx) * w.opts.N
     nrhs = w.F[0].shape[1] + (0 if w.V[0] is None else w.V[0].shape[1])
-    return {"value": solves / dt, "unit": "solves/s", "cores": threads, "kind": "oracle",
+    return {"value": solves / dt, "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "cpu": cpu_model(),
             "sample": f"{len(idx)} disks x {w.opts.N} nodes of problem 0 (n={prob.n}, {nrhs} right-hand sides, "
-                      f"complex128 LAPACK gesv per node), {dt:.1f} s"}
+                      f"complex128 LAPACK gesv per node), one single-threaded worker process per core over "
+                      f"disks; {dt:.1f} s wall, {float(np.mean(per)):.2f} s per disk"}
 
 
 def copy_calibration(nbytes: int = 1 << 30, reps: int = 3):
@@ -307,32 +357,81 @@ def complete_spectrum(pivot: int, reps: int = 1):
     return res
 
 
+def delay_run():
+    """The uneven delay family in full: 64 problems T(z) = -z I + A0 + A1 exp(-tau z) with
+    n drawn from {128, ..., 2048}, 8 x 16 rectangles x 48 nodes each (393,216 node
+    systems), complex64 LUs with complex128 refinement, all in one plan (largest n
+    first over two worker streams); one pass after the other blocks warmed the kernels."""
+    w = build_workload("delay", 64)
+    r = Runner(w)
+    T, o = timed(r, 1, 0)
+    r.close()
+    st = o["stats"]
+    return {"workload": "delay_uneven_64problems_8x16_N48", "problems": len(w.problems),
+            "n": sorted(set(p.n for p in w.problems)), "node_solves": int(st["node_solves"]), "seconds": T,
+            "value": st["node_solves"] / T, "unit": "solves/s", "lu_pflop": st["lu_flops"] / 1e15,
+            "lu_tflops_over_wall": st["lu_flops"] / T / 1e12,
+            "lu_frac_of_fp32_peak_over_wall": st["lu_flops"] / T / PEAK["fp32"],
+            "flagged_rectangles": int(np.sum(o["flags"])), "refine_sweeps": st["refine_sweeps"],
+            "refine_fallbacks": st["refine_fallbacks"], "phase_ms_stream_summed": phase_dict(st)}
+
+
+def screener_run():
+    """The learned screener on the n = 256 QEP family: SIM labels of 2000 problems on a
+    three-level quadtree, training on 1600, test metrics on 400 (miss rate against the
+    method's own flags, child solves a skip policy would save, child evaluations until
+    every positive child is screened in network order against raster and random order)."""
+    from paper_2312_13117_amd import screener
+    rep = screener.run(2000, 1600, 256, log=_log)
+    t = rep["test"]
+    return {"workload": "screener_qep_n256_2000problems_depth3", "label_solves": rep["dataset"]["solves"],
+            "label_seconds": rep["dataset"]["seconds"], "train_seconds": rep["training"]["seconds"],
+            "miss_rate": t["miss_rate"], "solves_saved": t["solves_saved"], "solves_total": t["solves_total"],
+            "evals_until_all_positive": t["evals_until_all_positive"], "per_level": t["per_level"],
+            "trivial_all_positive": rep["trivial_all_positive"]}
+
+
+def peak_measured():
+    """The matrix-core rate of the update's MFMA shape on this device (TFLOP/s)."""
+    from paper_2312_13117_amd import nep as N
+    return {"fp64": N.nep_mfma_peak(N.NEP_FP64), "fp32": N.nep_mfma_peak(N.NEP_FP32_REFINE),
+            "unit": "TFLOP/s", "kernel": "independent chains of the 16x16x4 MFMA, 1024 workgroups x 4 waves"}
+
+
 def phase_dict(st):
     return {k: st[k] for k in ("ms_assemble", "ms_lu", "ms_solve", "ms_refine", "ms_sums", "ms_total")}
 
 
 def measured_traffic(workload: str, prec: str, flops_per_launch: float = None):
     """HBM bytes per launch of the update kernel from the committed counter summary, or
-    None when there is none for this workload, the LU source has changed since, or the
-    launches now have another shape (a different batch: flops per launch differ)."""
+    None when there is none for this workload and precision, the LU source has changed
+    since, or the launches now have another shape (a different batch: flops per launch
+    differ)."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "lu_update_traffic_dense_n1024.md")
+    path = os.path.join(ROOT, "profiles", "lu_kernels_counters_dense_n1024.md")
     try:
+        text = open(path).read()
+    except OSError:
+        return None
+    for block in text.split("```")[1::2]:
         kv = {}
-        for line in open(path):
-            if ":" in line and not line.startswith(("#", "`", " ")):
+        for line in block.splitlines():
+            if ":" in line and not line.startswith((" ", "#")):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
-        src = os.path.join(ROOT, kv["kernel_source"])
-        h = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        if h != kv["kernel_source_sha256"] or kv["workload"] != workload or kv["precision"] != prec:
+        try:
+            if kv.get("workload") != workload or kv.get("precision") != prec:
+                continue
+            src = os.path.join(ROOT, kv["kernel_source"])
+            if hashlib.sha256(open(src, "rb").read()).hexdigest() != kv["kernel_source_sha256"]:
+                return None
+            if flops_per_launch is not None and \
+                    abs(float(kv["flops_per_launch"]) - flops_per_launch) > 0.005 * flops_per_launch:
+                return None
+            return float(kv["traffic_bytes_per_launch"])
+        except (OSError, KeyError, ValueError):
             return None
-        if flops_per_launch is not None and \
-                abs(float(kv["flops_per_launch"]) - flops_per_launch) > 0.005 * flops_per_launch:
-            return None
-        return float(kv["traffic_bytes_per_launch"])
-    except (OSError, KeyError, ValueError):
-        return None
+    return None
 
 
 def roofline(st, prec, workload=None):
@@ -344,10 +443,15 @@ def roofline(st, prec, workload=None):
     achieved = st["gemm_flops"] / (busy * 1e-3) if busy > 0 else 0.0
     fpl = st["gemm_flops"] / max(1, st["gemm_launches"])
     traffic = measured_traffic(workload, prec, fpl) if workload else None
+    # complex128 products are formed from 3 real products (3M): the matrix cores execute
+    # 6 of the 8 credited flops per complex multiply-add; complex64 uses all 4 (8 of 8)
+    executed = 0.75 if prec == "fp64" else 1.0
     return {"kernel": "lu_gemm_kernel<UPDATE2> (trailing update of the batched LU, two panels per pass, K = 128)",
             "bound": "mfma",
             "achieved": achieved / 1e12, "peak": PEAK[prec] / 1e12, "unit": "TFLOP/s",
             "frac": achieved / PEAK[prec], "traffic": traffic, "traffic_unit": "bytes per launch (HBM, counters)",
+            "executed_frac": executed * achieved / PEAK[prec],
+            "credit": "8 real flops per complex multiply-add" + (" (3M: 6 executed)" if prec == "fp64" else ""),
             "launches": st["gemm_launches"],
             "avg_launch_ms": busy / max(1, st["gemm_launches"]),
             "avg_launch_ms_own_interval": st["ms_gemm"] / max(1, st["gemm_launches"]),
@@ -361,10 +465,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="dense")
     ap.add_argument("--delay-count", type=int, default=8)
-    ap.add_argument("--cpu-disks", type=int, default=4)
+    ap.add_argument("--cpu-disks-per-core", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-eigen", action="store_true")
+    ap.add_argument("--no-delay", action="store_true", help="skip the full delay-family pass")
+    ap.add_argument("--no-screener", action="store_true", help="skip the screener block")
     ap.add_argument("--pivot", choices=("partial", "tournament"), default="partial",
                     help="pivot choice of the node LU panels")
     ap.add_argument("--verbose", action="store_true", help="one stderr line per step")
@@ -382,12 +488,15 @@ def main():
         sys.exit(2)
     w = build_workload(args.workload, args.delay_count, pivot)
     prec = "fp32" if w.opts.precision == 1 else "fp64"
+    # the CPU oracle first: its worker processes are forked before the GPU is touched
+    cpu = None if args.no_cpu_baseline else cpu_baseline(w, args.cpu_disks_per_core)
+    if cpu is not None:
+        _progress(f"cpu baseline {cpu['value']:.1f} solves/s on {cpu['cores']} cores")
     r = Runner(w)
     T, o = timed(r, args.steps, args.warmup)
     sums64 = r.sums() if (args.workload == "dense" and not args.no_mixed) else None
     r.close()
     st = o["stats"]
-    lu_rate = st["lu_flops"] / (st["ms_lu"] * 1e-3) if st["ms_lu"] > 0 else 0.0
     out = {
         "metric": "quadrature solves/s (node assembly + LU + block solve + sums per (disk, node)) over the "
                   "whole pmCIMb step; eigenpairs/s alongside",
@@ -412,10 +521,16 @@ def main():
         "phase_ms": phase_dict(st),
         "refine_sweeps": st["refine_sweeps"],
         "refine_fallbacks": st["refine_fallbacks"],
-        "lu_tflops": lu_rate / 1e12,
-        "lu_frac_of_peak": lu_rate / PEAK[prec],
+        "lu_flops_per_step": st["lu_flops"],
+        # the whole LU's algorithmic flops (sum of 8 n^3 / 3) over the wall time of the
+        # indicator sweep (assembly, LU, solves, sums; both worker streams) and of the step
+        "lu_frac_of_peak_over_sweep_wall": st["lu_flops"] / (st["ms_total"] * 1e-3) / PEAK[prec],
+        "lu_frac_of_peak_over_step_wall": st["lu_flops"] / T / PEAK[prec],
+        "sweep_ms": st["ms_total"],
         "roofline": roofline(st, prec, w.name),
     }
+    _progress(f"{w.name}: {out['value']:.0f} solves/s, {T * 1e3:.0f} ms per step")
+    out["peak_measured"] = peak_measured()
     if args.workload == "dense" and not args.no_mixed:
         wm = build_workload("dense_mixed", pivot=pivot)
         rm = Runner(wm)
@@ -430,13 +545,14 @@ def main():
         for d in fl:
             for a, b in ((sm[2][d], sums64[2][d]), (sm[3][d], sums64[3][d])):
                 rel = max(rel, float(np.linalg.norm(a - b) / np.linalg.norm(b)))
-        lu_m = stm["lu_flops"] / (stm["ms_lu"] * 1e-3) if stm["ms_lu"] > 0 else 0.0
+        _progress(f"{wm.name}: {stm['node_solves'] / Tm:.0f} solves/s")
         out["mixed"] = {"workload": wm.name, "value": stm["node_solves"] / Tm, "ms_per_step": Tm * 1e3,
                         "speedup_vs_fp64": T / Tm, "flags_identical": bool(np.array_equal(om["flags"], o["flags"])),
                         "max_rel_moment_diff_vs_fp64_flagged": rel, "refine_sweeps": stm["refine_sweeps"],
                         "refine_fallbacks": stm["refine_fallbacks"], "phase_ms": phase_dict(stm),
-                        "lu_tflops": lu_m / 1e12, "lu_frac_of_peak": lu_m / PEAK["fp32"],
-                        "roofline": roofline(stm, "fp32"), "verified_eigenpairs": int(len(om["eigs"]))}
+                        "sweep_ms": stm["ms_total"], "sweep_speedup_vs_fp64": st["ms_total"] / stm["ms_total"],
+                        "lu_frac_of_fp32_peak_over_sweep_wall": stm["lu_flops"] / (stm["ms_total"] * 1e-3) / PEAK["fp32"],
+                        "roofline": roofline(stm, "fp32", wm.name), "verified_eigenpairs": int(len(om["eigs"]))}
     if args.workload in ("dense", "dense_mixed") and not args.no_eigen:
         # eigenpairs where the rank test is not saturated (31 probe columns, n = 64)
         eo = {}
@@ -449,14 +565,23 @@ def main():
             eo[tag] = {"eigenpairs": int(len(oe["eigs"])), "ms_per_step": Te * 1e3,
                        "eigenpairs_per_s": len(oe["eigs"]) / Te}
         out["eigenpairs_unsaturated"] = {"workload": "qep_n64_4x4_L31", **eo}
+        _progress("unsaturated eigenpairs done")
     if args.workload == "dense" and not args.no_eigen and not args.no_mixed:
         out["eigenpairs_complete"] = {"workload": w.name + "_adaptive", **complete_spectrum(pivot)}
+        _progress("complete spectrum done")
     if args.workload == "dense" and not args.no_eigen:
         out["pmcima"] = pmcima_run()
         out["generic_assembly"] = generic_run(max(2, min(args.steps, 3)))
         out["scattering"] = scattering_run()
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_disks)
+        _progress("pmCIMa, generic assembly and scattering done")
+    if args.workload == "dense" and not args.no_delay:
+        out["delay_family"] = delay_run()
+        _progress(f"delay family: {out['delay_family']['value']:.0f} solves/s")
+    if args.workload == "dense" and not args.no_screener:
+        out["screener"] = screener_run()
+        _progress("screener done")
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out))
 
 

@@ -375,6 +375,14 @@ nep_status nep_mlp_adam(float* params_dev, const float* grad_dev, float* m_dev, 
 nep_status nep_mlp_features(const double* profiles_dev, int rows, int ncol, const int32_t* stat_rows_dev,
                             int nstat, float* mean_dev, float* sd_dev, float* X_dev, hipStream_t stream);
 
+/* nep_mfma_peak -- the device's matrix-core rate, measured (the check of the roofline
+ * denominators): 1024 workgroups of four waves each issue independent chains of the
+ * 16x16x4 MFMA of the LU's trailing update (precision NEP_FP64: f64; NEP_FP32_REFINE:
+ * f32) for `iters` iterations on the null stream; *tflops receives the dense rate in
+ * TFLOP/s (2 * 16 * 16 * 4 flops per instruction).  Allocates and frees 8 KB.
+ * Errors: NEP_ERR_ARG, NEP_ERR_NOMEM, NEP_ERR_HIP.                                  */
+nep_status nep_mfma_peak(int precision, int iters, double* tflops);
+
 /* Sizes of a plan: total disks, and the first global disk of problem p.             */
 int nep_total_disks(const nep_plan_t* plan);
 int nep_disk_offset(const nep_plan_t* plan, int problem);

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnep.so")
-SOURCES = ["lu.hip", "sweep.hip", "beyn.hip", "mlp.hip", "nep_abi.hip"]
+SOURCES = ["lu.hip", "sweep.hip", "beyn.hip", "mlp.hip", "peak.hip", "nep_abi.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wno-unused-result",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

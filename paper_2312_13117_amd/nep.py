@@ -87,13 +87,14 @@ def lib():
     L.nep_mlp_workspace_floats.restype = C.c_size_t
     L.nep_mlp_forward.argtypes = [fp, fp, fp, C.c_int, fp, fp, vp]
     L.nep_mlp_forward_noalloc.argtypes = [fp, fp, fp, C.c_int, fp, vp]
+    L.nep_mfma_peak.argtypes = [C.c_int, C.c_int, dp]
     L.nep_mlp_grad.argtypes = [fp, fp, fp, fp, C.c_int, fp, C.POINTER(C.c_float), fp, vp]
     L.nep_mlp_adam.argtypes = [fp, fp, fp, fp, C.c_int, C.c_float, C.c_float, C.c_float, C.c_float, vp]
     L.nep_mlp_features.argtypes = [fp, C.c_int, C.c_int, fp, C.c_int, fp, fp, fp, vp]
     for f in ("nep_plan", "nep_indicator", "nep_beyn", "nep_verify", "nep_refine", "nep_set_assembler",
               "nep_assemble_elementwise_delay", "nep_assemble_circle_double_layer", "nep_copy_sums", "nep_dedup",
               "nep_total_disks", "nep_disk_offset", "nep_get_stats", "nep_mlp_param_count", "nep_mlp_forward",
-              "nep_mlp_forward_noalloc",
+              "nep_mlp_forward_noalloc", "nep_mfma_peak",
               "nep_mlp_grad", "nep_mlp_adam", "nep_mlp_features"):
         getattr(L, f).restype = C.c_int
     _lib = L
@@ -456,6 +457,13 @@ def nep_mlp_forward_noalloc(params, X, idx, B, probs):
 
 
 NEP_MLP_NOALLOC_MAX_B = 4096
+
+
+def nep_mfma_peak(precision: int = NEP_FP64, iters: int = 8192) -> float:
+    """Measured matrix-core rate (TFLOP/s) of the MFMA shape the LU update uses."""
+    t = C.c_double(0.0)
+    _check(lib().nep_mfma_peak(precision, iters, C.byref(t)))
+    return t.value
 
 
 def nep_mlp_grad(params, X, Y, idx, B, grad, work, want_loss=False):

@@ -44,3 +44,13 @@ def test_traffic_only_for_the_measured_configuration():
     assert bench.measured_traffic("qep_n64_4x4", "fp64", fpl) is None
     assert bench.measured_traffic("qep_n1024_16x16", "fp32", fpl) is None
     assert bench.measured_traffic("qep_n1024_16x16", "fp64", 0.5 * fpl) is None
+    # the mixed-precision workload has its own figure (complex64 update, half the bytes)
+    t32 = bench.measured_traffic("qep_n1024_16x16_mixed", "fp32", fpl)
+    assert t32 is None or (t is not None and 0.3 * t < t32 < 0.6 * t)
+
+
+def test_executed_fraction_of_the_3m_update():
+    r = bench.roofline(_stats(280.0, 280.0), "fp64")
+    assert r["executed_frac"] == pytest.approx(0.75 * r["frac"])
+    r = bench.roofline(_stats(280.0, 280.0), "fp32")
+    assert r["executed_frac"] == pytest.approx(r["frac"])
