@@ -336,7 +336,28 @@ nep_status nep_copy_sums(nep_plan_t* plan, int first, int count, void* PfN, void
  * from two neighbouring disks).  Host only; keep[i] = 1 for survivors.             */
 nep_status nep_dedup(const void* lam, const double* sigma, int m, double rel, uint8_t* keep);
 
-/* ---------------------------------------------------------------- learned screener
+/* nep_merge -- pmCIMa's merge of approximate eigenvalues (Section 3.1, the remark after
+ * the algorithm: near an eigenvalue several small cells are flagged, and their centres
+ * are merged).  The first centre not yet taken gathers every untaken centre closer than
+ * tol_eps (absolute, strict), and the group's mean (summed in list order) is one merged
+ * value; groups are formed in list order and each centre joins one group.
+ *   centres  host complex128 [m];  merged  host complex128 [m] (the first *count valid)
+ *   group    host int32 [m] or NULL: the merged value each centre joined
+ * Host only.  Errors: NEP_ERR_ARG.                                                    */
+nep_status nep_merge(const void* centres, int m, double tol_eps, void* merged, int* count, int32_t* group);
+
+/* nep_own -- Step 2.f's keep-inside-the-cell rule across cells of different sizes (the
+ * saturation remedy at the end of Section 3.2 splits saturated cells, so candidates come
+ * from cells of several levels).  Candidate i was produced by the cell
+ * cells[4i .. 4i+3] = (x0, x1, y0, y1).  The distinct producing cells are ordered by
+ * (x0, y0); a candidate belongs to the first of them that contains it within
+ * band * max(1, |lambda|) (closed), and owned[i] = 1 iff that cell produced it: a value
+ * on an edge shared by two cells is kept once, by the cell with the smaller (x0, y0).
+ *   cells  host double [4 m];  lam  host complex128 [m];  owned  host uint8 [m]
+ * Host only.  Errors: NEP_ERR_ARG.                                                    */
+nep_status nep_own(const double* cells, const void* lam, int m, double band, uint8_t* owned);
+
+/* ---------------------------------------------------------------- learned screener/* ---------------------------------------------------------------- learned screener
  * A small network (not part of the paper's method) that orders the screening of the
  * four children of a flagged parent cell from the parent's node profile
  * ||T(z_j)^{-1} f||, j = 1..32.  It never decides a flag: every child is still swept.

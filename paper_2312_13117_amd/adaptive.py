@@ -16,8 +16,9 @@ level 0 use N_beyn = 64 nodes, see pmcimb_adaptive).  The candidates of
 the unsaturated disks of every level are filtered by ownership across all of them
 (Step 2.f's rule, extended over cells of different parents: a value within
 1e-6 max(1, |lambda|) of cells' shared edges belongs to the cell with the smallest
-(x0, y0)), verified (sigma_min(T(lambda)) < tol_ver) and merged.  Every sweep, extraction and verification runs in the library's
-kernels; only the cell bookkeeping is host code.
+(x0, y0); nep_own), verified (sigma_min(T(lambda)) < tol_ver) and merged (nep_dedup).
+Every sweep, extraction and verification runs in the library's kernels, the ownership
+and merge rules in its host routines; only the cell bookkeeping is Python.
 """
 from __future__ import annotations
 
@@ -65,19 +66,6 @@ def _cells_of(region, level):
             x0 = region.x0 + ix * hx
             y0 = region.y0 + iy * hy
             out.append(Cell(x0, x0 + hx, y0, y0 + hy, level))
-    return out
-
-
-def _owned(cands, band=1e-6):
-    """Mask of the candidates whose producing cell owns them among all producing cells."""
-    cells = sorted({c for c, _ in cands}, key=lambda c: (c[0], c[2]))
-    out = np.zeros(len(cands), dtype=bool)
-    for i, (c, lam) in enumerate(cands):
-        d = band * max(1.0, abs(lam))
-        for q in cells:
-            if q[0] - d <= lam.real <= q[1] + d and q[2] - d <= lam.imag <= q[3] + d:
-                out[i] = q == c
-                break
     return out
 
 
@@ -171,7 +159,7 @@ def pmcimb_adaptive(problem, region, opts, F, V, max_depth: int = 5, N_beyn: int
             lam = np.asarray([l for _, l in cands], dtype=np.complex128)
             lam, sig, acc, _ = N.nep_refine(plan0, np.zeros(len(lam), np.int32), lam, refine_iters)
             cands = [(c, l) for (c, _), l in zip(cands, lam)]
-            sel = _owned(cands) & acc
+            sel = N.nep_own(np.asarray([c for c, _ in cands], dtype=np.float64), lam) & acc
             al, asg = lam[sel], sig[sel]
             keep = N.nep_dedup(al, asg) if len(al) else np.zeros(0, bool)
             eigs, sg = al[keep], asg[keep]

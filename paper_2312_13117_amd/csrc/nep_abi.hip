@@ -1236,6 +1236,60 @@ extern "C" nep_status nep_dedup(const void* lam, const double* sigma, int m, dou
   return NEP_OK;
 }
 
+extern "C" nep_status nep_merge(const void* centres, int m, double tol_eps, void* merged, int* count, int32_t* group) {
+  if (m < 0 || (m > 0 && (!centres || !merged)) || !count || !(tol_eps >= 0)) return NEP_ERR_ARG;
+  const double2* z = static_cast<const double2*>(centres);
+  double2* out = static_cast<double2*>(merged);
+  std::vector<char> taken(m, 0);
+  int k = 0;
+  for (int i = 0; i < m; ++i) {
+    if (taken[i]) continue;
+    // the first untaken centre gathers every untaken centre closer than tol_eps; the
+    // group's mean is summed in list order
+    double sx = 0.0, sy = 0.0;
+    int cnt = 0;
+    for (int j = i; j < m; ++j) {
+      if (taken[j] || !(std::hypot(z[j].x - z[i].x, z[j].y - z[i].y) < tol_eps)) continue;
+      taken[j] = 1;
+      sx += z[j].x;
+      sy += z[j].y;
+      ++cnt;
+      if (group) group[j] = k;
+    }
+    out[k++] = make_double2(sx / cnt, sy / cnt);
+  }
+  *count = k;
+  return NEP_OK;
+}
+
+extern "C" nep_status nep_own(const double* cells, const void* lam, int m, double band, uint8_t* owned) {
+  if (m < 0 || (m > 0 && (!cells || !lam || !owned)) || !(band >= 0)) return NEP_ERR_ARG;
+  const double2* l = static_cast<const double2*>(lam);
+  // the distinct producing cells, ordered by (x0, y0)
+  std::vector<int> first;
+  for (int i = 0; i < m; ++i) {
+    bool seen = false;
+    for (int q : first)
+      if (std::memcmp(cells + 4 * q, cells + 4 * i, 4 * sizeof(double)) == 0) { seen = true; break; }
+    if (!seen) first.push_back(i);
+  }
+  std::stable_sort(first.begin(), first.end(), [&](int a, int b) {
+    return cells[4 * a] != cells[4 * b] ? cells[4 * a] < cells[4 * b] : cells[4 * a + 2] < cells[4 * b + 2];
+  });
+  for (int i = 0; i < m; ++i) {
+    owned[i] = 0;
+    const double d = band * std::max(1.0, std::hypot(l[i].x, l[i].y));
+    for (int q : first) {
+      const double* c = cells + 4 * q;
+      if (c[0] - d <= l[i].x && l[i].x <= c[1] + d && c[2] - d <= l[i].y && l[i].y <= c[3] + d) {
+        owned[i] = std::memcmp(c, cells + 4 * i, 4 * sizeof(double)) == 0 ? 1 : 0;
+        break;
+      }
+    }
+  }
+  return NEP_OK;
+}
+
 extern "C" int nep_total_disks(const nep_plan_t* P) { return P ? P->nd : 0; }
 extern "C" int nep_disk_offset(const nep_plan_t* P, int problem) {
   if (!P || problem < 0 || problem >= P->nprob) return -1;

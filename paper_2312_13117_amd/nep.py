@@ -72,6 +72,8 @@ def lib():
     L.nep_assemble_elementwise_delay.argtypes = [vp, C.c_int, vp, C.c_int, vp, C.c_longlong, vp]
     L.nep_assemble_circle_double_layer.argtypes = [vp, C.c_int, vp, C.c_int, vp, C.c_longlong, vp]
     L.nep_dedup.argtypes = [vp, dp, C.c_int, C.c_double, u8p]
+    L.nep_merge.argtypes = [vp, C.c_int, C.c_double, vp, C.POINTER(C.c_int), ip]
+    L.nep_own.argtypes = [dp, vp, C.c_int, C.c_double, u8p]
     L.nep_total_disks.argtypes = [vp]
     L.nep_disk_offset.argtypes = [vp, C.c_int]
     L.nep_get_stats.argtypes = [vp, C.POINTER(nep_stats)]
@@ -92,7 +94,7 @@ def lib():
     L.nep_mlp_adam.argtypes = [fp, fp, fp, fp, C.c_int, C.c_float, C.c_float, C.c_float, C.c_float, vp]
     L.nep_mlp_features.argtypes = [fp, C.c_int, C.c_int, fp, C.c_int, fp, fp, fp, vp]
     for f in ("nep_plan", "nep_indicator", "nep_beyn", "nep_verify", "nep_refine", "nep_set_assembler",
-              "nep_assemble_elementwise_delay", "nep_assemble_circle_double_layer", "nep_copy_sums", "nep_dedup",
+              "nep_assemble_elementwise_delay", "nep_assemble_circle_double_layer", "nep_copy_sums", "nep_dedup", "nep_merge", "nep_own",
               "nep_total_disks", "nep_disk_offset", "nep_get_stats", "nep_mlp_param_count", "nep_mlp_forward",
               "nep_mlp_forward_noalloc", "nep_mfma_peak",
               "nep_mlp_grad", "nep_mlp_adam", "nep_mlp_features"):
@@ -370,6 +372,30 @@ def nep_dedup(lam, sigma, rel: float = 1e-8):
     keep = np.zeros(len(la), np.uint8)
     _check(L.nep_dedup(_ptr(la), sg.ctypes.data_as(C.POINTER(C.c_double)), len(la), rel,
                        keep.ctypes.data_as(C.POINTER(C.c_uint8))))
+    return keep.astype(bool)
+
+
+def nep_merge(centres, tol_eps: float):
+    """(merged values, group index of every centre): pmCIMa's merge of flagged centres."""
+    L = lib()
+    z = np.ascontiguousarray(np.asarray(centres, dtype=np.complex128))
+    out = np.zeros(len(z), np.complex128)
+    grp = np.zeros(len(z), np.int32)
+    cnt = C.c_int(0)
+    _check(L.nep_merge(_ptr(z), len(z), tol_eps, _ptr(out), C.byref(cnt),
+                       grp.ctypes.data_as(C.POINTER(C.c_int32))))
+    return out[:cnt.value].copy(), grp
+
+
+def nep_own(cells, lam, band: float = 1e-6):
+    """Mask of the candidates kept by the cell that produced them (cells: m x 4 rows
+    (x0, x1, y0, y1) of each candidate's producing cell)."""
+    L = lib()
+    c = np.ascontiguousarray(np.asarray(cells, dtype=np.float64).reshape(-1, 4))
+    la = np.ascontiguousarray(np.asarray(lam, dtype=np.complex128))
+    keep = np.zeros(len(la), np.uint8)
+    _check(L.nep_own(c.ctypes.data_as(C.POINTER(C.c_double)), _ptr(la), len(la), band,
+                     keep.ctypes.data_as(C.POINTER(C.c_uint8))))
     return keep.astype(bool)
 
 

@@ -14,8 +14,9 @@ Step 2   for every merged value, the right singular vector of sigma_min(T(lambda
          eigenvalues by the two-sided Rayleigh functional and duplicates merged
          (not part of the paper's method; reported separately).
 
-Only the cell bookkeeping and the merge are host code; every node system, sum and
-indicator, and Step 2, run in the library's kernels.
+Only the cell bookkeeping is Python; the merge is the library's host routine
+(nep_merge), and every node system, sum and indicator, and Step 2, run in the
+library's kernels.
 """
 from __future__ import annotations
 
@@ -49,24 +50,6 @@ def region_cells(x0: float, x1: float, y0: float, y1: float, nx: int, ny: int):
             cy = y0 + (2 * iy + 1) * hy
             out.append(((cx - hx, cx + hx, cy - hy, cy + hy), complex(cx, cy), r))
     return out
-
-
-def merge_centres(z: np.ndarray, tol_eps: float) -> np.ndarray:
-    """Centres closer than tol_eps (absolute) merged: the first centre not yet taken
-    gathers every other untaken centre within tol_eps of it; each group's mean."""
-    z = np.asarray(z, dtype=np.complex128)
-    taken = np.zeros(len(z), dtype=bool)
-    out = []
-    for i in range(len(z)):
-        if taken[i]:
-            continue
-        grp = np.nonzero(~taken & (np.abs(z - z[i]) < tol_eps))[0]
-        taken[grp] = True
-        acc = 0j
-        for j in grp:                     # list order, as each group is formed
-            acc += z[j]
-        out.append(acc / len(grp))
-    return np.asarray(out, dtype=np.complex128)
 
 
 @dataclass
@@ -128,7 +111,7 @@ def pmcima(problem, region, F, N_nodes: int = 16, tol_ind: float = 0.1, tol_eps:
                 regs = [gen.Region(c[0], c[1], c[2], c[3], 2, 2) for c, _, _ in flagged]
                 disks = [d for c, _, _ in flagged for d in region_cells(c[0], c[1], c[2], c[3], 2, 2)]
         centres = np.asarray([c for _, c, _ in flagged], dtype=np.complex128)
-        eigs = merge_centres(centres, tol_eps)
+        eigs, _ = N.nep_merge(centres, tol_eps)
         res = PmcimaResult(len(all_disks), all_disks, all_ind, all_flags, centres, eigs)
         if len(eigs) and (vectors or refine_iters > 0):
             pid = np.zeros(len(eigs), np.int32)

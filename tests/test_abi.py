@@ -85,3 +85,40 @@ def test_dedup_keeps_smaller_sigma():
     keep = N.nep_dedup(lam, sig, 1e-8)
     assert keep.tolist() == [False, True, True, True, True]
     assert N.nep_dedup(np.zeros(0, np.complex128), np.zeros(0)).shape == (0,)
+
+
+def test_merge_matches_the_oracle_merge():
+    # pmCIMa's merge (Section 3.1): star groups in list order, means summed in list order
+    N, L = _lib()
+    from oracle import pmcima as opm
+    rng = np.random.default_rng(5)
+    base = rng.uniform(-1, 1, 12) + 1j * rng.uniform(-1, 1, 12)
+    z = np.concatenate([base + 3e-7 * (rng.uniform(-1, 1, 12) + 1j * rng.uniform(-1, 1, 12)) for _ in range(4)])
+    z = z[rng.permutation(len(z))]
+    got, grp = N.nep_merge(z, 1e-6)
+    want = opm.merge(z, 1e-6)
+    assert len(got) == len(want) == 12
+    assert np.array_equal(got, want)                       # same sums in the same order
+    for k in range(len(got)):
+        assert np.all(np.abs(z[grp == k] - z[np.argmax(grp == k)]) < 1e-6)
+    assert N.nep_merge(np.zeros(0, np.complex128), 1e-6)[0].shape == (0,)
+
+
+def test_ownership_across_cells_of_different_sizes():
+    N, L = _lib()
+    big = (0.0, 1.0, 0.0, 1.0)                 # a level-0 cell
+    s1 = (1.0, 1.5, 0.0, 0.5)                  # two children of its right neighbour
+    s2 = (1.0, 1.5, 0.5, 1.0)
+    cells = [big, s1, big, s1, s2, s2, big]
+    lam = np.array([0.5 + 0.5j,                # inside big: kept
+                    1.0 + 0.25j,               # on the edge big | s1, produced by s1: big owns it
+                    1.0 + 0.25j,               # the same value produced by big: kept
+                    1.2 + 0.5j,                # on the edge s1 | s2, produced by s1: s1 comes first
+                    1.2 + 0.5j,                # produced by s2: dropped
+                    1.3 + 0.7j,                # inside s2: kept
+                    2.0 + 0.0j], np.complex128)  # outside every cell: dropped
+    keep = N.nep_own(np.asarray(cells), lam)
+    assert keep.tolist() == [True, False, True, True, False, True, False]
+    # within the band of an edge counts as on it
+    keep = N.nep_own(np.asarray([s1, big]), np.array([1.0 + 5e-7 + 0.25j, 1.0 + 5e-7 + 0.25j]))
+    assert keep.tolist() == [False, True]
