@@ -471,6 +471,8 @@ def main():
     ap.add_argument("--no-eigen", action="store_true")
     ap.add_argument("--no-delay", action="store_true", help="skip the full delay-family pass")
     ap.add_argument("--no-screener", action="store_true", help="skip the screener block")
+    ap.add_argument("--graph", action="store_true",
+                    help="capture the indicator sweep in a HIP graph on its first call and replay it")
     ap.add_argument("--pivot", choices=("partial", "tournament"), default="partial",
                     help="pivot choice of the node LU panels")
     ap.add_argument("--verbose", action="store_true", help="one stderr line per step")
@@ -487,6 +489,7 @@ def main():
         print("bench.py measures one GPU: the library has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     w = build_workload(args.workload, args.delay_count, pivot)
+    w.opts.graph = 1 if args.graph else 0
     prec = "fp32" if w.opts.precision == 1 else "fp64"
     # the CPU oracle first: its worker processes are forked before the GPU is touched
     cpu = None if args.no_cpu_baseline else cpu_baseline(w, args.cpu_disks_per_core)
