@@ -388,7 +388,12 @@ def screener_run():
             "label_seconds": rep["dataset"]["seconds"], "train_seconds": rep["training"]["seconds"],
             "miss_rate": t["miss_rate"], "solves_saved": t["solves_saved"], "solves_total": t["solves_total"],
             "evals_until_all_positive": t["evals_until_all_positive"], "per_level": t["per_level"],
-            "trivial_all_positive": rep["trivial_all_positive"]}
+            "trivial_all_positive": rep["trivial_all_positive"],
+            "ranked_rounds": {o: {"seconds": v["seconds"],
+                                  "positive_children_known_after_round": [lv["known_after_round"] for lv in v["levels"]],
+                                  "mean_sweeps_until_all_positive": [lv["mean_sweeps_until_all_positive"]
+                                                                     for lv in v["levels"]]}
+                              for o, v in rep["ranked_rounds"].items()}}
 
 
 def peak_measured():

@@ -56,8 +56,9 @@ def children(cell: Cell):
 
 
 def merge(centres: Sequence[complex], tol_eps: float) -> np.ndarray:
-    """Star clusters in list order, each centre counted once; cluster means."""
-    z = list(centres)
+    """Star clusters in list order, each centre counted once; cluster means, the real
+    and imaginary parts each summed in list order and divided by the member count."""
+    z = [complex(v) for v in centres]
     used = [False] * len(z)
     out = []
     for i in range(len(z)):
@@ -66,7 +67,9 @@ def merge(centres: Sequence[complex], tol_eps: float) -> np.ndarray:
         members = [j for j in range(len(z)) if not used[j] and abs(z[j] - z[i]) < tol_eps]
         for j in members:
             used[j] = True
-        out.append(sum(z[j] for j in members) / len(members))
+        re = sum(z[j].real for j in members)
+        im = sum(z[j].imag for j in members)
+        out.append(complex(re / len(members), im / len(members)))
     return np.asarray(out, dtype=np.complex128)
 
 

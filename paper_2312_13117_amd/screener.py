@@ -14,7 +14,11 @@ family of problems this driver
   3. evaluates it on held-out problems: miss rate against the method's own flags,
      solves saved by the counterfactual "skip predicted-negative children" policy, and
      the ordering gain (child evaluations until every positive child has been screened,
-     network order vs raster and random order).
+     network order vs raster and random order);
+  4. screens the held-out problems again with each level's children swept in ranked
+     rounds (screen_ordered): round r sweeps every parent's child of rank r, ranked by
+     the network or in cover order, and the positive children known after each round
+     are counted.
 
 The network only orders the screening; every child is still swept by the method, so
 the flags (and the eigenvalues) never depend on it.
@@ -171,7 +175,8 @@ def train(ds: Dataset, train_mask: np.ndarray, epochs: int = 200, batch: int = 2
             log(f"epoch {ep}: batch loss {losses[-1]:.4f}")
     torch.cuda.synchronize()
     return params, X, {"epochs": epochs, "steps": step, "seconds": time.perf_counter() - t0,
-                       "loss_first": losses[0], "loss_last": losses[-1]}
+                       "loss_first": losses[0], "loss_last": losses[-1],
+                       "feature_mean": mean.cpu().tolist(), "feature_sd": sd.cpu().tolist()}
 
 
 def predict(params, X, rows: np.ndarray) -> np.ndarray:
@@ -182,6 +187,73 @@ def predict(params, X, rows: np.ndarray) -> np.ndarray:
     work = torch.empty(N.nep_mlp_workspace_floats(B), dtype=torch.float32, device="cuda")
     N.nep_mlp_forward(params, X, idx, B, probs, work)
     return probs.cpu().numpy()
+
+
+def screen_ordered(problems, params, feature_mean, feature_sd, depth: int = 3, order: str = "network",
+                   root: Rect = Rect(-4, 4, -4, 4), N_nodes: int = 32, probe_seed: int = 2) -> dict:
+    """The SIM recursion of build_dataset with the children screened in ranked rounds:
+    at every level, round r sweeps, for every flagged parent, its child of rank r --
+    by descending network probability (order "network"; features of the parent's
+    profile standardised with the training statistics, probabilities from the
+    allocation-free forward pass) or in cover order ("raster").  Every child is still
+    swept, so the flags are the method's; the ranking only decides which children are
+    known first.  Returns, per level, the positive children known after each round, the
+    mean number of child sweeps per parent until its positive children are all known,
+    the wall time, and the labels (problem, level, cell, flags) for comparison."""
+    import gen
+    import torch
+    opts = gen.Options(N=N_nodes, s=1, L=0)
+    devp = [N.upload_problem(p) for p in problems]
+    F = [N._dev_complex(gen.probes(probe_seed, p.n, 1), torch) for p in problems]
+    mean = torch.tensor(feature_mean, dtype=torch.float32, device="cuda")
+    sd = torch.tensor(feature_sd, dtype=torch.float32, device="cuda")
+    t0 = time.perf_counter()
+    f, pr = _sweep(devp, [(p, root) for p in range(len(problems))], 1, opts, F)
+    parents = [(p, root, pr[p, 0]) for p in range(len(problems))]
+    levels, labels = [], []
+    for level in range(1, depth + 1):
+        if not parents:
+            break
+        P = len(parents)
+        if order == "network":
+            prof = torch.from_numpy(np.ascontiguousarray(np.stack([q for _, _, q in parents]), dtype=np.float64))
+            prof = prof.to("cuda")
+            X = torch.empty((P, N_nodes), dtype=torch.float32, device="cuda")
+            N.nep_mlp_features(prof, P, N_nodes, None, mean, sd, X)
+            probs = torch.empty((P, 4), dtype=torch.float32, device="cuda")
+            for c0 in range(0, P, N.NEP_MLP_NOALLOC_MAX_B):
+                B = min(N.NEP_MLP_NOALLOC_MAX_B, P - c0)
+                idx = torch.arange(c0, c0 + B, dtype=torch.int32, device="cuda")
+                N.nep_mlp_forward_noalloc(params, X, idx, B, probs[c0:c0 + B])
+            rank = np.argsort(-probs.cpu().numpy(), axis=1, kind="stable")
+        else:
+            rank = np.tile(np.arange(4), (P, 1))
+        flags = np.zeros((P, 4), dtype=bool)
+        cprof = np.zeros((P, 4, N_nodes))
+        known = []
+        kids = [_children(r) for _, r, _ in parents]
+        for rnd in range(4):
+            ent = [(p, kids[i][rank[i, rnd]]) for i, (p, _, _) in enumerate(parents)]
+            fl, q = _sweep(devp, ent, 1, opts, F)
+            flags[np.arange(P), rank[:, rnd]] = fl[:, 0].astype(bool)
+            cprof[np.arange(P), rank[:, rnd]] = q[:, 0]
+            known.append(int(flags.sum()))
+        # child sweeps per parent until all of its positive children were known
+        pos_rank = np.where(np.take_along_axis(flags, rank, axis=1), np.arange(4)[None, :] + 1, 0)
+        until = pos_rank.max(axis=1)
+        has = until > 0
+        levels.append({"level": level, "parents": P, "positive_children": known[-1],
+                       "known_after_round": known, "mean_sweeps_until_all_positive":
+                       float(until[has].mean()) if has.any() else 0.0})
+        nxt = []
+        for i, (p, r, _) in enumerate(parents):
+            labels.append((p, level - 1, (r.x0, r.x1, r.y0, r.y1), flags[i].copy()))
+            if level < depth:
+                nxt.extend((p, kids[i][k], cprof[i, k]) for k in range(4) if flags[i, k])
+        parents = nxt
+    torch.cuda.synchronize()
+    return {"order": order, "problems": len(problems), "seconds": time.perf_counter() - t0, "levels": levels,
+            "labels": labels}
 
 
 def evaluate(prob: np.ndarray, labels: np.ndarray, levels: np.ndarray, nodes: int = 32, seed: int = 13) -> dict:
@@ -238,11 +310,19 @@ def run(n_problems: int = 2000, n_train: int = 1600, n: int = 256, depth: int = 
     probs = predict(params, X, test_rows)
     ev = evaluate(probs, ds.labels[test_rows], ds.level[test_rows])
     trivial = evaluate(np.ones_like(probs), ds.labels[test_rows], ds.level[test_rows])
+    # the held-out problems screened again with the children in ranked rounds
+    live = {}
+    for order in ("network", "raster"):
+        r = screen_ordered(problems[n_train:], params, tstats["feature_mean"], tstats["feature_sd"], depth=depth,
+                           order=order)
+        live[order] = {k: r[k] for k in ("seconds", "levels")}
+    log(f"ranked rounds: {live}")
     return {"problems": n_problems, "train_problems": n_train, "n": n, "depth": depth,
             "dataset": {"parents": int(len(ds.labels)), "disk_sweeps": ds.sweeps, "solves": ds.sweeps * 32,
                         "seconds": ds.seconds},
-            "training": tstats, "test": ev, "trivial_all_positive": {k: trivial[k] for k in
-                                                                     ("miss_rate", "solves_saved")}}
+            "training": {k: v for k, v in tstats.items() if not k.startswith("feature_")}, "test": ev,
+            "trivial_all_positive": {k: trivial[k] for k in ("miss_rate", "solves_saved")},
+            "ranked_rounds": live}
 
 
 def main():

@@ -114,3 +114,23 @@ def test_screener_labels_training_and_gain(N):
     # the trained network orders the children better than a random order
     assert e["network"] < e["random"]
     assert 0.0 <= ev["miss_rate"] <= 1.0
+    # a live screen of the held-out problems in ranked rounds: every child is swept, so
+    # the labels are the method's; network ranking knows more positive children after
+    # the first round than cover order
+    held = problems[180:]
+    runs = {o: screener.screen_ordered(held, params, tstats["feature_mean"], tstats["feature_sd"], depth=3,
+                                       order=o) for o in ("network", "raster")}
+    want = {}
+    for i in test_rows:
+        key = (int(ds.problem[i]) - 180, int(ds.level[i])) + tuple(np.round(ds.cell[i], 12))
+        want[key] = ds.labels[i] > 0.5
+    for o, r in runs.items():
+        got = {(p, lv) + tuple(np.round(c, 12)): f for p, lv, c, f in r["labels"]}
+        assert set(got) == set(want), o
+        for k in want:
+            assert np.array_equal(got[k], want[k]), (o, k)
+    first = {o: sum(lv["known_after_round"][0] for lv in r["levels"]) for o, r in runs.items()}
+    tot = sum(lv["positive_children"] for lv in runs["network"]["levels"])
+    say(f"positive children known after the first round: network {first['network']}, raster {first['raster']} "
+        f"of {tot}")
+    assert first["network"] > first["raster"]
