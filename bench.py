@@ -351,6 +351,13 @@ def complete_spectrum(pivot: int, reps: int = 1):
         if ref is not None:
             e["max_rel_err_vs_companion"], e["one_to_one"] = _match_err(r.eigs, ref)
             e["companion_eigenvalues"] = int(len(ref))
+            if len(r.eigs):
+                # every eigenvalue's relative error against its nearest companion eigenvalue
+                d = np.abs(r.eigs[:, None] - ref[None, :])
+                near = np.argmin(d, axis=1)
+                err = d[np.arange(len(r.eigs)), near] / np.maximum(1.0, np.abs(ref[near]))
+                e["rel_err_quantiles"] = {q: float(np.quantile(err, float(q))) for q in ("0.5", "0.9", "0.99", "1.0")}
+                e["eigenvalues_above_1e-8"] = int(np.sum(err > 1e-8))
         res[tag] = e
         _log(f"complete spectrum {tag}: {e}")
     res["speedup_mixed_vs_fp64"] = res["fp64"]["seconds"] / res["mixed"]["seconds"]
@@ -378,17 +385,21 @@ def delay_run():
 
 def screener_run():
     """The learned screener on the n = 256 QEP family: SIM labels of 2000 problems on a
-    three-level quadtree, training on 1600, test metrics on 400 (miss rate against the
-    method's own flags, child solves a skip policy would save, child evaluations until
-    every positive child is screened in network order against raster and random order)."""
+    three-level quadtree (complex64 LUs with complex128 refinement), training on 1600,
+    test metrics on 400 (miss rate against the method's own flags, child solves a skip
+    policy would save, child evaluations until every positive child is screened in
+    network order against raster and random order), the held-out problems screened in
+    ranked rounds, and the labels of 400 problems again in complex128 (time, identity)."""
     from paper_2312_13117_amd import screener
-    rep = screener.run(2000, 1600, 256, log=_log)
+    rep = screener.run(2000, 1600, 256, log=_log, precision=1, compare_fp64=400)
     t = rep["test"]
     return {"workload": "screener_qep_n256_2000problems_depth3", "label_solves": rep["dataset"]["solves"],
             "label_seconds": rep["dataset"]["seconds"], "train_seconds": rep["training"]["seconds"],
             "miss_rate": t["miss_rate"], "solves_saved": t["solves_saved"], "solves_total": t["solves_total"],
             "evals_until_all_positive": t["evals_until_all_positive"], "per_level": t["per_level"],
             "trivial_all_positive": rep["trivial_all_positive"],
+            "label_precision": "complex64 + complex128 refinement",
+            "labels_mixed_vs_fp64": rep["labels_mixed_vs_fp64"],
             "ranked_rounds": {o: {"seconds": v["seconds"],
                                   "positive_children_known_after_round": [lv["known_after_round"] for lv in v["levels"]],
                                   "mean_sweeps_until_all_positive": [lv["mean_sweeps_until_all_positive"]
@@ -476,6 +487,8 @@ def main():
     ap.add_argument("--no-eigen", action="store_true")
     ap.add_argument("--no-delay", action="store_true", help="skip the full delay-family pass")
     ap.add_argument("--no-screener", action="store_true", help="skip the screener block")
+    ap.add_argument("--precision", choices=("default", "fp64", "mixed"), default="default",
+                    help="override the workload's LU arithmetic (complex128, or complex64 + refinement)")
     ap.add_argument("--graph", action="store_true",
                     help="capture the indicator sweep in a HIP graph on its first call and replay it")
     ap.add_argument("--pivot", choices=("partial", "tournament"), default="partial",
@@ -495,6 +508,9 @@ def main():
         sys.exit(2)
     w = build_workload(args.workload, args.delay_count, pivot)
     w.opts.graph = 1 if args.graph else 0
+    if args.precision != "default":
+        w.opts.precision = 0 if args.precision == "fp64" else 1
+        w.name += "_" + args.precision
     prec = "fp32" if w.opts.precision == 1 else "fp64"
     # the CPU oracle first: its worker processes are forked before the GPU is touched
     cpu = None if args.no_cpu_baseline else cpu_baseline(w, args.cpu_disks_per_core)

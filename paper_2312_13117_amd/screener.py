@@ -82,11 +82,12 @@ class Dataset:
 
 
 def build_dataset(problems, depth: int = 3, root: Rect = Rect(-4, 4, -4, 4), N_nodes: int = 32,
-                  probe_seed: int = 2, chunk: int = 1000, log=print) -> Dataset:
-    """SIM recursion over the quadtree for every problem; one record per flagged parent."""
+                  probe_seed: int = 2, chunk: int = 1000, log=print, precision: int = 0) -> Dataset:
+    """SIM recursion over the quadtree for every problem; one record per flagged parent.
+    precision: 0 = complex128 LU, 1 = complex64 LU with complex128 refinement."""
     import gen
     import torch
-    opts = gen.Options(N=N_nodes, s=1, L=0)
+    opts = gen.Options(N=N_nodes, s=1, L=0, precision=precision)
     devp = [N.upload_problem(p) for p in problems]
     F = [N._dev_complex(gen.probes(probe_seed, p.n, 1), torch) for p in problems]
     t0 = time.perf_counter()
@@ -296,12 +297,26 @@ def evaluate(prob: np.ndarray, labels: np.ndarray, levels: np.ndarray, nodes: in
 
 
 def run(n_problems: int = 2000, n_train: int = 1600, n: int = 256, depth: int = 3, epochs: int = 200,
-        log=print) -> dict:
+        log=print, precision: int = 0, compare_fp64: int = 0) -> dict:
+    """The whole pipeline; the labels' sweeps in the given precision.  With
+    compare_fp64 > 0 (and precision 1) the first compare_fp64 held-out problems are
+    labelled again in complex128 for the time ratio and label identity."""
     import gen
     t0 = time.perf_counter()
     problems = [gen.screener_problem(p, n) for p in range(n_problems)]
     log(f"generated {n_problems} problems (n={n}) in {time.perf_counter() - t0:.1f} s")
-    ds = build_dataset(problems, depth=depth, log=log)
+    ds = build_dataset(problems, depth=depth, log=log, precision=precision)
+    versus = None
+    if precision == 1 and compare_fp64 > 0:
+        sub = problems[n_train:n_train + compare_fp64]
+        d64 = build_dataset(sub, depth=depth, log=lambda *a: None, precision=0)
+        d32 = build_dataset(sub, depth=depth, log=lambda *a: None, precision=1)
+        same = (len(d64.labels) == len(d32.labels) and np.array_equal(d64.labels, d32.labels)
+                and np.array_equal(d64.cell, d32.cell))
+        versus = {"problems": len(sub), "seconds_fp64": d64.seconds, "seconds_mixed": d32.seconds,
+                  "speedup_mixed_vs_fp64": d64.seconds / d32.seconds, "labels_identical": bool(same)}
+        log(f"labels of {len(sub)} problems: complex128 {d64.seconds:.2f} s, mixed {d32.seconds:.2f} s, "
+            f"identical {same}")
     log(f"dataset: {len(ds.labels)} parents from {ds.sweeps} disk sweeps ({ds.sweeps * 32} solves) "
         f"in {ds.seconds:.1f} s")
     train_mask = ds.problem < n_train
@@ -322,7 +337,7 @@ def run(n_problems: int = 2000, n_train: int = 1600, n: int = 256, depth: int = 
                         "seconds": ds.seconds},
             "training": {k: v for k, v in tstats.items() if not k.startswith("feature_")}, "test": ev,
             "trivial_all_positive": {k: trivial[k] for k in ("miss_rate", "solves_saved")},
-            "ranked_rounds": live}
+            "ranked_rounds": live, "precision": precision, "labels_mixed_vs_fp64": versus}
 
 
 def main():
@@ -331,9 +346,12 @@ def main():
     ap.add_argument("--train", type=int, default=1600)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--epochs", type=int, default=200)
+    ap.add_argument("--precision", type=int, default=0, help="0: complex128 LU, 1: complex64 + refinement")
+    ap.add_argument("--compare-fp64", type=int, default=0)
     ap.add_argument("--out", default=None)
     a = ap.parse_args()
-    rep = run(a.problems, a.train, a.n, epochs=a.epochs, log=lambda *x: print(*x, file=sys.stderr, flush=True))
+    rep = run(a.problems, a.train, a.n, epochs=a.epochs, log=lambda *x: print(*x, file=sys.stderr, flush=True),
+              precision=a.precision, compare_fp64=a.compare_fp64)
     js = json.dumps(rep)
     print(js)
     if a.out:
