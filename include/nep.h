@@ -319,7 +319,9 @@ int nep_assemble_elementwise_delay(void* ctx, int n, const void* z_dev, int nb, 
  * disk (Section 4.2).  T(k) = (I + K_n(k)) / 2 with K the double-layer operator
  * (kernel 2 dPhi/dnu(y), Phi = (i/4) H0(k |x - y|)) on n equispaced points of the
  * unit circle (n even), discretised by Kress's Nystrom rule with the logarithmic
- * splitting; J1 and Y1 from their power series (accurate for |k| up to ~10).  The
+ * splitting; J1 and Y1 from their power series, used for |k| <= 10 (at |k| = 10 about
+ * 1e-9 of the sums is lost to cancellation).  Nodes with |k| > 10 get a NaN matrix,
+ * which nep_indicator reports as NEP_WARN_SINGULAR_NODE with the disk flagged.  The
  * context is unused (NULL).  Its singular points in the lower half-plane are the
  * zeros of the Hankel functions H_m, each double (modes m and -m).              */
 int nep_assemble_circle_double_layer(void* ctx, int n, const void* z_dev, int nb, void* W_dev, long long mstride,

@@ -598,6 +598,10 @@ hipError_t launch_elementwise_delay(const double2* A0, const double2* A1, const 
 // Y1 come from their power series in w = k r / 2 (|w| <= |k|: all terms decay after
 // q ~ |w|, at most 60 of them); L2 = -1/(2 pi) on the diagonal.  One thread per entry,
 // grid (ceil(P^2 / 256), nb).
+// |k| up to which the power series are used: |w| <= |k|, the largest term is about
+// |k|^(2q+1) / (q! (q+1)!) at q ~ |k| (~1e7 at |k| = 10, so ~1e-9 of the sums is lost to
+// cancellation) and 60 terms reach the 1e-18 stopping level
+constexpr double CDL_MAX_K = 10.0;
 __global__ __launch_bounds__(256) void circle_double_layer_kernel(int P, const double2* __restrict__ kz,
                                                                   double2* __restrict__ W, long long mstride) {
   constexpr double PI = 3.141592653589793238, EULER = 0.5772156649015328606;
@@ -607,6 +611,12 @@ __global__ __launch_bounds__(256) void circle_double_layer_kernel(int P, const d
   const int i = e / P, j = e - i * P;
   const int m = P / 2;
   const double2 k = kz[b];
+  if (!(k.x * k.x + k.y * k.y <= CDL_MAX_K * CDL_MAX_K)) {
+    // beyond the series' range (or a non-finite node): the node's matrix is NaN, which
+    // the sweep reports as a non-finite node solution (warning, disk flagged)
+    W[(long long)b * mstride + e] = cmk<double>(__builtin_nan(""), __builtin_nan(""));
+    return;
+  }
   const double d = 2.0 * PI * (double)(i - j) / (double)P;
   double R = 0.0;
   for (int l = 1; l < m; ++l) R += cos(l * d) / l;

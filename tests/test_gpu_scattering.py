@@ -79,3 +79,25 @@ def test_pmcima_paper_region(N):
     # Step 2: the vector is a null vector of T at the pole to O(tol_eps)
     for lam, v in zip(r.eigs, r.vectors):
         assert np.linalg.norm(oracle.assemble(prob, lam) @ v) < 1e-5
+
+
+def test_wavenumbers_beyond_the_series_range_are_reported(N):
+    # |k| > 10 lies outside the power series' range: the assembler writes a NaN matrix at
+    # such nodes, the sweep reports them as non-finite node solutions and flags their
+    # disks; a disk inside the range keeps the oracle's flag
+    prob = gen.CircleDoubleLayer(16)
+    reg = gen.Region(7.0, 13.0, -0.5, 0.0, 3, 1)            # disk 0 inside |k| <= 10, disk 2 beyond
+    opts = gen.Options(N=16, s=1, L=0)
+    F = gen.probes(11, 16, 1)
+    say("case scattering wavenumbers beyond |k| = 10")
+    cov = oracle.cover(reg)
+    assert abs(cov[0].c) + cov[0].r < 10.0 and abs(cov[2].c) - cov[2].r > 10.0
+    plan = N.nep_plan([prob], [reg], opts)
+    try:
+        ind, flags, _, st = N.nep_indicator(plan, [F])
+    finally:
+        N.nep_destroy(plan)
+    assert st == N.NEP_WARN_SINGULAR_NODE
+    assert flags[1] and flags[2]
+    I0, _ = oracle.sweep_disk(prob, cov[0].c, cov[0].r, opts.N, F, None).indicator()
+    assert np.isfinite(ind[0]).all() and bool(flags[0]) == (I0 > opts.tol_ind)
