@@ -327,7 +327,7 @@ def scattering_run():
                        "levels": pa.levels, "node_solves": int(pa.node_solves)}}
 
 
-def complete_spectrum(pivot: int, reps: int = 1):
+def complete_spectrum(pivot: int, reps: int = 2):
     """The saturation remedy on the dense workload (cells split until no flagged disk
     saturates, candidates refined and verified): eigenpairs/s of the complete spectrum
     and the worst relative error against the companion pencil, per precision."""
@@ -477,7 +477,7 @@ def roofline(st, prec, workload=None):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="dense")
     ap.add_argument("--delay-count", type=int, default=8)
