@@ -101,3 +101,30 @@ def test_delay_lambert_roots():
     res = P.pmcima(prob, reg, gen.probes(6, n, 1), vectors=False)
     assert len(res.eigs) == len(inside)
     assert _one_to_one(res.eigs, inside, 1e-6) <= 0.5e-6
+
+
+def test_sim_quadtree_labels_against_root_positions():
+    # a rotated diagonal linear problem with known roots: a child's disk is flagged
+    # exactly when it holds a root, for roots kept at least 0.15 r away from every
+    # child circle (inside: I ~ 1 per root; outside: I ~ q^{N/2} << tol_ind); the root
+    # is always split, and only flagged children are split again, in cover order
+    roots = np.array([0.61 + 0.37j, -1.22 - 1.41j, 2.63 - 0.52j, -2.9 + 2.7j, 3.55 + 3.45j])
+    n = len(roots)
+    prob = gen.rotated_diagonal(roots, 19)
+    F = gen.probes(23, n, 1)
+    recs = P.sim_quadtree_labels(prob, (-4.0, 4.0, -4.0, 4.0), 3, F, N=32)
+
+    def holds(c, r):
+        return np.abs(roots - c) < r
+
+    parents = {(-4.0, 4.0, -4.0, 4.0)}
+    for level, cell, ind in recs:
+        assert cell in parents, (level, cell)
+        for (ch, c, r), I in zip(P.children(cell), ind):
+            d = np.abs(np.abs(roots - c) - r)
+            if np.all(d > 0.15 * r):
+                assert (I > 0.1) == bool(holds(c, r).any()), (level, ch, I)
+            if I > 0.1 and level < 2:
+                parents.add(ch)
+    # level 0 has one record; each later record's cell was a flagged child of the previous level
+    assert [lv for lv, _, _ in recs].count(0) == 1
