@@ -1879,6 +1879,99 @@ __global__ __launch_bounds__(256) void solve_rows_kernel(const c2<T>* __restrict
     }
 }
 
+// solve_top_kernel for a single right-hand side: the step's row exchange (forward), then
+// the block of the solution as a 64 x 64 matrix-vector product with inv(L11) (forward)
+// or inv(U11) (backward), 16 lanes per row, partial sums added by lane shuffles.
+template <typename T, int NB, bool FWD>
+__global__ __launch_bounds__(256) void solve_top1_kernel(const c2<T>* __restrict__ W, long long mstride, int n,
+                                                         int step, const int* __restrict__ perm,
+                                                         long long perm_stride, const c2<T>* __restrict__ Inv,
+                                                         long long inv_stride, double2* __restrict__ X,
+                                                         long long xstride, const int* __restrict__ active) {
+  const int b = blockIdx.x;
+  if (active && !active[b]) return;
+  const int t = threadIdx.x, kl = t & 15, rl = t >> 4;
+  double2* Xb = X + (long long)b * xstride;
+  const int k0 = step * NB, nbk = min(NB, n - k0);
+  __shared__ c2<T> xs[NB];
+  if (FWD) {
+    // new[pos[i]] = old[src[i]], pos[i] = k0 + i for i < nbk: the new top rows go to
+    // LDS, the displaced ones are written after every old value has been read
+    const int* P = perm + (long long)b * perm_stride + (long long)step * (1 + 4 * NB);
+    const int cnt = P[0];
+    double2 dv = make_double2(0.0, 0.0);
+    int dpos = -1;
+    if (t < nbk) xs[t] = ccast<T, double>(Xb[P[1 + 2 * NB + t]]);
+    else if (t < NB) xs[t] = czero<T>();
+    if (t >= nbk && t < cnt) {
+      dv = Xb[P[1 + 2 * NB + t]];
+      dpos = P[1 + t];
+    }
+    __syncthreads();
+    if (dpos >= 0) Xb[dpos] = dv;
+  } else {
+    if (t < NB) xs[t] = (t < nbk) ? ccast<T, double>(Xb[k0 + t]) : czero<T>();
+    __syncthreads();
+  }
+  const c2<T>* Ib = Inv + (long long)b * inv_stride + (long long)step * NB * NB;
+#pragma unroll
+  for (int pass = 0; pass < NB / 16; ++pass) {
+    const int r = pass * 16 + rl;
+    c2<T> acc = czero<T>();
+    if (r < nbk) {
+#pragma unroll
+      for (int j = 0; j < NB / 16; ++j) {
+        const int k = kl + 16 * j;
+        if (k < nbk) acc = cfma<T>(acc, Ib[(long long)r * NB + k], xs[k]);
+      }
+    }
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) {
+      acc.x += __shfl_xor(acc.x, o, 16);
+      acc.y += __shfl_xor(acc.y, o, 16);
+    }
+    if (kl == 0 && r < nbk) Xb[k0 + r] = ccast<double, T>(acc);
+  }
+}
+
+// solve_rows_kernel for a single right-hand side: the tile product is a matrix-vector
+// product, so the factor's rows are streamed straight from global memory with no LDS
+// staging and no barrier.  A workgroup owns 16 rows, 16 lanes per row read 16
+// consecutive entries (one 128-byte line per row per load in complex64, two in
+// complex128) and the 16 partial sums of a row are added by lane shuffles.
+template <typename T, int NB>
+__global__ __launch_bounds__(256) void solve_rows1_kernel(const c2<T>* __restrict__ W, long long mstride, int n,
+                                                          int step, int r_lo, int r_hi, int tiles,
+                                                          double2* __restrict__ X, long long xstride,
+                                                          const int* __restrict__ active) {
+  const int b = blockIdx.x / tiles, tl = blockIdx.x % tiles;
+  if (active && !active[b]) return;
+  const int t = threadIdx.x, kl = t & 15, rl = t >> 4;
+  const int k0 = step * NB, nbk = min(NB, n - k0);
+  const int row = r_lo + tl * 16 + rl;
+  const c2<T>* A = W + (long long)b * mstride;
+  double2* Xb = X + (long long)b * xstride;
+  c2<T> acc = czero<T>();
+  if (row < r_hi) {
+    const c2<T>* Ar = A + (long long)row * n + k0;
+#pragma unroll
+    for (int j = 0; j < NB / 16; ++j) {
+      const int k = kl + 16 * j;
+      if (k < nbk) acc = cfma<T>(acc, Ar[k], ccast<T, double>(Xb[k0 + k]));
+    }
+  }
+  // the 16 lanes of a row are consecutive: reduce within each group of 16
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) {
+    acc.x += __shfl_xor(acc.x, o, 16);
+    acc.y += __shfl_xor(acc.y, o, 16);
+  }
+  if (kl == 0 && row < r_hi) {
+    const double2 x = Xb[row];
+    Xb[row] = make_double2(x.x - (double)acc.x, x.y - (double)acc.y);
+  }
+}
+
 // ----------------------------------------------------------------------------- launchers
 template <typename T>
 static void launch_trailing(c2<T>* W, long long mstride, int n, int nbatch, int k0, int nbk, int s, int* perm,
@@ -2059,9 +2152,17 @@ static void solve_launch(const c2<T>* W, long long mstride, int n, int nbatch, c
     const int nsteps = (n + NB - 1) / NB;
     for (int s = 0; s < nsteps; ++s) {
       const int k0 = s * NB, kend = min(n, k0 + NB);
-      solve_top_kernel<T, NB, true, JN><<<nbatch, 256, 0, st>>>(W, mstride, n, s, perm, perm_stride, Linv, inv_stride,
-                                                            X, xstride, m, active);
-      if (kend < n) {
+      if (m == 1)
+        solve_top1_kernel<T, NB, true><<<nbatch, 256, 0, st>>>(W, mstride, n, s, perm, perm_stride, Linv, inv_stride,
+                                                             X, xstride, active);
+      else
+        solve_top_kernel<T, NB, true, JN><<<nbatch, 256, 0, st>>>(W, mstride, n, s, perm, perm_stride, Linv,
+                                                                inv_stride, X, xstride, m, active);
+      if (kend < n && m == 1) {
+        const int tiles = (n - kend + 15) / 16;
+        solve_rows1_kernel<T, NB><<<dim3((unsigned)(nbatch * tiles)), 256, 0, st>>>(W, mstride, n, s, kend, n, tiles,
+                                                                                X, xstride, active);
+      } else if (kend < n) {
         const int tiles = (n - kend + 63) / 64;
         solve_rows_kernel<T, NB, JN><<<dim3((unsigned)(nbatch * tiles)), 256, 0, st>>>(W, mstride, n, s, kend, n, tiles,
                                                                                   X, xstride, m, active);
@@ -2069,9 +2170,17 @@ static void solve_launch(const c2<T>* W, long long mstride, int n, int nbatch, c
     }
     for (int s = nsteps - 1; s >= 0; --s) {
       const int k0 = s * NB;
-      solve_top_kernel<T, NB, false, JN><<<nbatch, 256, 0, st>>>(W, mstride, n, s, perm, perm_stride, Uinv, inv_stride,
-                                                             X, xstride, m, active);
-      if (k0 > 0) {
+      if (m == 1)
+        solve_top1_kernel<T, NB, false><<<nbatch, 256, 0, st>>>(W, mstride, n, s, perm, perm_stride, Uinv, inv_stride,
+                                                              X, xstride, active);
+      else
+        solve_top_kernel<T, NB, false, JN><<<nbatch, 256, 0, st>>>(W, mstride, n, s, perm, perm_stride, Uinv,
+                                                                 inv_stride, X, xstride, m, active);
+      if (k0 > 0 && m == 1) {
+        const int tiles = (k0 + 15) / 16;
+        solve_rows1_kernel<T, NB><<<dim3((unsigned)(nbatch * tiles)), 256, 0, st>>>(W, mstride, n, s, 0, k0, tiles, X,
+                                                                                xstride, active);
+      } else if (k0 > 0) {
         const int tiles = (k0 + 63) / 64;
         solve_rows_kernel<T, NB, JN><<<dim3((unsigned)(nbatch * tiles)), 256, 0, st>>>(W, mstride, n, s, 0, k0, tiles,
                                                                                   X, xstride, m, active);
