@@ -7,10 +7,12 @@ namespace nep {
 
 constexpr int LU_NB = 64;   // panel width
 // The solve runs step by step over many workgroups per matrix for orders >= 256 with
-// at most 8 right-hand sides; with more columns one workgroup per matrix has enough
-// work per load (measured: delay workload, m = 1, solve and refinement phases 1.4-1.6x
-// faster split; dense workload, m = 20, no gain).
+// at most 8 right-hand sides (measured: delay workload, m = 1, solve and refinement
+// phases 1.4-1.6x faster split), and for orders >= LU_SOLVE_MFMA_N with 9 to 32 on the
+// matrix cores (dense workload, m = 20: 1.4x faster than one workgroup per matrix; the
+// same steps on the vector units gave no gain there).
 constexpr int LU_SOLVE_SPLIT_N = 256, LU_SOLVE_SPLIT_M = 8;
+constexpr int LU_SOLVE_MFMA_N = 512;
 
 // Per-step row-exchange record: [cnt, pos[2*NB], src[2*NB]] ints per step per matrix.
 constexpr long long perm_ints_per_step() { return 1 + 4 * LU_NB; }

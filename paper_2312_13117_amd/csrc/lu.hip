@@ -1972,6 +1972,256 @@ __global__ __launch_bounds__(256) void solve_rows1_kernel(const c2<T>* __restric
   }
 }
 
+// solve_rows_kernel on the matrix cores for 9 to 32 right-hand sides.  A workgroup
+// takes up to SOLVE_TPW consecutive 64-row tiles of one matrix, a wave 16 rows of each
+// and all 16 JB columns (16 x 16 blocks of the 16x16x4 MFMA).  The factor goes from
+// global memory straight into the A operands: for each group of 16 entries of a row a
+// lane reads the 4 consecutive ones its 4 products take (the sum over k is regrouped
+// to match: in product u of group g the lanes of quarter kq take k = 16 g + 4 kq + u),
+// so a wave's load covers 64 contiguous bytes of each of its 16 rows.  Each group's
+// registers are refilled with the same group of the next tile as soon as they are
+// used, one tile ahead of the products.  The step's block of X is staged once per
+// workgroup in LDS as the B operands; the tiles of a matrix share one XCD, so the block
+// stays in its L2.  The products start from zero and are subtracted from the tile's
+// rows of X at its end.  complex128 forms each
+// complex product from three real ones (as the paired update), complex64 from four.
+constexpr int SOLVE_TPW = 4;
+// two workgroups per CU for complex128 (a tile of operands in flight, the tile's rows
+// of X and three accumulator sets need up to 256 registers), three for complex64
+template <typename T, int JB>
+constexpr int solve_rowsm_min_blocks() { return sizeof(T) == 8 ? 2 : 3; }
+template <typename T, int NB, int JB>
+__global__ __launch_bounds__(256, (solve_rowsm_min_blocks<T, JB>())) void solve_rowsm_kernel(const c2<T>* __restrict__ W, long long mstride, int n,
+                                                             int step, int r_lo, int r_hi, int tiles, int nbatch,
+                                                             double2* __restrict__ X, long long xstride, int m,
+                                                             const int* __restrict__ active) {
+  constexpr int NC = 16 * JB, G = NB / 16;
+  constexpr bool G3 = sizeof(T) == 8;
+  const int wpm = (tiles + SOLVE_TPW - 1) / SOLVE_TPW;   // workgroups per matrix
+  const int wg = blockIdx.x, xcd = wg & 7, slot = wg >> 3;
+  const int b = (slot / wpm) * 8 + xcd, w = slot % wpm;
+  if (b >= nbatch || (active && !active[b])) return;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, l16 = lane & 15, kq = lane >> 4;
+  const int k0 = step * NB, nbk = min(NB, n - k0);
+  const int tfirst = w * SOLVE_TPW, tcount = min(SOLVE_TPW, tiles - tfirst);
+  const c2<T>* A = W + (long long)b * mstride;
+  double2* Xb = X + (long long)b * xstride;
+  // Every load below is issued unconditionally at a clamped in-range address: with no
+  // branches or selects next to them the compiler can wait for each group of operands
+  // alone instead of for every load in flight.
+  // the step's block of X into LDS (its loads first, so that waiting for them does not
+  // wait for the operands issued next)
+  __shared__ c2<T> Xs[NB][NC];
+  constexpr int XE = NB * NC / 256;
+  double2 xs[XE];
+#pragma unroll
+  for (int q = 0; q < XE; ++q) {
+    const int e = t + q * 256, k = e / NC, c = e % NC;
+    xs[q] = Xb[(long long)(k0 + min(k, nbk - 1)) * m + min(c, m - 1)];
+  }
+  __builtin_amdgcn_sched_barrier(0);   // these loads stay ahead of the operands'
+  // A operands of group g of tile i: row r_lo + 64 (tfirst + i) + 16 wave + l16,
+  // entries 16 g + 4 kq + 0..3
+  c2<T> af[G][4];
+  // Out-of-range operands are read at clamped addresses and not masked: a row past the
+  // range only feeds outputs that are not stored, and an entry k >= nbk (the last step
+  // of an order that is not a multiple of 64) meets a zero row of the X block, being a
+  // copy of the row's entry nbk - 1 (finite wherever that one is).  Past the last tile
+  // (i == tcount) the last tile is read again (from L2; values unused).
+  auto load_a = [&](int g, int i) {
+    const int row = min(r_lo + (tfirst + min(i, tcount - 1)) * 64 + wave * 16 + l16, r_hi - 1);
+    const c2<T>* Ar = A + (long long)row * n + k0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) af[g][u] = Ar[min(16 * g + 4 * kq + u, nbk - 1)];
+  };
+#pragma unroll
+  for (int g = 0; g < G; ++g) load_a(g, 0);
+#pragma unroll
+  for (int q = 0; q < XE; ++q) {
+    const int e = t + q * 256, k = e / NC, c = e % NC;
+    Xs[k][c] = (k < nbk && c < m) ? ccast<T, double>(xs[q]) : czero<T>();
+  }
+  // the LDS writes done, then the barrier alone: __syncthreads() would also wait for
+  // the operand loads in flight
+  __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0)
+  __builtin_amdgcn_s_barrier();
+  // the tile loop is unrolled (no loop-carried copies of the prefetched operands)
+#pragma unroll
+  for (int i = 0; i < SOLVE_TPW; ++i) {
+    if (i >= tcount) break;
+    const int R0 = r_lo + (tfirst + i) * 64 + wave * 16;
+    // the tile's rows of X, loaded before the next tile's operands so that waiting for
+    // them does not wait for those
+    double2 xv[JB][4];
+#pragma unroll
+    for (int bj = 0; bj < JB; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = R0 + acc_row<T>(lane, r), col = bj * 16 + l16;
+        xv[bj][r] = Xb[(long long)min(row, r_hi - 1) * m + min(col, m - 1)];
+      }
+    __builtin_amdgcn_sched_barrier(0);   // these loads stay ahead of the next tile's
+    acc4<T> p1[JB], p2[JB], p3[JB];
+#pragma unroll
+    for (int bj = 0; bj < JB; ++bj) {
+      p1[bj] = acc_zero<T>();
+      p2[bj] = acc_zero<T>();
+      p3[bj] = acc_zero<T>();
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = 16 * g + 4 * kq + u;
+        const c2<T> a = af[g][u];
+        c2<T> bf[JB];
+#pragma unroll
+        for (int bj = 0; bj < JB; ++bj) bf[bj] = Xs[k][bj * 16 + l16];
+        if (G3) {
+          // p1 = sum a.x b.x, p2 = -sum a.y b.y, p3 = sum (a.x + a.y)(b.x + b.y)
+          const T as = a.x + a.y;
+#pragma unroll
+          for (int bj = 0; bj < JB; ++bj) p1[bj] = mfma16(a.x, bf[bj].x, p1[bj]);
+#pragma unroll
+          for (int bj = 0; bj < JB; ++bj) p2[bj] = mfma16(-a.y, bf[bj].y, p2[bj]);
+#pragma unroll
+          for (int bj = 0; bj < JB; ++bj) p3[bj] = mfma16(as, bf[bj].x + bf[bj].y, p3[bj]);
+        } else {
+          // p1 = Re, p3 = Im of the product
+#pragma unroll
+          for (int bj = 0; bj < JB; ++bj) {
+            p1[bj] = mfma16(a.x, bf[bj].x, p1[bj]);
+            p3[bj] = mfma16(a.x, bf[bj].y, p3[bj]);
+          }
+#pragma unroll
+          for (int bj = 0; bj < JB; ++bj) {
+            p1[bj] = mfma16(-a.y, bf[bj].y, p1[bj]);
+            p3[bj] = mfma16(a.y, bf[bj].x, p3[bj]);
+          }
+        }
+      }
+      load_a(g, i + 1);
+      // keep the B-fragment reads of later groups from being hoisted here (they would
+      // hold a whole tile's fragments in registers)
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int bj = 0; bj < JB; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = R0 + acc_row<T>(lane, r), col = bj * 16 + l16;
+        const T re = G3 ? p1[bj][r] + p2[bj][r] : p1[bj][r];
+        const T im = G3 ? p3[bj][r] - p1[bj][r] + p2[bj][r] : p3[bj][r];
+        const double2 v = make_double2(xv[bj][r].x - (double)re, xv[bj][r].y - (double)im);
+        if (row < r_hi && col < m) Xb[(long long)row * m + col] = v;
+      }
+  }
+}
+
+// solve_top_kernel on the matrix cores for 9 to 32 right-hand sides (one workgroup per
+// matrix): the step's block of the solution, inv(L11) (forward, after the step's row
+// exchange) or inv(U11) (backward) times the block's rows, as one 64-row tile of
+// solve_rowsm_kernel's products with the inverse as the A operands.  Forward, the rows
+// the exchange displaces from the block are moved unchanged; every read of X precedes
+// the barrier, every write follows it.
+template <typename T, int NB, bool FWD, int JB>
+__global__ __launch_bounds__(256, (solve_rowsm_min_blocks<T, JB>())) void solve_topm_kernel(
+    int n, int step, const int* __restrict__ perm, long long perm_stride, const c2<T>* __restrict__ Inv,
+    long long inv_stride, double2* __restrict__ X, long long xstride, int m, const int* __restrict__ active) {
+  constexpr int NC = 16 * JB, G = NB / 16, XE = NB * NC / 256;
+  constexpr bool G3 = sizeof(T) == 8;
+  const int b = blockIdx.x;
+  if (active && !active[b]) return;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, l16 = lane & 15, kq = lane >> 4;
+  const int k0 = step * NB, nbk = min(NB, n - k0);
+  double2* Xb = X + (long long)b * xstride;
+  const c2<T>* Ib = Inv + (long long)b * inv_stride + (long long)step * NB * NB;
+  __shared__ c2<T> Xs[NB][NC];
+  __shared__ int s_pos[2 * NB], s_src[2 * NB], s_cnt;
+  int cnt = nbk;
+  if (FWD) {
+    const int* P = perm + (long long)b * perm_stride + (long long)step * (1 + 4 * NB);
+    if (t == 0) s_cnt = P[0];
+    for (int i = t; i < 2 * NB; i += 256) { s_pos[i] = P[1 + i]; s_src[i] = P[1 + 2 * NB + i]; }
+    __syncthreads();
+    cnt = s_cnt;
+  }
+  // inverse rows 16 wave + l16 (clamped to the block: rows past it are not stored),
+  // entries 16 g + 4 kq + 0..3 (clamped: entries past the block meet zero rows of Xs)
+  c2<T> af[G][4];
+  const c2<T>* Ar = Ib + (long long)min(wave * 16 + l16, nbk - 1) * NB;
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) af[g][u] = Ar[min(16 * g + 4 * kq + u, nbk - 1)];
+  // the block's rows (forward: the rows the exchange brings in) into LDS
+#pragma unroll
+  for (int q = 0; q < XE; ++q) {
+    const int e = t + q * 256, k = e / NC, c = e % NC;
+    const int kk = min(k, nbk - 1);
+    const int r = FWD ? s_src[kk] : k0 + kk;
+    const double2 v = Xb[(long long)r * m + min(c, m - 1)];
+    Xs[k][c] = (k < nbk && c < m) ? ccast<T, double>(v) : czero<T>();
+  }
+  __syncthreads();
+  // forward: the rows the exchange displaces from the block (old block rows, intact
+  // until the block is written after the second barrier) move below it
+  if constexpr (FWD) {
+    const int nd = cnt - nbk;
+    for (int e = t; e < nd * m; e += 256) {
+      const int i = e / m, c = e % m;
+      Xb[(long long)s_pos[nbk + i] * m + c] = Xb[(long long)s_src[nbk + i] * m + c];
+    }
+  }
+  acc4<T> p1[JB], p2[JB], p3[JB];
+#pragma unroll
+  for (int bj = 0; bj < JB; ++bj) {
+    p1[bj] = acc_zero<T>();
+    p2[bj] = acc_zero<T>();
+    p3[bj] = acc_zero<T>();
+  }
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = 16 * g + 4 * kq + u;
+      const c2<T> a = af[g][u];
+      c2<T> bf[JB];
+#pragma unroll
+      for (int bj = 0; bj < JB; ++bj) bf[bj] = Xs[k][bj * 16 + l16];
+      if (G3) {
+        const T as = a.x + a.y;
+#pragma unroll
+        for (int bj = 0; bj < JB; ++bj) p1[bj] = mfma16(a.x, bf[bj].x, p1[bj]);
+#pragma unroll
+        for (int bj = 0; bj < JB; ++bj) p2[bj] = mfma16(-a.y, bf[bj].y, p2[bj]);
+#pragma unroll
+        for (int bj = 0; bj < JB; ++bj) p3[bj] = mfma16(as, bf[bj].x + bf[bj].y, p3[bj]);
+      } else {
+#pragma unroll
+        for (int bj = 0; bj < JB; ++bj) {
+          p1[bj] = mfma16(a.x, bf[bj].x, p1[bj]);
+          p3[bj] = mfma16(a.x, bf[bj].y, p3[bj]);
+        }
+#pragma unroll
+        for (int bj = 0; bj < JB; ++bj) {
+          p1[bj] = mfma16(-a.y, bf[bj].y, p1[bj]);
+          p3[bj] = mfma16(a.y, bf[bj].x, p3[bj]);
+        }
+      }
+    }
+  if constexpr (FWD) __syncthreads();   // every displaced row has been read
+#pragma unroll
+  for (int bj = 0; bj < JB; ++bj)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = wave * 16 + acc_row<T>(lane, r), col = bj * 16 + l16;
+      const T re = G3 ? p1[bj][r] + p2[bj][r] : p1[bj][r];
+      const T im = G3 ? p3[bj][r] - p1[bj][r] + p2[bj][r] : p3[bj][r];
+      if (row < nbk && col < m) Xb[(long long)(k0 + row) * m + col] = make_double2((double)re, (double)im);
+    }
+}
+
 // ----------------------------------------------------------------------------- launchers
 template <typename T>
 static void launch_trailing(c2<T>* W, long long mstride, int n, int nbatch, int k0, int nbk, int s, int* perm,
@@ -2145,6 +2395,30 @@ static void solve_launch(const c2<T>* W, long long mstride, int n, int nbatch, c
                          int m, bool trans, const int* active, hipStream_t st) {
   if (trans) {
     lu_solve_kernel<T, LU_NB, true, JN><<<nbatch, 256, 0, st>>>(W, mstride, n, perm, perm_stride, Linv, Uinv, inv_stride, X, xstride, m, active);
+  } else if (m > LU_SOLVE_SPLIT_M && n >= LU_SOLVE_MFMA_N) {
+    constexpr int NB = LU_NB, JB = JN > 2 ? 2 : 1;
+    const int nsteps = (n + NB - 1) / NB;
+    const long long groups = (nbatch + 7) / 8;
+    for (int s = 0; s < nsteps; ++s) {
+      const int kend = min(n, s * NB + NB);
+      solve_topm_kernel<T, NB, true, JB><<<nbatch, 256, 0, st>>>(n, s, perm, perm_stride, Linv, inv_stride, X, xstride,
+                                                               m, active);
+      if (kend < n) {
+        const int tiles = (n - kend + 63) / 64, wpm = (tiles + SOLVE_TPW - 1) / SOLVE_TPW;
+        solve_rowsm_kernel<T, NB, JB><<<dim3((unsigned)(groups * 8 * wpm)), 256, 0, st>>>(
+            W, mstride, n, s, kend, n, tiles, nbatch, X, xstride, m, active);
+      }
+    }
+    for (int s = nsteps - 1; s >= 0; --s) {
+      const int k0 = s * NB;
+      solve_topm_kernel<T, NB, false, JB><<<nbatch, 256, 0, st>>>(n, s, perm, perm_stride, Uinv, inv_stride, X,
+                                                                xstride, m, active);
+      if (k0 > 0) {
+        const int tiles = (k0 + 63) / 64, wpm = (tiles + SOLVE_TPW - 1) / SOLVE_TPW;
+        solve_rowsm_kernel<T, NB, JB><<<dim3((unsigned)(groups * 8 * wpm)), 256, 0, st>>>(
+            W, mstride, n, s, 0, k0, tiles, nbatch, X, xstride, m, active);
+      }
+    }
   } else if (n < LU_SOLVE_SPLIT_N || m > LU_SOLVE_SPLIT_M) {
     lu_solve_kernel<T, LU_NB, false, JN><<<nbatch, 256, 0, st>>>(W, mstride, n, perm, perm_stride, Linv, Uinv, inv_stride, X, xstride, m, active);
   } else {

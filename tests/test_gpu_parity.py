@@ -101,8 +101,12 @@ def check_sums(N, plan, prob, reg, opts, F, V, tol, disks=None):
 # leaves of 8 columns in pairs; 1025 to
 # 2048 in complex64 leaves of 16 columns, two rows per thread; more: the streaming
 # panel (n = 1100, complex128; the largest orders below).  Orders >= 256 with <= 8
-# columns take the step-parallel solve.
+# columns take the step-parallel solve; orders >= 512 with 9 to 32 columns the
+# step-parallel solve with its row tiles on the matrix cores (m = 12: one 16-column
+# block; 20, 29 and 32: two; n = 600, 777 and 1030 end in a ragged block).
 @pytest.mark.parametrize("n,Nn,s,L,prec,pivot", [(4, 8, 1, 2, 0, 0), (37, 8, 1, 4, 0, 0), (100, 16, 2, 6, 0, 0),
+                                                 (600, 8, 4, 8, 0, 0), (777, 8, 4, 16, 1, 0),
+                                                 (1030, 4, 3, 26, 0, 0), (520, 8, 2, 30, 1, 0),
                                                  (200, 16, 1, 8, 0, 0), (200, 16, 1, 8, 1, 0),
                                                  (130, 12, 3, 5, 1, 0), (300, 8, 1, 4, 0, 0), (700, 8, 1, 4, 1, 0),
                                                  (4, 8, 1, 2, 0, 1), (200, 16, 1, 8, 0, 1), (130, 12, 3, 5, 1, 1),
