@@ -1158,6 +1158,13 @@ __global__ __launch_bounds__(256) void rpanel_finish_kernel(const c2<T>* __restr
   }
 }
 
+// A workgroup barrier that orders LDS accesses only: the caller first waits for what
+// must be complete (s_waitcnt), and the asm's memory clobber keeps the compiler from
+// moving any memory access across it.  __syncthreads() would also be a release/acquire
+// fence, which waits for every load in flight, including loads meant to stay in flight
+// across the barrier (and LDS loads issued by the memory units).
+__device__ __forceinline__ void barrier_only() { asm volatile("s_barrier" ::: "memory"); }
+
 // ----------------------------------------------------------------------------- matrix-core steps
 // 256 threads = 4 waves; a workgroup owns a 64 x 64 tile, a wave a 32 x 32 quarter
 // (2 x 2 blocks of 16 x 16, real and imaginary accumulators).  Workgroup ids are
@@ -1452,6 +1459,212 @@ __global__ __launch_bounds__(256, gemm_min_blocks<MODE>()) void lu_gemm_kernel(c
       if (e < ndisp * 64 && col < n) A[(long long)s_pos[i] * n + col] = dval[q];
     }
   }
+}
+
+// the products of one operand chunk of lu_update2_kernel (its swizzled A layout)
+template <typename T, int KC, int EPS>
+__device__ __forceinline__ void upd2_compute(acc4<T> (&c1)[2][2], acc4<T> (&c2a)[2][2], acc4<T> (&c3)[2][2],
+                                             const c2<T>* __restrict__ as, const c2<T>* __restrict__ bs, int wave,
+                                             int l16, int kq) {
+  constexpr bool G3 = sizeof(T) == 8;
+#pragma unroll
+  for (int ks = 0; ks < KC / 4; ++ks) {
+    const int k = ks * 4 + kq;
+    c2<T> af[2], bf[2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi) {
+      const int i = (wave >> 1) * 32 + bi * 16 + l16;
+      const c2<T> v = as[i * KC + (((k / EPS) ^ ((i >> 1) & 7)) * EPS) + k % EPS];
+      af[bi] = cmk<T>(-v.x, -v.y);     // C - A B
+    }
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) bf[bj] = bs[k * 64 + (wave & 1) * 32 + bj * 16 + l16];
+    if (G3) {
+      T as_[2], bs_[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        as_[q] = af[q].x + af[q].y;
+        bs_[q] = bf[q].x + bf[q].y;
+      }
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) c1[bi][bj] = mfma16(af[bi].x, bf[bj].x, c1[bi][bj]);
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) c2a[bi][bj] = mfma16(-af[bi].y, bf[bj].y, c2a[bi][bj]);
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) c3[bi][bj] = mfma16(as_[bi], bs_[bj], c3[bi][bj]);
+    } else {
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+          c1[bi][bj] = mfma16(af[bi].x, bf[bj].x, c1[bi][bj]);
+          c3[bi][bj] = mfma16(af[bi].x, bf[bj].y, c3[bi][bj]);
+        }
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+          c1[bi][bj] = mfma16(-af[bi].y, bf[bj].y, c1[bi][bj]);
+          c3[bi][bj] = mfma16(af[bi].y, bf[bj].x, c3[bi][bj]);
+        }
+    }
+  }
+}
+
+// The paired trailing update (GEMM_UPDATE2's product, same tiles, operands and
+// arithmetic) with its operand chunks loaded by the memory units straight into LDS
+// (global_load_lds_dwordx4: a lane's 16 bytes land at the instruction's LDS base + 16
+// lane) three chunks deep, so that a chunk's loads are issued two chunks of products
+// before they are read; the register-staged form waits for each chunk one chunk after
+// issuing it.  A chunk is 64 rows x KC entries of A (8 slots of 16 bytes per row) and
+// KC rows x 64 columns of B, 8 KB each.  The A slots of row i are stored XOR-swizzled
+// (slot s holds entries (s ^ ((i >> 1) & 7)) EPS ..) so that the 16 rows a quarter-wave
+// reads for one k fall on 16 different bank groups; B rows are read along columns and
+// need none.  Rows and columns past the matrix are read at clamped addresses (they only
+// feed outputs that are not stored).  The launcher sends full pairs only (K = 128: 16
+// chunks in complex128, 8 in complex64; a last pair narrower than 128 columns takes
+// lu_gemm_kernel) and, in complex64, even orders (16-byte aligned rows).
+template <typename T>
+__global__ __launch_bounds__(256, 3) void lu_update2_kernel(c2<T>* __restrict__ W, long long mstride, int n, int k0,
+                                                            int nbk, int step, int nbatch, int tiles,
+                                                            const int* __restrict__ perm, long long perm_stride) {
+  typedef __attribute__((address_space(3))) void* lds_ptr;
+  constexpr int NBMAX = 64;
+  constexpr int EPS = 16 / (int)sizeof(c2<T>);     // complex entries per 16-byte slot
+  constexpr int KC = 8 * EPS;                      // chunk depth: 8 (complex128), 16 (complex64)
+  constexpr bool G3 = sizeof(T) == 8;
+  const int wg = blockIdx.x, xcd = wg & 7, slot = wg >> 3;
+  const int ntile = tiles * tiles;
+  const int b = (slot / ntile) * 8 + xcd;
+  if (b >= nbatch) return;
+  const int tile = slot % ntile, tr = tile / tiles, tcn = tile % tiles;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, l16 = lane & 15, kq = lane >> 4;
+  c2<T>* A = W + (long long)b * mstride;
+  const int kend = k0 + nbk, k0p = k0 - NBMAX;
+  const int R0 = kend + tr * 64, C0 = kend + tcn * 64;
+  constexpr int NCH = 2 * NBMAX / KC;             // full pairs only: K = 128
+  const int rb = R0 + (wave >> 1) * 32, cb = C0 + (wave & 1) * 32;
+
+  // s_from[i] = the row whose step-s multipliers position R0 + i uses (positions past
+  // the matrix: its last row)
+  __shared__ int s_from[64];
+  {
+    const int* P = perm + (long long)b * perm_stride + (long long)step * (1 + 4 * NBMAX);
+    if (t < 64) s_from[t] = min(R0 + t, n - 1);
+    __syncthreads();
+    const int cnt = P[0];
+    if (t < cnt - nbk) {
+      const int pos = P[1 + nbk + t];
+      if (pos >= R0 && pos < R0 + 64) s_from[pos - R0] = P[1 + 2 * NBMAX + nbk + t];
+    }
+    __syncthreads();
+  }
+
+  // the C tile's loads first: they complete with chunk 0's
+  c2<T> cv[2][2][4];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+      const int col = min(cb + bj * 16 + l16, n - 1);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = min(rb + bi * 16 + acc_row<T>(lane, r), n - 1);
+        cv[bi][bj][r] = A[(long long)row * n + col];
+      }
+    }
+
+  // this wave's two A and two B load instructions per chunk: instruction j = 2 wave + q
+  // covers A rows 8 j .. 8 j + 7 (lane: row 8 j + lane / 8, slot lane % 8) and B's
+  // 1 KB row block j (complex128: row j, column lane; complex64: row 2 j + lane / 32,
+  // columns 2 (lane % 32) + 0, 1)
+  long long a_lo[2], a_hi[2];
+  int a_sw[2];
+  long long b_off[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int j = 2 * wave + q, i = 8 * j + (lane >> 3);
+    a_lo[q] = (long long)s_from[i] * n + k0p;
+    a_hi[q] = (long long)min(R0 + i, n - 1) * n + k0 - NBMAX;
+    a_sw[q] = ((lane & 7) ^ ((i >> 1) & 7)) * EPS;
+    if (EPS == 1)
+      b_off[q] = (long long)(k0p + j) * n + min(C0 + lane, n - 1);
+    else
+      b_off[q] = (long long)(k0p + 2 * j + (lane >> 5)) * n + min(C0 + 2 * (lane & 31), n - 2);
+  }
+  __shared__ __align__(16) c2<T> As0[64 * KC], As1[64 * KC], As2[64 * KC];
+  __shared__ __align__(16) c2<T> Bs0[KC * 64], Bs1[KC * 64], Bs2[KC * 64];
+  auto issue = [&](c2<T>* as, c2<T>* bs, int c) {
+    const int kc = c * KC;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int j = 2 * wave + q;
+      const c2<T>* ga = A + (kc < NBMAX ? a_lo[q] : a_hi[q]) + kc + a_sw[q];
+      __builtin_amdgcn_global_load_lds((const void*)ga, (lds_ptr)(as + j * 64 * EPS), 16, 0, 0);
+      const c2<T>* gb = A + b_off[q] + (long long)kc * n;
+      __builtin_amdgcn_global_load_lds((const void*)gb, (lds_ptr)(bs + j * 64 * EPS), 16, 0, 0);
+    }
+  };
+  // Chunk c: issue chunk c + 2 into the buffer chunk c - 1 used (free since the last
+  // barrier), multiply chunk c, wait for this wave's loads of chunk c + 1 (its four
+  // loads of chunk c + 2 may stay in flight) and for its LDS traffic (lgkmcnt(0): with
+  // the vector-memory count alone, orders from 1600 on gave wrong sums now and then),
+  // and meet the other waves, whose loads of chunk c + 1 are then complete too.  The loop is unrolled, so every buffer is a
+  // distinct array at every use and the compiler's own waits never cover the loads
+  // still in flight.
+  issue(As0, Bs0, 0);
+  issue(As1, Bs1, 1);
+  __builtin_amdgcn_sched_barrier(0);    // nothing that reads C moves above
+  __builtin_amdgcn_s_waitcnt(0x0074);   // vmcnt(4) lgkmcnt(0): chunk 0 and the C loads before it
+  barrier_only();
+  // accumulators from C (3M: A1 = Re C, A2 = 0, A3 = Im C + Re C)
+  acc4<T> c1[2][2], c2a[2][2], c3[2][2];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+      c2a[bi][bj] = acc_zero<T>();
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        c1[bi][bj][r] = cv[bi][bj][r].x;
+        c3[bi][bj][r] = G3 ? cv[bi][bj][r].y + cv[bi][bj][r].x : cv[bi][bj][r].y;
+      }
+    }
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    c2<T>* as = c % 3 == 0 ? As0 : (c % 3 == 1 ? As1 : As2);
+    c2<T>* bs = c % 3 == 0 ? Bs0 : (c % 3 == 1 ? Bs1 : Bs2);
+    c2<T>* an = c % 3 == 0 ? As2 : (c % 3 == 1 ? As0 : As1);
+    c2<T>* bn = c % 3 == 0 ? Bs2 : (c % 3 == 1 ? Bs0 : Bs1);
+    if (c + 2 < NCH) issue(an, bn, c + 2);
+    upd2_compute<T, KC, EPS>(c1, c2a, c3, as, bs, wave, l16, kq);
+    if (c + 1 < NCH) {
+      if (c + 2 < NCH) __builtin_amdgcn_s_waitcnt(0x0074);   // vmcnt(4) lgkmcnt(0)
+      else __builtin_amdgcn_s_waitcnt(0x0070);               // vmcnt(0) lgkmcnt(0)
+      barrier_only();
+    }
+  }
+
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+      const int col = cb + bj * 16 + l16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = rb + bi * 16 + acc_row<T>(lane, r);
+        if (row < n && col < n) {
+          const T a1 = c1[bi][bj][r], a3 = c3[bi][bj][r];
+          A[(long long)row * n + col] = G3 ? cmk<T>(a1 + c2a[bi][bj][r], a3 - a1 + c2a[bi][bj][r]) : cmk<T>(a1, a3);
+        }
+      }
+    }
 }
 
 // ----------------------------------------------------------------------------- solves
@@ -2041,10 +2254,9 @@ __global__ __launch_bounds__(256, (solve_rowsm_min_blocks<T, JB>())) void solve_
     const int e = t + q * 256, k = e / NC, c = e % NC;
     Xs[k][c] = (k < nbk && c < m) ? ccast<T, double>(xs[q]) : czero<T>();
   }
-  // the LDS writes done, then the barrier alone: __syncthreads() would also wait for
-  // the operand loads in flight
+  // the LDS writes done, then the barrier alone (the operand loads stay in flight)
   __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0)
-  __builtin_amdgcn_s_barrier();
+  barrier_only();
   // the tile loop is unrolled (no loop-carried copies of the prefetched operands)
 #pragma unroll
   for (int i = 0; i < SOLVE_TPW; ++i) {
@@ -2344,7 +2556,9 @@ hipError_t lu_factor_batch(c2<T>* W, long long mstride, int n, int nbatch, void*
     const bool timed = mode == GEMM_UPDATE2 && tm && tm->ev_enabled && tm->npairs < LuTimers::MAXP;
     if (timed) hipEventRecord(tm->ev[2 * tm->npairs], st);
     const dim3 grid((unsigned)(groups * 8 * tc * tc));
-    if (mode == GEMM_UPDATE2)
+    if (mode == GEMM_UPDATE2 && nbk == NB && (sizeof(T) == 8 || n % 2 == 0))
+      lu_update2_kernel<T><<<grid, 256, 0, st>>>(W, mstride, n, k0, nbk, s, nbatch, tc, perm, perm_stride);
+    else if (mode == GEMM_UPDATE2)
       lu_gemm_kernel<T, GEMM_UPDATE2><<<grid, 256, 0, st>>>(W, mstride, n, k0, nbk, s, nbatch, tc, tc, perm,
                                                              perm_stride, Linv, inv_stride);
     else
