@@ -462,7 +462,7 @@ def roofline(st, prec, workload=None):
     # complex128 products are formed from 3 real products (3M): the matrix cores execute
     # 6 of the 8 credited flops per complex multiply-add; complex64 uses all 4 (8 of 8)
     executed = 0.75 if prec == "fp64" else 1.0
-    return {"kernel": "lu_update2_kernel (trailing update of the batched LU, two panels per pass, K = 128, operands loaded straight into LDS)",
+    return {"kernel": "lu_gemm_dma_kernel<UPDATE2> (trailing update of the batched LU, two panels per pass, K = 128, operands loaded straight into LDS)",
             "bound": "mfma",
             "achieved": achieved / 1e12, "peak": PEAK[prec] / 1e12, "unit": "TFLOP/s",
             "frac": achieved / PEAK[prec], "traffic": traffic, "traffic_unit": "bytes per launch (HBM, counters)",

@@ -1461,12 +1461,12 @@ __global__ __launch_bounds__(256, gemm_min_blocks<MODE>()) void lu_gemm_kernel(c
   }
 }
 
-// the products of one operand chunk of lu_update2_kernel (its swizzled A layout)
-template <typename T, int KC, int EPS>
+// the products of one operand chunk of lu_gemm_dma_kernel (its swizzled A layout)
+template <typename T, int KC, int EPS, bool SUB>
 __device__ __forceinline__ void upd2_compute(acc4<T> (&c1)[2][2], acc4<T> (&c2a)[2][2], acc4<T> (&c3)[2][2],
                                              const c2<T>* __restrict__ as, const c2<T>* __restrict__ bs, int wave,
                                              int l16, int kq) {
-  constexpr bool G3 = sizeof(T) == 8;
+  constexpr bool G3 = SUB && sizeof(T) == 8;
 #pragma unroll
   for (int ks = 0; ks < KC / 4; ++ks) {
     const int k = ks * 4 + kq;
@@ -1475,7 +1475,7 @@ __device__ __forceinline__ void upd2_compute(acc4<T> (&c1)[2][2], acc4<T> (&c2a)
     for (int bi = 0; bi < 2; ++bi) {
       const int i = (wave >> 1) * 32 + bi * 16 + l16;
       const c2<T> v = as[i * KC + (((k / EPS) ^ ((i >> 1) & 7)) * EPS) + k % EPS];
-      af[bi] = cmk<T>(-v.x, -v.y);     // C - A B
+      af[bi] = SUB ? cmk<T>(-v.x, -v.y) : v;     // C - A B, or A B
     }
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) bf[bj] = bs[k * 64 + (wave & 1) * 32 + bj * 16 + l16];
@@ -1530,31 +1530,36 @@ __device__ __forceinline__ void upd2_compute(acc4<T> (&c1)[2][2], acc4<T> (&c2a)
 // feed outputs that are not stored).  The launcher sends full pairs only (K = 128: 16
 // chunks in complex128, 8 in complex64; a last pair narrower than 128 columns takes
 // lu_gemm_kernel) and, in complex64, even orders (16-byte aligned rows).
-template <typename T>
-__global__ __launch_bounds__(256, 3) void lu_update2_kernel(c2<T>* __restrict__ W, long long mstride, int n, int k0,
-                                                            int nbk, int step, int nbatch, int tiles,
-                                                            const int* __restrict__ perm, long long perm_stride) {
+template <typename T, int MODE>
+__global__ __launch_bounds__(256, 3) void lu_gemm_dma_kernel(c2<T>* __restrict__ W, long long mstride, int n, int k0,
+                                                             int nbk, int step, int nbatch, int tiles_r, int tiles_c,
+                                                             const int* __restrict__ perm, long long perm_stride,
+                                                             const c2<T>* __restrict__ Linv, long long inv_stride) {
   typedef __attribute__((address_space(3))) void* lds_ptr;
+  static_assert(MODE == GEMM_UPDATE2 || MODE == GEMM_UPDATE || MODE == GEMM_TRSM_ID, "mode");
   constexpr int NBMAX = 64;
   constexpr int EPS = 16 / (int)sizeof(c2<T>);     // complex entries per 16-byte slot
   constexpr int KC = 8 * EPS;                      // chunk depth: 8 (complex128), 16 (complex64)
-  constexpr bool G3 = sizeof(T) == 8;
+  constexpr bool TOP = MODE == GEMM_TRSM_ID;
+  constexpr bool SUB = !TOP;                       // C - A B (TRSM_ID: A B)
+  constexpr bool G3 = SUB && sizeof(T) == 8;
+  constexpr int NCH = (MODE == GEMM_UPDATE2 ? 2 * NBMAX : NBMAX) / KC;   // full panels only
   const int wg = blockIdx.x, xcd = wg & 7, slot = wg >> 3;
-  const int ntile = tiles * tiles;
+  const int ntile = tiles_r * tiles_c;
   const int b = (slot / ntile) * 8 + xcd;
   if (b >= nbatch) return;
-  const int tile = slot % ntile, tr = tile / tiles, tcn = tile % tiles;
+  const int tile = slot % ntile, tr = tile / tiles_c, tcn = tile % tiles_c;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6, l16 = lane & 15, kq = lane >> 4;
   c2<T>* A = W + (long long)b * mstride;
   const int kend = k0 + nbk, k0p = k0 - NBMAX;
-  const int R0 = kend + tr * 64, C0 = kend + tcn * 64;
-  constexpr int NCH = 2 * NBMAX / KC;             // full pairs only: K = 128
+  const int R0 = (TOP ? k0 : kend) + tr * 64, C0 = kend + tcn * 64;
+  const int rlim = TOP ? kend : n;
   const int rb = R0 + (wave >> 1) * 32, cb = C0 + (wave & 1) * 32;
 
-  // s_from[i] = the row whose step-s multipliers position R0 + i uses (positions past
-  // the matrix: its last row)
+  // UPDATE2: s_from[i] = the row whose step-s multipliers position R0 + i uses
+  // (positions past the matrix: its last row)
   __shared__ int s_from[64];
-  {
+  if (MODE == GEMM_UPDATE2) {
     const int* P = perm + (long long)b * perm_stride + (long long)step * (1 + 4 * NBMAX);
     if (t < 64) s_from[t] = min(R0 + t, n - 1);
     __syncthreads();
@@ -1568,35 +1573,47 @@ __global__ __launch_bounds__(256, 3) void lu_update2_kernel(c2<T>* __restrict__ 
 
   // the C tile's loads first: they complete with chunk 0's
   c2<T> cv[2][2][4];
+  if (SUB) {
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
+    for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj) {
-      const int col = min(cb + bj * 16 + l16, n - 1);
+      for (int bj = 0; bj < 2; ++bj) {
+        const int col = min(cb + bj * 16 + l16, n - 1);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = min(rb + bi * 16 + acc_row<T>(lane, r), n - 1);
-        cv[bi][bj][r] = A[(long long)row * n + col];
+        for (int r = 0; r < 4; ++r) {
+          const int row = min(rb + bi * 16 + acc_row<T>(lane, r), n - 1);
+          cv[bi][bj][r] = A[(long long)row * n + col];
+        }
       }
-    }
+  }
 
   // this wave's two A and two B load instructions per chunk: instruction j = 2 wave + q
   // covers A rows 8 j .. 8 j + 7 (lane: row 8 j + lane / 8, slot lane % 8) and B's
   // 1 KB row block j (complex128: row j, column lane; complex64: row 2 j + lane / 32,
-  // columns 2 (lane % 32) + 0, 1)
-  long long a_lo[2], a_hi[2];
-  int a_sw[2];
-  long long b_off[2];
+  // columns 2 (lane % 32) + 0, 1).  A rows: UPDATE2 the step-s multipliers of row
+  // s_from[i] for k < 64 and the step-s+1 multipliers of row R0 + i after; UPDATE the
+  // step's multipliers of row R0 + i; TRSM_ID row i of the step's inv(L11).  B rows: the
+  // U rows of the pair (UPDATE2) or of the step.
+  const c2<T>* a_lo[2];
+  const c2<T>* a_hi[2];
+  const c2<T>* b_at[2];
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     const int j = 2 * wave + q, i = 8 * j + (lane >> 3);
-    a_lo[q] = (long long)s_from[i] * n + k0p;
-    a_hi[q] = (long long)min(R0 + i, n - 1) * n + k0 - NBMAX;
-    a_sw[q] = ((lane & 7) ^ ((i >> 1) & 7)) * EPS;
+    const int sw = ((lane & 7) ^ ((i >> 1) & 7)) * EPS;
+    if (MODE == GEMM_UPDATE2) {
+      a_lo[q] = A + (long long)s_from[i] * n + k0p + sw;
+      a_hi[q] = A + (long long)min(R0 + i, n - 1) * n + k0 - NBMAX + sw;
+    } else if (MODE == GEMM_UPDATE) {
+      a_lo[q] = a_hi[q] = A + (long long)min(R0 + i, n - 1) * n + k0 + sw;
+    } else {
+      a_lo[q] = a_hi[q] = Linv + (long long)b * inv_stride + (long long)step * NBMAX * NBMAX + i * NBMAX + sw;
+    }
+    const int brow0 = MODE == GEMM_UPDATE2 ? k0p : k0;
     if (EPS == 1)
-      b_off[q] = (long long)(k0p + j) * n + min(C0 + lane, n - 1);
+      b_at[q] = A + (long long)(brow0 + j) * n + min(C0 + lane, n - 1);
     else
-      b_off[q] = (long long)(k0p + 2 * j + (lane >> 5)) * n + min(C0 + 2 * (lane & 31), n - 2);
+      b_at[q] = A + (long long)(brow0 + 2 * j + (lane >> 5)) * n + min(C0 + 2 * (lane & 31), n - 2);
   }
   __shared__ __align__(16) c2<T> As0[64 * KC], As1[64 * KC], As2[64 * KC];
   __shared__ __align__(16) c2<T> Bs0[KC * 64], Bs1[KC * 64], Bs2[KC * 64];
@@ -1605,12 +1622,13 @@ __global__ __launch_bounds__(256, 3) void lu_update2_kernel(c2<T>* __restrict__ 
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int j = 2 * wave + q;
-      const c2<T>* ga = A + (kc < NBMAX ? a_lo[q] : a_hi[q]) + kc + a_sw[q];
+      const c2<T>* ga = (kc < NBMAX ? a_lo[q] : a_hi[q]) + kc;
       __builtin_amdgcn_global_load_lds((const void*)ga, (lds_ptr)(as + j * 64 * EPS), 16, 0, 0);
-      const c2<T>* gb = A + b_off[q] + (long long)kc * n;
+      const c2<T>* gb = b_at[q] + (long long)kc * n;
       __builtin_amdgcn_global_load_lds((const void*)gb, (lds_ptr)(bs + j * 64 * EPS), 16, 0, 0);
     }
   };
+
   // Chunk c: issue chunk c + 2 into the buffer chunk c - 1 used (free since the last
   // barrier), multiply chunk c, wait for this wave's loads of chunk c + 1 (its four
   // loads of chunk c + 2 may stay in flight) and for its LDS traffic (lgkmcnt(0): with
@@ -1623,17 +1641,21 @@ __global__ __launch_bounds__(256, 3) void lu_update2_kernel(c2<T>* __restrict__ 
   __builtin_amdgcn_sched_barrier(0);    // nothing that reads C moves above
   __builtin_amdgcn_s_waitcnt(0x0074);   // vmcnt(4) lgkmcnt(0): chunk 0 and the C loads before it
   barrier_only();
-  // accumulators from C (3M: A1 = Re C, A2 = 0, A3 = Im C + Re C)
+  // accumulators from C (3M: A1 = Re C, A2 = 0, A3 = Im C + Re C) or zero (TRSM_ID)
   acc4<T> c1[2][2], c2a[2][2], c3[2][2];
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) {
+      c1[bi][bj] = acc_zero<T>();
       c2a[bi][bj] = acc_zero<T>();
+      c3[bi][bj] = acc_zero<T>();
+      if (SUB) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        c1[bi][bj][r] = cv[bi][bj][r].x;
-        c3[bi][bj][r] = G3 ? cv[bi][bj][r].y + cv[bi][bj][r].x : cv[bi][bj][r].y;
+        for (int r = 0; r < 4; ++r) {
+          c1[bi][bj][r] = cv[bi][bj][r].x;
+          c3[bi][bj][r] = G3 ? cv[bi][bj][r].y + cv[bi][bj][r].x : cv[bi][bj][r].y;
+        }
       }
     }
 #pragma unroll
@@ -1643,7 +1665,7 @@ __global__ __launch_bounds__(256, 3) void lu_update2_kernel(c2<T>* __restrict__ 
     c2<T>* an = c % 3 == 0 ? As2 : (c % 3 == 1 ? As0 : As1);
     c2<T>* bn = c % 3 == 0 ? Bs2 : (c % 3 == 1 ? Bs0 : Bs1);
     if (c + 2 < NCH) issue(an, bn, c + 2);
-    upd2_compute<T, KC, EPS>(c1, c2a, c3, as, bs, wave, l16, kq);
+    upd2_compute<T, KC, EPS, SUB>(c1, c2a, c3, as, bs, wave, l16, kq);
     if (c + 1 < NCH) {
       if (c + 2 < NCH) __builtin_amdgcn_s_waitcnt(0x0074);   // vmcnt(4) lgkmcnt(0)
       else __builtin_amdgcn_s_waitcnt(0x0070);               // vmcnt(0) lgkmcnt(0)
@@ -1659,7 +1681,7 @@ __global__ __launch_bounds__(256, 3) void lu_update2_kernel(c2<T>* __restrict__ 
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = rb + bi * 16 + acc_row<T>(lane, r);
-        if (row < n && col < n) {
+        if (row < rlim && col < n) {
           const T a1 = c1[bi][bj][r], a3 = c3[bi][bj][r];
           A[(long long)row * n + col] = G3 ? cmk<T>(a1 + c2a[bi][bj][r], a3 - a1 + c2a[bi][bj][r]) : cmk<T>(a1, a3);
         }
@@ -2550,14 +2572,20 @@ hipError_t lu_factor_batch(c2<T>* W, long long mstride, int n, int nbatch, void*
     }
   };
   const long long groups = (nbatch + 7) / 8;
+  // lu_gemm_dma_kernel takes full 64-column panels and, in complex64, even orders
+  auto dma_ok = [&](int nbk) { return nbk == NB && (sizeof(T) == 8 || n % 2 == 0); };
   auto timed_update = [&](int mode, int k0, int nbk, int s, int m, int kdepth) {
     const int tc = (m + 63) / 64;
     // the timers follow the paired update only (the dominant kernel)
     const bool timed = mode == GEMM_UPDATE2 && tm && tm->ev_enabled && tm->npairs < LuTimers::MAXP;
     if (timed) hipEventRecord(tm->ev[2 * tm->npairs], st);
     const dim3 grid((unsigned)(groups * 8 * tc * tc));
-    if (mode == GEMM_UPDATE2 && nbk == NB && (sizeof(T) == 8 || n % 2 == 0))
-      lu_update2_kernel<T><<<grid, 256, 0, st>>>(W, mstride, n, k0, nbk, s, nbatch, tc, perm, perm_stride);
+    if (mode == GEMM_UPDATE2 && dma_ok(nbk))
+      lu_gemm_dma_kernel<T, GEMM_UPDATE2><<<grid, 256, 0, st>>>(W, mstride, n, k0, nbk, s, nbatch, tc, tc, perm,
+                                                                 perm_stride, Linv, inv_stride);
+    else if (mode == GEMM_UPDATE && dma_ok(nbk))
+      lu_gemm_dma_kernel<T, GEMM_UPDATE><<<grid, 256, 0, st>>>(W, mstride, n, k0, nbk, s, nbatch, tc, tc, perm,
+                                                                perm_stride, Linv, inv_stride);
     else if (mode == GEMM_UPDATE2)
       lu_gemm_kernel<T, GEMM_UPDATE2><<<grid, 256, 0, st>>>(W, mstride, n, k0, nbk, s, nbatch, tc, tc, perm,
                                                              perm_stride, Linv, inv_stride);
@@ -2587,15 +2615,23 @@ hipError_t lu_factor_batch(c2<T>* W, long long mstride, int n, int nbatch, void*
     // delayed pair (s, s+1): make panel s+1 current, factor it, then one pass over the
     // trailing matrix for both steps
     const int tr = (m + 63) / 64;
-    lu_gemm_kernel<T, GEMM_UPDATE><<<dim3((unsigned)(groups * 8 * tr)), 256, 0, st>>>(
-        W, mstride, n, k0, nbk, s, nbatch, tr, 1, perm, perm_stride, Linv, inv_stride);
+    if (dma_ok(nbk))
+      lu_gemm_dma_kernel<T, GEMM_UPDATE><<<dim3((unsigned)(groups * 8 * tr)), 256, 0, st>>>(
+          W, mstride, n, k0, nbk, s, nbatch, tr, 1, perm, perm_stride, Linv, inv_stride);
+    else
+      lu_gemm_kernel<T, GEMM_UPDATE><<<dim3((unsigned)(groups * 8 * tr)), 256, 0, st>>>(
+          W, mstride, n, k0, nbk, s, nbatch, tr, 1, perm, perm_stride, Linv, inv_stride);
     panel(s + 1);
     const int k1 = kend, nb1 = min(NB, n - k1), m1 = n - k1 - nb1;   // m1 > 0 here
     const int tc1 = (m1 + 63) / 64;
     lu_gemm_kernel<T, GEMM_PREUPD><<<dim3((unsigned)(groups * 8 * tc1)), 256, 0, st>>>(
         W, mstride, n, k1, nb1, s + 1, nbatch, 1, tc1, perm, perm_stride, Linv, inv_stride);
-    lu_gemm_kernel<T, GEMM_TRSM_ID><<<dim3((unsigned)(groups * 8 * tc1)), 256, 0, st>>>(
-        W, mstride, n, k1, nb1, s + 1, nbatch, 1, tc1, perm, perm_stride, Linv, inv_stride);
+    if (dma_ok(nb1))
+      lu_gemm_dma_kernel<T, GEMM_TRSM_ID><<<dim3((unsigned)(groups * 8 * tc1)), 256, 0, st>>>(
+          W, mstride, n, k1, nb1, s + 1, nbatch, 1, tc1, perm, perm_stride, Linv, inv_stride);
+    else
+      lu_gemm_kernel<T, GEMM_TRSM_ID><<<dim3((unsigned)(groups * 8 * tc1)), 256, 0, st>>>(
+          W, mstride, n, k1, nb1, s + 1, nbatch, 1, tc1, perm, perm_stride, Linv, inv_stride);
     timed_update(GEMM_UPDATE2, k1, nb1, s + 1, m1, NB + nb1);
     s += 2;
   }
