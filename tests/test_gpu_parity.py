@@ -134,10 +134,13 @@ def test_sums_ragged_sizes(N, n, Nn, s, L, prec, pivot):
         N.nep_destroy(plan)
 
 
-@pytest.mark.parametrize("n,prec", [(2048, 0), (2048, 1), (3000, 1), (4096, 0)])
+@pytest.mark.parametrize("n,prec", [(1600, 0), (2048, 0), (2048, 1), (3000, 1), (4096, 0)])
 def test_largest_orders_sampled(N, n, prec):
     # up to the library's largest order: panels of more than 1024 (complex128) or 2048
-    # (complex64) rows take the streaming panel; one disk of four nodes
+    # (complex64) rows take the streaming panel; one disk of four nodes.  Orders from
+    # 1600 on also keep many workgroups of the LDS-loaded updates in flight at once
+    # (where waiting for the vector-memory count alone before a barrier gave wrong
+    # sums now and then)
     say(f"case largest orders n={n} precision={prec}")
     A = gen.gaussian(100 + n, n)
     B = gen.gaussian(200 + n, n)
