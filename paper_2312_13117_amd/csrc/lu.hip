@@ -1517,19 +1517,20 @@ __device__ __forceinline__ void upd2_compute(acc4<T> (&c1)[2][2], acc4<T> (&c2a)
   }
 }
 
-// The paired trailing update (GEMM_UPDATE2's product, same tiles, operands and
-// arithmetic) with its operand chunks loaded by the memory units straight into LDS
-// (global_load_lds_dwordx4: a lane's 16 bytes land at the instruction's LDS base + 16
-// lane) three chunks deep, so that a chunk's loads are issued two chunks of products
-// before they are read; the register-staged form waits for each chunk one chunk after
-// issuing it.  A chunk is 64 rows x KC entries of A (8 slots of 16 bytes per row) and
+// lu_gemm_kernel's UPDATE2 (the paired trailing update), UPDATE and TRSM_ID steps for
+// full 64-column panels (same tiles, operands and arithmetic), with the operand chunks
+// loaded by the memory units straight into LDS (global_load_lds_dwordx4: a lane's 16
+// bytes land at the instruction's LDS base + 16 lane) three chunks deep, so that a
+// chunk's loads are issued two chunks of products before they are read; the
+// register-staged kernel waits for each chunk one chunk after issuing it.  A chunk is 64 rows x KC entries of A (8 slots of 16 bytes per row) and
 // KC rows x 64 columns of B, 8 KB each.  The A slots of row i are stored XOR-swizzled
 // (slot s holds entries (s ^ ((i >> 1) & 7)) EPS ..) so that the 16 rows a quarter-wave
 // reads for one k fall on 16 different bank groups; B rows are read along columns and
 // need none.  Rows and columns past the matrix are read at clamped addresses (they only
-// feed outputs that are not stored).  The launcher sends full pairs only (K = 128: 16
-// chunks in complex128, 8 in complex64; a last pair narrower than 128 columns takes
-// lu_gemm_kernel) and, in complex64, even orders (16-byte aligned rows).
+// feed outputs that are not stored).  The launcher sends full panels only (K = 128 for
+// UPDATE2: 16 chunks in complex128, 8 in complex64; K = 64 for the others; a narrower
+// last panel takes lu_gemm_kernel) and, in complex64, even orders (16-byte aligned
+// rows).
 template <typename T, int MODE>
 __global__ __launch_bounds__(256, 3) void lu_gemm_dma_kernel(c2<T>* __restrict__ W, long long mstride, int n, int k0,
                                                              int nbk, int step, int nbatch, int tiles_r, int tiles_c,
