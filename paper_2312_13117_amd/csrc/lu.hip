@@ -1517,8 +1517,10 @@ __device__ __forceinline__ void upd2_compute(acc4<T> (&c1)[2][2], acc4<T> (&c2a)
   }
 }
 
-// lu_gemm_kernel's UPDATE2 (the paired trailing update), UPDATE and TRSM_ID steps for
-// full 64-column panels (same tiles, operands and arithmetic), with the operand chunks
+// lu_gemm_kernel's UPDATE2 (the paired trailing update), UPDATE, PREUPD and TRSM_ID
+// steps for full 64-column panels (same tiles and operands; PREUPD in complex128 also
+// takes 3M products, and runs at two workgroups per CU for the exchange's displaced rows
+// it holds in registers), with the operand chunks
 // loaded by the memory units straight into LDS (global_load_lds_dwordx4: a lane's 16
 // bytes land at the instruction's LDS base + 16 lane) three chunks deep, so that a
 // chunk's loads are issued two chunks of products before they are read; the
@@ -1532,17 +1534,17 @@ __device__ __forceinline__ void upd2_compute(acc4<T> (&c1)[2][2], acc4<T> (&c2a)
 // last panel takes lu_gemm_kernel) and, in complex64, even orders (16-byte aligned
 // rows).
 template <typename T, int MODE>
-__global__ __launch_bounds__(256, 3) void lu_gemm_dma_kernel(c2<T>* __restrict__ W, long long mstride, int n, int k0,
+__global__ __launch_bounds__(256, (MODE == GEMM_PREUPD ? 2 : 3)) void lu_gemm_dma_kernel(c2<T>* __restrict__ W, long long mstride, int n, int k0,
                                                              int nbk, int step, int nbatch, int tiles_r, int tiles_c,
                                                              const int* __restrict__ perm, long long perm_stride,
                                                              const c2<T>* __restrict__ Linv, long long inv_stride) {
   typedef __attribute__((address_space(3))) void* lds_ptr;
-  static_assert(MODE == GEMM_UPDATE2 || MODE == GEMM_UPDATE || MODE == GEMM_TRSM_ID, "mode");
+  static_assert(MODE == GEMM_UPDATE2 || MODE == GEMM_UPDATE || MODE == GEMM_TRSM_ID || MODE == GEMM_PREUPD, "mode");
   constexpr int NBMAX = 64;
   constexpr int EPS = 16 / (int)sizeof(c2<T>);     // complex entries per 16-byte slot
   constexpr int KC = 8 * EPS;                      // chunk depth: 8 (complex128), 16 (complex64)
-  constexpr bool TOP = MODE == GEMM_TRSM_ID;
-  constexpr bool SUB = !TOP;                       // C - A B (TRSM_ID: A B)
+  constexpr bool TOP = MODE == GEMM_TRSM_ID || MODE == GEMM_PREUPD;
+  constexpr bool SUB = MODE != GEMM_TRSM_ID;       // C - A B (TRSM_ID: A B)
   constexpr bool G3 = SUB && sizeof(T) == 8;
   constexpr int NCH = (MODE == GEMM_UPDATE2 ? 2 * NBMAX : NBMAX) / KC;   // full panels only
   const int wg = blockIdx.x, xcd = wg & 7, slot = wg >> 3;
@@ -1571,6 +1573,15 @@ __global__ __launch_bounds__(256, 3) void lu_gemm_dma_kernel(c2<T>* __restrict__
     }
     __syncthreads();
   }
+  // PREUPD: the step's exchange record (position, source of every moved row)
+  __shared__ int s_src[MODE == GEMM_PREUPD ? 2 * NBMAX : 1], s_pos[MODE == GEMM_PREUPD ? 2 * NBMAX : 1];
+  __shared__ int s_cnt;
+  if (MODE == GEMM_PREUPD) {
+    const int* P = perm + (long long)b * perm_stride + (long long)step * (1 + 4 * NBMAX);
+    if (t == 0) s_cnt = P[0];
+    for (int i = t; i < 2 * NBMAX; i += 256) { s_pos[i] = P[1 + i]; s_src[i] = P[1 + 2 * NBMAX + i]; }
+    __syncthreads();
+  }
 
   // the C tile's loads first: they complete with chunk 0's
   c2<T> cv[2][2][4];
@@ -1583,7 +1594,8 @@ __global__ __launch_bounds__(256, 3) void lu_gemm_dma_kernel(c2<T>* __restrict__
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = min(rb + bi * 16 + acc_row<T>(lane, r), n - 1);
-          cv[bi][bj][r] = A[(long long)row * n + col];
+          const int srow = MODE == GEMM_PREUPD ? s_src[row - k0] : row;   // PREUPD: rows k0 .. kend-1
+          cv[bi][bj][r] = A[(long long)srow * n + col];
         }
       }
   }
@@ -1593,8 +1605,24 @@ __global__ __launch_bounds__(256, 3) void lu_gemm_dma_kernel(c2<T>* __restrict__
   // 1 KB row block j (complex128: row j, column lane; complex64: row 2 j + lane / 32,
   // columns 2 (lane % 32) + 0, 1).  A rows: UPDATE2 the step-s multipliers of row
   // s_from[i] for k < 64 and the step-s+1 multipliers of row R0 + i after; UPDATE the
-  // step's multipliers of row R0 + i; TRSM_ID row i of the step's inv(L11).  B rows: the
-  // U rows of the pair (UPDATE2) or of the step.
+  // step's multipliers of row R0 + i; PREUPD the previous step's multipliers of row
+  // s_src[i] (the row the exchange brings to k0 + i); TRSM_ID row i of the step's
+  // inv(L11).  B rows: the U rows of the pair (UPDATE2), of the previous step (PREUPD) or
+  // of the step.
+  // PREUPD: the rows the exchange displaces from the top block, read before any write
+  // (they move unchanged to the positions their replacements left)
+  constexpr int DMAX = MODE == GEMM_PREUPD ? (NBMAX * 64) / 256 : 1;
+  c2<T> dval[DMAX];
+  int ndisp = 0;
+  if (MODE == GEMM_PREUPD) {
+    ndisp = s_cnt - nbk;
+#pragma unroll
+    for (int q = 0; q < DMAX; ++q) {
+      const int e = t + q * 256;
+      const int i = nbk + e / 64, col = C0 + (e & 63);
+      dval[q] = (e < ndisp * 64 && col < n) ? A[(long long)s_src[i] * n + col] : czero<T>();
+    }
+  }
   const c2<T>* a_lo[2];
   const c2<T>* a_hi[2];
   const c2<T>* b_at[2];
@@ -1607,10 +1635,12 @@ __global__ __launch_bounds__(256, 3) void lu_gemm_dma_kernel(c2<T>* __restrict__
       a_hi[q] = A + (long long)min(R0 + i, n - 1) * n + k0 - NBMAX + sw;
     } else if (MODE == GEMM_UPDATE) {
       a_lo[q] = a_hi[q] = A + (long long)min(R0 + i, n - 1) * n + k0 + sw;
+    } else if (MODE == GEMM_PREUPD) {
+      a_lo[q] = a_hi[q] = A + (long long)s_src[i] * n + k0p + sw;
     } else {
       a_lo[q] = a_hi[q] = Linv + (long long)b * inv_stride + (long long)step * NBMAX * NBMAX + i * NBMAX + sw;
     }
-    const int brow0 = MODE == GEMM_UPDATE2 ? k0p : k0;
+    const int brow0 = (MODE == GEMM_UPDATE2 || MODE == GEMM_PREUPD) ? k0p : k0;
     if (EPS == 1)
       b_at[q] = A + (long long)(brow0 + j) * n + min(C0 + lane, n - 1);
     else
@@ -1688,6 +1718,16 @@ __global__ __launch_bounds__(256, 3) void lu_gemm_dma_kernel(c2<T>* __restrict__
         }
       }
     }
+  // PREUPD: every read of the exchange's rows (the C tile, the displaced rows) completed
+  // before the first barrier, so the moved rows are written now
+  if (MODE == GEMM_PREUPD) {
+#pragma unroll
+    for (int q = 0; q < DMAX; ++q) {
+      const int e = t + q * 256;
+      const int i = nbk + e / 64, col = C0 + (e & 63);
+      if (e < ndisp * 64 && col < n) A[(long long)s_pos[i] * n + col] = dval[q];
+    }
+  }
 }
 
 // ----------------------------------------------------------------------------- solves
@@ -2625,8 +2665,12 @@ hipError_t lu_factor_batch(c2<T>* W, long long mstride, int n, int nbatch, void*
     panel(s + 1);
     const int k1 = kend, nb1 = min(NB, n - k1), m1 = n - k1 - nb1;   // m1 > 0 here
     const int tc1 = (m1 + 63) / 64;
-    lu_gemm_kernel<T, GEMM_PREUPD><<<dim3((unsigned)(groups * 8 * tc1)), 256, 0, st>>>(
-        W, mstride, n, k1, nb1, s + 1, nbatch, 1, tc1, perm, perm_stride, Linv, inv_stride);
+    if (dma_ok(nb1))
+      lu_gemm_dma_kernel<T, GEMM_PREUPD><<<dim3((unsigned)(groups * 8 * tc1)), 256, 0, st>>>(
+          W, mstride, n, k1, nb1, s + 1, nbatch, 1, tc1, perm, perm_stride, Linv, inv_stride);
+    else
+      lu_gemm_kernel<T, GEMM_PREUPD><<<dim3((unsigned)(groups * 8 * tc1)), 256, 0, st>>>(
+          W, mstride, n, k1, nb1, s + 1, nbatch, 1, tc1, perm, perm_stride, Linv, inv_stride);
     if (dma_ok(nb1))
       lu_gemm_dma_kernel<T, GEMM_TRSM_ID><<<dim3((unsigned)(groups * 8 * tc1)), 256, 0, st>>>(
           W, mstride, n, k1, nb1, s + 1, nbatch, 1, tc1, perm, perm_stride, Linv, inv_stride);
