@@ -1517,10 +1517,12 @@ __device__ __forceinline__ void upd2_compute(acc4<T> (&c1)[2][2], acc4<T> (&c2a)
   }
 }
 
-// lu_gemm_kernel's UPDATE2 (the paired trailing update), UPDATE, PREUPD and TRSM_ID
-// steps for full 64-column panels (same tiles and operands; PREUPD in complex128 also
-// takes 3M products, and runs at two workgroups per CU for the exchange's displaced rows
-// it holds in registers), with the operand chunks
+// lu_gemm_kernel's UPDATE2 (the paired trailing update), UPDATE, PREUPD, TRSM and
+// TRSM_ID steps for full 64-column panels (same tiles and operands; PREUPD in complex128
+// also takes 3M products; PREUPD and TRSM run at two workgroups per CU for the
+// exchange's displaced rows they hold in registers, and TRSM reads its B rows through
+// the exchange, each lane's rows of every chunk taken from the record once), with the
+// operand chunks
 // loaded by the memory units straight into LDS (global_load_lds_dwordx4: a lane's 16
 // bytes land at the instruction's LDS base + 16 lane) three chunks deep, so that a
 // chunk's loads are issued two chunks of products before they are read; the
@@ -1534,17 +1536,19 @@ __device__ __forceinline__ void upd2_compute(acc4<T> (&c1)[2][2], acc4<T> (&c2a)
 // last panel takes lu_gemm_kernel) and, in complex64, even orders (16-byte aligned
 // rows).
 template <typename T, int MODE>
-__global__ __launch_bounds__(256, (MODE == GEMM_PREUPD ? 2 : 3)) void lu_gemm_dma_kernel(c2<T>* __restrict__ W, long long mstride, int n, int k0,
+__global__ __launch_bounds__(256, ((MODE == GEMM_PREUPD || MODE == GEMM_TRSM) ? 2 : 3)) void lu_gemm_dma_kernel(c2<T>* __restrict__ W, long long mstride, int n, int k0,
                                                              int nbk, int step, int nbatch, int tiles_r, int tiles_c,
                                                              const int* __restrict__ perm, long long perm_stride,
                                                              const c2<T>* __restrict__ Linv, long long inv_stride) {
   typedef __attribute__((address_space(3))) void* lds_ptr;
-  static_assert(MODE == GEMM_UPDATE2 || MODE == GEMM_UPDATE || MODE == GEMM_TRSM_ID || MODE == GEMM_PREUPD, "mode");
+  static_assert(MODE == GEMM_UPDATE2 || MODE == GEMM_UPDATE || MODE == GEMM_TRSM_ID || MODE == GEMM_PREUPD ||
+                    MODE == GEMM_TRSM, "mode");
   constexpr int NBMAX = 64;
   constexpr int EPS = 16 / (int)sizeof(c2<T>);     // complex entries per 16-byte slot
   constexpr int KC = 8 * EPS;                      // chunk depth: 8 (complex128), 16 (complex64)
-  constexpr bool TOP = MODE == GEMM_TRSM_ID || MODE == GEMM_PREUPD;
-  constexpr bool SUB = MODE != GEMM_TRSM_ID;       // C - A B (TRSM_ID: A B)
+  constexpr bool TOP = MODE == GEMM_TRSM_ID || MODE == GEMM_PREUPD || MODE == GEMM_TRSM;
+  constexpr bool SUB = MODE != GEMM_TRSM_ID && MODE != GEMM_TRSM;   // C - A B (TRSM, TRSM_ID: A B)
+  constexpr bool EXCH = MODE == GEMM_PREUPD || MODE == GEMM_TRSM;    // applies the step's row exchange
   constexpr bool G3 = SUB && sizeof(T) == 8;
   constexpr int NCH = (MODE == GEMM_UPDATE2 ? 2 * NBMAX : NBMAX) / KC;   // full panels only
   const int wg = blockIdx.x, xcd = wg & 7, slot = wg >> 3;
@@ -1573,10 +1577,10 @@ __global__ __launch_bounds__(256, (MODE == GEMM_PREUPD ? 2 : 3)) void lu_gemm_dm
     }
     __syncthreads();
   }
-  // PREUPD: the step's exchange record (position, source of every moved row)
-  __shared__ int s_src[MODE == GEMM_PREUPD ? 2 * NBMAX : 1], s_pos[MODE == GEMM_PREUPD ? 2 * NBMAX : 1];
+  // PREUPD, TRSM: the step's exchange record (position, source of every moved row)
+  __shared__ int s_src[EXCH ? 2 * NBMAX : 1], s_pos[EXCH ? 2 * NBMAX : 1];
   __shared__ int s_cnt;
-  if (MODE == GEMM_PREUPD) {
+  if (EXCH) {
     const int* P = perm + (long long)b * perm_stride + (long long)step * (1 + 4 * NBMAX);
     if (t == 0) s_cnt = P[0];
     for (int i = t; i < 2 * NBMAX; i += 256) { s_pos[i] = P[1 + i]; s_src[i] = P[1 + 2 * NBMAX + i]; }
@@ -1606,15 +1610,15 @@ __global__ __launch_bounds__(256, (MODE == GEMM_PREUPD ? 2 : 3)) void lu_gemm_dm
   // columns 2 (lane % 32) + 0, 1).  A rows: UPDATE2 the step-s multipliers of row
   // s_from[i] for k < 64 and the step-s+1 multipliers of row R0 + i after; UPDATE the
   // step's multipliers of row R0 + i; PREUPD the previous step's multipliers of row
-  // s_src[i] (the row the exchange brings to k0 + i); TRSM_ID row i of the step's
-  // inv(L11).  B rows: the U rows of the pair (UPDATE2), of the previous step (PREUPD) or
-  // of the step.
-  // PREUPD: the rows the exchange displaces from the top block, read before any write
-  // (they move unchanged to the positions their replacements left)
-  constexpr int DMAX = MODE == GEMM_PREUPD ? (NBMAX * 64) / 256 : 1;
+  // s_src[i] (the row the exchange brings to k0 + i); TRSM and TRSM_ID row i of the
+  // step's inv(L11).  B rows: the U rows of the pair (UPDATE2), of the previous step
+  // (PREUPD) or of the step (UPDATE, TRSM_ID); TRSM row s_src[k] for k.
+  // PREUPD, TRSM: the rows the exchange displaces from the top block, read before any
+  // write (they move unchanged to the positions their replacements left)
+  constexpr int DMAX = EXCH ? (NBMAX * 64) / 256 : 1;
   c2<T> dval[DMAX];
   int ndisp = 0;
-  if (MODE == GEMM_PREUPD) {
+  if (EXCH) {
     ndisp = s_cnt - nbk;
 #pragma unroll
     for (int q = 0; q < DMAX; ++q) {
@@ -1641,10 +1645,24 @@ __global__ __launch_bounds__(256, (MODE == GEMM_PREUPD ? 2 : 3)) void lu_gemm_dm
       a_lo[q] = a_hi[q] = Linv + (long long)b * inv_stride + (long long)step * NBMAX * NBMAX + i * NBMAX + sw;
     }
     const int brow0 = (MODE == GEMM_UPDATE2 || MODE == GEMM_PREUPD) ? k0p : k0;
-    if (EPS == 1)
+    if (MODE == GEMM_TRSM)   // the column part only: the row comes from the exchange record
+      b_at[q] = A + (EPS == 1 ? min(C0 + lane, n - 1) : min(C0 + 2 * (lane & 31), n - 2));
+    else if (EPS == 1)
       b_at[q] = A + (long long)(brow0 + j) * n + min(C0 + lane, n - 1);
     else
       b_at[q] = A + (long long)(brow0 + 2 * j + (lane >> 5)) * n + min(C0 + 2 * (lane & 31), n - 2);
+  }
+  // TRSM: B row k of the step is the row its exchange brings to k0 + k, s_src[k]; this
+  // lane's rows of every chunk, read once (the pipeline's addresses then wait on no LDS)
+  int bsrc[MODE == GEMM_TRSM ? NCH : 1][2];
+  if (MODE == GEMM_TRSM) {
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int j = 2 * wave + q;
+        bsrc[c][q] = s_src[c * KC + (EPS == 1 ? j : 2 * j + (lane >> 5))];
+      }
   }
   __shared__ __align__(16) c2<T> As0[64 * KC], As1[64 * KC], As2[64 * KC];
   __shared__ __align__(16) c2<T> Bs0[KC * 64], Bs1[KC * 64], Bs2[KC * 64];
@@ -1655,7 +1673,9 @@ __global__ __launch_bounds__(256, (MODE == GEMM_PREUPD ? 2 : 3)) void lu_gemm_dm
       const int j = 2 * wave + q;
       const c2<T>* ga = (kc < NBMAX ? a_lo[q] : a_hi[q]) + kc;
       __builtin_amdgcn_global_load_lds((const void*)ga, (lds_ptr)(as + j * 64 * EPS), 16, 0, 0);
-      const c2<T>* gb = b_at[q] + (long long)kc * n;
+      const c2<T>* gb;
+      if constexpr (MODE == GEMM_TRSM) gb = b_at[q] + (long long)bsrc[c][q] * n;
+      else gb = b_at[q] + (long long)kc * n;
       __builtin_amdgcn_global_load_lds((const void*)gb, (lds_ptr)(bs + j * 64 * EPS), 16, 0, 0);
     }
   };
@@ -1718,9 +1738,9 @@ __global__ __launch_bounds__(256, (MODE == GEMM_PREUPD ? 2 : 3)) void lu_gemm_dm
         }
       }
     }
-  // PREUPD: every read of the exchange's rows (the C tile, the displaced rows) completed
-  // before the first barrier, so the moved rows are written now
-  if (MODE == GEMM_PREUPD) {
+  // PREUPD, TRSM: every read of the exchange's rows (the C tile, the B rows, the
+  // displaced rows) completed before the last barrier, so the moved rows are written now
+  if (EXCH) {
 #pragma unroll
     for (int q = 0; q < DMAX; ++q) {
       const int e = t + q * 256;
@@ -2645,8 +2665,12 @@ hipError_t lu_factor_batch(c2<T>* W, long long mstride, int n, int nbatch, void*
     panel(s);
     if (m <= 0) break;
     const int tc = (m + 63) / 64;
-    lu_gemm_kernel<T, GEMM_TRSM><<<dim3((unsigned)(groups * 8 * tc)), 256, 0, st>>>(
-        W, mstride, n, k0, nbk, s, nbatch, 1, tc, perm, perm_stride, Linv, inv_stride);
+    if (dma_ok(nbk))
+      lu_gemm_dma_kernel<T, GEMM_TRSM><<<dim3((unsigned)(groups * 8 * tc)), 256, 0, st>>>(
+          W, mstride, n, k0, nbk, s, nbatch, 1, tc, perm, perm_stride, Linv, inv_stride);
+    else
+      lu_gemm_kernel<T, GEMM_TRSM><<<dim3((unsigned)(groups * 8 * tc)), 256, 0, st>>>(
+          W, mstride, n, k0, nbk, s, nbatch, 1, tc, perm, perm_stride, Linv, inv_stride);
     if (s + 1 == nsteps - 1 || m <= NB) {
       // the next panel is the last one: one plain update
       timed_update(GEMM_UPDATE, k0, nbk, s, m, nbk);
