@@ -2518,28 +2518,6 @@ __global__ __launch_bounds__(256, (solve_rowsm_min_blocks<T, JB>())) void solve_
 }
 
 // ----------------------------------------------------------------------------- launchers
-template <typename T>
-static void launch_trailing(c2<T>* W, long long mstride, int n, int nbatch, int k0, int nbk, int s, int* perm,
-                            long long perm_stride, c2<T>* Linv, long long inv_stride, hipStream_t st,
-                            LuTimers* tm) {
-  const int m = n - k0 - nbk;
-  if (m <= 0) return;
-  const int tc = (m + 63) / 64;
-  const long long groups = (nbatch + 7) / 8;
-  lu_gemm_kernel<T, GEMM_TRSM><<<dim3((unsigned)(groups * 8 * tc)), 256, 0, st>>>(
-      W, mstride, n, k0, nbk, s, nbatch, 1, tc, perm, perm_stride, Linv, inv_stride);
-  const bool timed = tm && tm->ev_enabled && tm->npairs < LuTimers::MAXP;
-  if (timed) hipEventRecord(tm->ev[2 * tm->npairs], st);
-  lu_gemm_kernel<T, GEMM_UPDATE><<<dim3((unsigned)(groups * 8 * tc * tc)), 256, 0, st>>>(
-      W, mstride, n, k0, nbk, s, nbatch, tc, tc, perm, perm_stride, Linv, inv_stride);
-  if (timed) {
-    hipEventRecord(tm->ev[2 * tm->npairs + 1], st);
-    tm->npairs++;
-    tm->gemm_launches += 1;   // launches and flops of the timed launches only
-    tm->gemm_flops += 8.0 * (double)m * (double)m * (double)nbk * (double)nbatch;
-  }
-}
-
 size_t lu_factor_scratch_bytes(int n, size_t elem_bytes) {
   const size_t partial = sizeof(int) * ((size_t)n + RP_EXMAX);
   const size_t tournament = 2 * sizeof(int) * 64 * 64 + elem_bytes * (size_t)LU_NB * LU_NB;
